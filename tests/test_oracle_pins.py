@@ -1,0 +1,244 @@
+"""Pins of the CPU oracle against things other than itself: dense brute force
+(n <= 8), closed forms (product, basis, cluster, GHZ states), the
+parameter-shift rule of Eq. 13, finite differences, the Walsh-Hadamard
+identity for the diagonal, and invariants (norm, reversibility, Eq. 12 term
+split, periodicity, restricted = masked gradient)."""
+import numpy as np
+import pytest
+from scipy.linalg import hadamard
+
+import oracle
+from oracle import closed_forms as cf
+from oracle import dense
+from paper_2607_02749_amd import synth
+
+ENTS = [synth.ENT_NONE, synth.ENT_CZ_LINEAR, synth.ENT_CZ_CIRCULAR,
+        synth.ENT_CNOT_LINEAR, synth.ENT_CNOT_CIRCULAR]
+
+
+def rand_terms(rng, n, m, offdiag=True):
+    x = rng.integers(0, 1 << n, size=m, dtype=np.uint64) if offdiag else np.zeros(m, np.uint64)
+    z = rng.integers(0, 1 << n, size=m, dtype=np.uint64)
+    c = rng.normal(size=m)
+    return x, z, c
+
+
+def test_gate_matrices_eq7():
+    # RY(pi)|0> = |1>, RZ phases -t/2 on |0>, +t/2 on |1>
+    assert np.allclose(dense.ry(np.pi) @ [1, 0], [0, 1])
+    t = 0.7
+    assert np.allclose(np.diag(dense.rz(t)), [np.exp(-0.35j), np.exp(0.35j)])
+    # RY(t) = exp(-i t Y / 2), RZ(t) = exp(-i t Z / 2)
+    from scipy.linalg import expm
+    assert np.allclose(dense.ry(t), expm(-0.5j * t * dense.Y))
+    assert np.allclose(dense.rz(t), expm(-0.5j * t * dense.Z))
+
+
+def test_pauli_encoding_y_phase():
+    # P(x, z) = i^{|x&z|} X^x Z^z: Y = i X Z on one qubit, and on two qubits
+    # the label route agrees with the defining product.
+    assert np.allclose(dense.pauli(dense.label(1, 1, 1)), 1j * dense.X @ dense.Z)
+    n = 3
+    for x in range(8):
+        for z in range(8):
+            xm = dense.embed(n, {q: dense.X for q in range(n) if (x >> q) & 1})
+            zm = dense.embed(n, {q: dense.Z for q in range(n) if (z >> q) & 1})
+            want = (1j ** bin(x & z).count("1")) * xm @ zm
+            assert np.allclose(dense.pauli(dense.label(n, x, z)), want)
+
+
+@pytest.mark.parametrize("ent", ENTS)
+@pytest.mark.parametrize("final_rotation", [0, 1])
+def test_state_vs_dense(ent, final_rotation):
+    rng = np.random.default_rng(ent * 7 + final_rotation)
+    for n in (1, 2, 3, 5):
+        layers = 2
+        th = rng.uniform(-np.pi, np.pi, oracle.num_params(n, layers, final_rotation))
+        a = oracle.prepare(n, layers, ent, th, final_rotation)
+        b = dense.state(n, layers, ent, th, final_rotation)
+        assert np.abs(a - b).max() < 1e-13
+        assert abs(np.vdot(a, a).real - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("ent", ENTS)
+def test_energy_grad_vs_dense(ent):
+    rng = np.random.default_rng(100 + ent)
+    n, layers = 5, 2
+    x, z, c = rand_terms(rng, n, 12)
+    th = rng.uniform(-np.pi, np.pi, oracle.num_params(n, layers))
+    h = dense.hamiltonian(n, x, z, c)
+    e_dense = dense.energy(n, layers, ent, th, h)
+    g_dense = dense.param_shift_grad(n, layers, ent, th, h)
+    e, g = oracle.energy_grad(n, layers, ent, th, x, z, c)
+    assert abs(e.real - e_dense.real) < 1e-12
+    assert abs(e.imag) < 1e-12 and abs(e_dense.imag) < 1e-12
+    assert np.abs(g - g_dense).max() < 1e-11
+    # same with the Z-only part through the direct-sum diagonal
+    d = oracle.diag(n, x, z, c)
+    e2, g2 = oracle.energy_grad(n, layers, ent, th, x, z, c, d=d)
+    assert abs(e2.real - e_dense.real) < 1e-12
+    assert np.abs(g2 - g_dense).max() < 1e-11
+
+
+def test_hamiltonian_apply_vs_dense():
+    rng = np.random.default_rng(5)
+    n = 6
+    x, z, c = rand_terms(rng, n, 30)
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    h = dense.hamiltonian(n, x, z, c)
+    assert np.abs(oracle.apply_h(n, x, z, c, psi) - h @ psi).max() < 1e-12
+    d = oracle.diag(n, x, z, c)
+    assert np.abs(oracle.apply_h(n, x, z, c, psi, d) - h @ psi).max() < 1e-12
+
+
+def test_final_rotation_eq8_param_count():
+    # Eq. 8: P = 2 N (D + 1) for D repetitions plus the initial rotation layer
+    assert oracle.num_params(8, 4, 1) == 2 * 8 * 5
+    assert oracle.num_params(10, 2, 0) == 40
+
+
+@pytest.mark.parametrize("ent", [synth.ENT_CZ_LINEAR, synth.ENT_CNOT_LINEAR])
+def test_adjoint_vs_param_shift_and_fd(ent):
+    inst = synth.make_instance(9, 3, 60, 4, 3, seed=3, m_off=10,
+                               off_types=("XX", "YY", "XZ", "ZY"), ent=ent)
+    args = (inst.n, inst.layers, ent, inst.theta, inst.x, inst.z, inst.c)
+    _, g = oracle.energy_grad(*args)
+    ps = oracle.param_shift_grad(*args)
+    assert np.abs(g - ps).max() < 1e-11
+    h = 1e-5
+    for j in (0, 5, 17, 40):
+        tp, tm = inst.theta.copy(), inst.theta.copy()
+        tp[j] += h
+        tm[j] -= h
+        fd = (oracle.energy(inst.n, inst.layers, ent, tp, inst.x, inst.z, inst.c).real
+              - oracle.energy(inst.n, inst.layers, ent, tm, inst.x, inst.z, inst.c).real) / (2 * h)
+        assert abs(fd - g[j]) < 1e-6 * max(1.0, abs(g[j]))
+
+
+@pytest.mark.parametrize("final_rotation", [0, 1])
+def test_product_state_closed_form(final_rotation):
+    inst = synth.make_instance(12, 3, 150, 4, 3, seed=11, m_off=40,
+                               off_types=("XX", "YY", "XZ", "ZY"), ent=synth.ENT_NONE,
+                               final_rotation=final_rotation)
+    e_cf, g_cf = cf.product_energy_grad(inst.n, inst.layers + final_rotation, inst.theta,
+                                        inst.x, inst.z, inst.c)
+    e, g = oracle.energy_grad(inst.n, inst.layers, synth.ENT_NONE, inst.theta, inst.x,
+                              inst.z, inst.c, final_rotation=final_rotation)
+    assert abs(e.real - e_cf) < 1e-11 * max(1, abs(e_cf))
+    assert np.abs(g - g_cf).max() < 1e-11
+
+
+def test_basis_states_give_diagonal_entries():
+    inst = synth.workload_small()
+    d = oracle.diag(inst.n, inst.x, inst.z, inst.c)
+    rng = np.random.default_rng(2)
+    for b in list(rng.integers(0, 1 << inst.n, size=6)) + [0, (1 << inst.n) - 1]:
+        b = int(b)
+        th = cf.basis_theta(inst.n, inst.layers, b)
+        e = oracle.energy(inst.n, inst.layers, inst.ent, th, inst.x, inst.z, inst.c).real
+        want = cf.diag_entry(b, inst.x, inst.z, inst.c)
+        assert abs(e - want) < 1e-11
+        assert abs(d[b] - want) < 1e-11
+    # theta = 0: E = sum of the Z-only coefficients
+    e0 = oracle.energy(inst.n, inst.layers, inst.ent, np.zeros(inst.num_params),
+                       inst.x, inst.z, inst.c).real
+    assert abs(e0 - inst.c[inst.x == 0].sum()) < 1e-11
+
+
+def test_diagonal_is_walsh_hadamard_of_coefficients():
+    # D = W h with h[z] = sum of c_k over Z-strings z_k = z and W the
+    # unnormalised (Sylvester) Walsh-Hadamard matrix: W_{iz} = (-1)^{popcount(i&z)}
+    rng = np.random.default_rng(9)
+    n = 7
+    x = np.zeros(40, np.uint64)
+    z = rng.integers(0, 1 << n, size=40, dtype=np.uint64)
+    c = rng.normal(size=40)
+    h = np.zeros(1 << n)
+    np.add.at(h, z.astype(np.int64), c)
+    w = hadamard(1 << n)
+    assert np.abs(oracle.diag(n, x, z, c) - w @ h).max() < 1e-12
+    assert np.allclose(w @ w, (1 << n) * np.eye(1 << n))
+    # single term: D_i = c (-1)^{popcount(i & z)}
+    d1 = oracle.diag(n, x[:1], z[:1], c[:1])
+    for i in range(1 << n):
+        assert d1[i] == pytest.approx(c[0] * (-1) ** bin(i & int(z[0])).count("1"))
+    # entries one by one
+    idx = rng.integers(0, 1 << n, size=10)
+    assert np.allclose(oracle.diag_at(x, z, c, idx), oracle.diag(n, x, z, c)[idx])
+
+
+def test_cluster_state_stabilizers():
+    n = 8
+    th = cf.cluster_theta(n)
+    for x, z in cf.cluster_stabilizers(n):
+        e = oracle.energy(n, 1, synth.ENT_CZ_LINEAR, th, [x], [z], [1.0])
+        assert abs(e - 1.0) < 1e-12
+    rng = np.random.default_rng(4)
+    for zmask in rng.integers(1, 1 << n, size=10):
+        e = oracle.energy(n, 1, synth.ENT_CZ_LINEAR, th, [0], [int(zmask)], [1.0])
+        assert abs(e) < 1e-12
+
+
+def test_ghz_state():
+    n = 9
+    th = cf.ghz_theta(n)
+    psi = oracle.prepare(n, 1, synth.ENT_CNOT_LINEAR, th)
+    want = np.zeros(1 << n, complex)
+    want[0] = want[-1] = 1 / np.sqrt(2)
+    assert np.abs(psi - want).max() < 1e-14
+    e = oracle.energy(n, 1, synth.ENT_CNOT_LINEAR, th, [0], [(1 << 3) | (1 << 7)], [1.0])
+    assert abs(e - 1) < 1e-12
+    e = oracle.energy(n, 1, synth.ENT_CNOT_LINEAR, th, [0], [0b10101], [1.0])
+    assert abs(e) < 1e-12
+    e = oracle.energy(n, 1, synth.ENT_CNOT_LINEAR, th, [(1 << n) - 1], [0], [1.0])
+    assert abs(e - 1) < 1e-12
+
+
+def test_reversibility_and_norm():
+    inst = synth.make_instance(10, 3, 50, 4, 2, seed=8)
+    psi = oracle.prepare(inst.n, inst.layers, inst.ent, inst.theta)
+    assert abs(np.vdot(psi, psi).real - 1) < 1e-13
+    ng = oracle.num_gates(inst.n, inst.layers, inst.ent)
+    oracle.apply_gates(inst.n, inst.layers, inst.ent, inst.theta, psi, 0, ng, inverse=True)
+    e0 = np.zeros_like(psi)
+    e0[0] = 1
+    assert np.abs(psi - e0).max() < 1e-13
+
+
+def test_term_split_eq12():
+    inst = synth.make_instance(10, 2, 80, 4, 4, seed=6, m_off=20)
+    a = slice(0, 37)
+    b = slice(37, None)
+    args = (inst.n, inst.layers, inst.ent, inst.theta)
+    e = oracle.energy(*args, inst.x, inst.z, inst.c).real
+    ea = oracle.energy(*args, inst.x[a], inst.z[a], inst.c[a]).real
+    eb = oracle.energy(*args, inst.x[b], inst.z[b], inst.c[b]).real
+    assert abs(e - (ea + eb)) < 1e-12
+
+
+def test_periodicity_and_restricted_mask():
+    inst = synth.make_instance(8, 2, 40, 4, 2, seed=12, m_off=8, cluster=1)
+    args = (inst.n, inst.layers, inst.ent)
+    e, g = oracle.energy_grad(*args, inst.theta, inst.x, inst.z, inst.c)
+    th2 = inst.theta.copy()
+    th2[3] += 2 * np.pi
+    e2 = oracle.energy(*args, th2, inst.x, inst.z, inst.c)
+    assert abs(e - e2) < 1e-12
+    m = oracle.param_mask(inst.n, inst.layers, inst.cluster_mask)
+    assert m.sum() == 2 * inst.layers * bin(inst.cluster_mask).count("1")
+    _, gm = oracle.energy_grad(*args, inst.theta, inst.x, inst.z, inst.c, mask=m)
+    assert np.all(gm[m == 0] == 0.0)
+    assert np.abs(gm - np.where(m == 1, g, 0.0)).max() < 1e-13
+
+
+def test_adjoint_gate_steps_match_full_sweep():
+    inst = synth.make_instance(8, 2, 30, 3, 2, seed=13)
+    n, L, ent = inst.n, inst.layers, inst.ent
+    e, g = oracle.energy_grad(n, L, ent, inst.theta, inst.x, inst.z, inst.c)
+    phi = oracle.prepare(n, L, ent, inst.theta)
+    lam = oracle.apply_h(n, inst.x, inst.z, inst.c, phi)
+    gg = np.zeros_like(g)
+    ng = oracle.num_gates(n, L, ent)
+    oracle.adjoint_gates(n, L, ent, inst.theta, phi, lam, gg, ng // 2, ng - ng // 2)
+    oracle.adjoint_gates(n, L, ent, inst.theta, phi, lam, gg, 0, ng // 2)
+    assert np.abs(gg - g).max() < 1e-13
