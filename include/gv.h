@@ -1,0 +1,174 @@
+/*
+ * gv.h -- C ABI of the MI355X (gfx950) state-vector energy / gradient engine
+ * for Graph-VQE's hot path.
+ *
+ * What the library computes (Graph-VQE, Sec. IV):
+ *   psi(theta) = U(theta)|0...0>  -- hardware-efficient ansatz: per layer RY on
+ *                                    every qubit, RZ on every qubit, then an
+ *                                    entangler ladder (Sec. IV-B, Eq. 7, Eq. 8)
+ *   H = sum_k c_k P_k             -- real coefficients, Pauli strings (Eq. 6)
+ *   E(theta) = <psi|H|psi>        -- the VQE objective (Eq. 4)
+ *   dE/dtheta                     -- exact gradient (Eq. 13 gives one way to get
+ *                                    it; this library uses a reverse sweep)
+ *   restricted gradient           -- only the parameters of a qubit block
+ *                                    (Eq. 11 and the block gradient of Sec. IV-D)
+ *
+ * Conventions:
+ *   - qubit q is bit q of an amplitude index (little endian);
+ *   - amplitudes are interleaved complex (re, im): float pairs for GV_C64,
+ *     double pairs for GV_C128, 2^n of them, index-ordered;
+ *   - parameters are doubles, index l*2n + g*n + q for layer l, gate g
+ *     (0 = RY, 1 = RZ) and qubit q; P = 2 n (layers + final_rotation);
+ *   - RY(t) = [[cos t/2, -sin t/2], [sin t/2, cos t/2]],
+ *     RZ(t) = diag(exp(-i t/2), exp(i t/2))  (Eq. 7);
+ *   - a Pauli string is the pair of bit masks (x, z) with
+ *     P(x, z) = i^{popcount(x & z)} X^x Z^z, so Y on qubit q is x_q = z_q = 1.
+ *
+ * Memory ownership: every device buffer (state, workspace, Hamiltonian
+ * buffer, parameters, outputs) belongs to the caller and is borrowed for the
+ * lifetime of the handle that was given it.  Compute calls allocate no device
+ * memory.  Host-side handles are owned by the library and released by the
+ * matching *_destroy call.
+ *
+ * Streams: compute calls enqueue work on the state's stream (a hipStream_t
+ * passed as void*, NULL = the default stream) and return without waiting.
+ * Outputs are valid once that stream reaches the point of the call.
+ *
+ * Errors: every call returns a gv_status.  Arguments are validated before any
+ * work is enqueued; on a non-OK status nothing has been enqueued and no output
+ * is written.  GV_EHIP means the HIP runtime reported an error while
+ * enqueueing; state contents are then undefined but the handle stays valid.
+ * gv_last_error() returns a thread-local description of the last failure.
+ * Handles are not thread-safe; distinct handles may be used from distinct
+ * threads.
+ */
+#ifndef GV_H
+#define GV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GV_OK = 0,
+    GV_EINVAL = 1,        /* bad argument (null pointer, range, mask bit >= n, non-finite) */
+    GV_ESIZE = 2,         /* a caller buffer is smaller than required */
+    GV_EUNSUPPORTED = 3,  /* valid request this build does not handle */
+    GV_ESTATE = 4,        /* call order (e.g. energy before any ansatz) or handle mismatch */
+    GV_EHIP = 5           /* HIP runtime error while enqueueing */
+} gv_status;
+
+typedef enum { GV_C64 = 0, GV_C128 = 1 } gv_precision;
+
+/* Entangler of each repeated layer (Sec. IV-B lists linear, circular, full). */
+typedef enum {
+    GV_ENT_NONE = 0,
+    GV_ENT_CZ_LINEAR = 1,     /* CZ(q, q+1), q = 0..n-2 (all commute) */
+    GV_ENT_CZ_CIRCULAR = 2,   /* linear plus CZ(n-1, 0) when n > 2 */
+    GV_ENT_CNOT_LINEAR = 3,   /* CNOT(q -> q+1) applied for q = 0, 1, ..., n-2 */
+    GV_ENT_CNOT_CIRCULAR = 4  /* CNOT(n-1 -> 0) first (n > 2), then the linear ladder */
+} gv_entangler;
+
+/* How the reverse sweep recovers the forward states at large n. */
+typedef enum {
+    GV_GRAD_UNCOMPUTE = 0,    /* undo gates on the final state; no extra memory */
+    GV_GRAD_CHECKPOINT = 1,   /* store the state at the layers-1 inner layer boundaries */
+    GV_GRAD_RECOMPUTE = 2     /* re-run the forward from |0> to each layer boundary */
+} gv_grad_mode;
+
+/* Kernel family.  FUSED: tile passes that apply many gates per HBM sweep.
+ * PLAIN: one kernel per gate (the straightforward reference GPU path). */
+typedef enum { GV_ENGINE_FUSED = 0, GV_ENGINE_PLAIN = 1 } gv_engine;
+
+typedef struct {
+    int32_t n;               /* qubits, 1..34 */
+    int32_t layers;          /* repeated [RY all, RZ all, entangler] layers, >= 0 */
+    int32_t ent;             /* gv_entangler */
+    int32_t final_rotation;  /* 1: one more RY/RZ layer without entangler
+                                (EfficientSU2 of Eq. 8: P = 2 n (layers + 1)) */
+} gv_ansatz;
+
+typedef struct gv_state_s *gv_state;
+typedef struct gv_pauli_s *gv_pauli_sum;
+
+/* Library version string. */
+const char *gv_version(void);
+
+/* Thread-local text of the last non-OK status ("" if none). */
+const char *gv_last_error(void);
+
+/* Number of ansatz parameters, 2 n (layers + final_rotation), or -1 if the
+ * ansatz is invalid. */
+int64_t gv_num_params(const gv_ansatz *ansatz);
+
+/* Buffer sizes for a state that will run `ansatz` in `prec` with gradient
+ * mode `mode` on `engine`: state_bytes = 2^n amplitudes; work_bytes = the
+ * workspace gv_energy_grad needs (adjoint vector, checkpoints, tables,
+ * reduction partials).  Either output pointer may be NULL. */
+gv_status gv_query_sizes(const gv_ansatz *ansatz, gv_precision prec, gv_engine engine,
+                         gv_grad_mode mode, size_t *state_bytes, size_t *work_bytes);
+
+/* Create a state over caller-owned device memory.
+ *   amps_dev / amps_bytes: >= 2^n amplitudes of `prec`, 256-byte aligned;
+ *   work_dev / work_bytes: workspace (may be NULL/0 when only gv_apply_ansatz
+ *                          and gv_energy are used with the PLAIN engine);
+ *   stream: hipStream_t (as void*), NULL for the default stream.
+ * The state starts "empty": gv_energy before gv_apply_ansatz is GV_ESTATE. */
+gv_status gv_state_create(int32_t n, gv_precision prec, gv_engine engine,
+                          void *amps_dev, size_t amps_bytes,
+                          void *work_dev, size_t work_bytes,
+                          void *stream, gv_state *out);
+gv_status gv_state_destroy(gv_state st);
+gv_status gv_state_set_stream(gv_state st, void *stream);
+
+/* psi <- U(theta)|0...0> (Eq. 7, Eq. 8).  params_dev: device doubles, P of
+ * them.  ansatz->n must equal the state's n. */
+gv_status gv_apply_ansatz(gv_state st, const double *params_dev, const gv_ansatz *ansatz);
+
+/* Build a Pauli sum from host arrays (copied; Eq. 6).  Terms with the same
+ * (x, z) are merged by adding coefficients; zero coefficients are dropped.
+ * Mask bits >= n and non-finite coefficients are GV_EINVAL. */
+gv_status gv_pauli_sum_create(int32_t n, int64_t m, const uint64_t *x, const uint64_t *z,
+                              const double *c, gv_pauli_sum *out);
+gv_status gv_pauli_sum_destroy(gv_pauli_sum h);
+
+/* Counts after merging: diagonal (Z-only, incl. identity) terms, off-diagonal
+ * terms, qubit-wise-commuting groups of the off-diagonal terms.  Any output
+ * pointer may be NULL. */
+gv_status gv_pauli_sum_info(gv_pauli_sum h, int64_t *n_diag, int64_t *n_offdiag,
+                            int64_t *n_groups);
+
+/* Device bytes the Hamiltonian needs: the FP64 diagonal of its Z-only part
+ * (2^n doubles) followed by the off-diagonal term tables. */
+gv_status gv_pauli_sum_device_bytes(gv_pauli_sum h, size_t *bytes);
+
+/* Build the device form of H into caller memory `dev` (>= device_bytes,
+ * 256-byte aligned): the diagonal D_i = sum_{k: x_k = 0} c_k (-1)^{|i & z_k|}
+ * by an in-place fast Walsh-Hadamard transform, and the off-diagonal tables.
+ * Runs on the state's stream and waits for it (a setup call).  `dev` is
+ * borrowed until gv_pauli_sum_destroy. */
+gv_status gv_pauli_sum_prepare(gv_pauli_sum h, gv_state st, void *dev, size_t bytes);
+
+/* <psi|H|psi> of the state's current psi.  energy_dev: 2 device doubles
+ * (real part, imaginary part; the latter is rounding noise for real c_k).
+ * Needs work memory for reduction partials (FUSED: always; PLAIN: >= 1 MiB). */
+gv_status gv_energy(gv_state st, gv_pauli_sum h, double *energy_dev);
+
+/* Energy and gradient at params_dev (Eq. 4; gradient as Eq. 13 defines it).
+ *   grad_mask_dev: NULL = every parameter; else P device bytes, nonzero where
+ *                  the gradient is wanted (restricted update of Eq. 11); other
+ *                  entries of grad_dev are written as 0;
+ *   mode: how forward states are recovered in the reverse sweep;
+ *   energy_dev: 2 device doubles (re, im); grad_dev: P device doubles.
+ * Leaves psi(theta) in the state's amplitude buffer. */
+gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *params_dev,
+                         const gv_ansatz *ansatz, const uint8_t *grad_mask_dev,
+                         gv_grad_mode mode, double *energy_dev, double *grad_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GV_H */

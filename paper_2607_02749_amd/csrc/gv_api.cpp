@@ -1,0 +1,672 @@
+// gv_api.cpp -- the C ABI (include/gv.h): validation, Hamiltonian ingest and
+// canonicalisation (Eq. 6), planning, and the launch sequences of the energy
+// (Eq. 4) and its gradient.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "gv_internal.hpp"
+
+namespace gv {
+
+static thread_local std::string g_last_error;
+
+gv_status set_error(gv_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+gv_status check_hip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return GV_OK;
+    return set_error(GV_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int rot_layers(const gv_ansatz &a) { return a.layers + a.final_rotation; }
+int64_t nparams(const gv_ansatz &a) { return 2ll * a.n * rot_layers(a); }
+
+// Tile passes of one layer: pass 0 takes bits 0..K-1; later passes keep the C
+// low bits (for contiguous runs) and take the next K-C unprocessed bits,
+// topping up with already-processed bits so every tile has K bits.
+bool make_tile_plan(int n, int K, int C, TilePlan *out)
+{
+    if (K < 1 || K > kMaxTileBits || K > n || C < 0 || C > K) return false;
+    TilePlan p;
+    p.K = K;
+    p.C = C;
+    p.npass = 0;
+    int next = K;
+    {
+        PassPlan &pp = p.pass[p.npass++];
+        for (int j = 0; j < K; ++j) pp.pos[j] = (int8_t)j;
+        pp.active = (K >= 32) ? 0xffffffffu : ((1u << K) - 1u);
+    }
+    while (next < n) {
+        if (p.npass >= kMaxPasses || K - C < 1) return false;
+        const int m = std::min(K - C, n - next);
+        std::vector<int> bits;
+        for (int j = 0; j < C; ++j) bits.push_back(j);
+        const int fill = K - C - m;
+        for (int j = 0; j < fill; ++j) bits.push_back(C + j);   // C + fill <= next
+        for (int j = 0; j < m; ++j) bits.push_back(next + j);
+        std::sort(bits.begin(), bits.end());
+        PassPlan &pp = p.pass[p.npass++];
+        pp.active = 0;
+        for (int j = 0; j < K; ++j) {
+            pp.pos[j] = (int8_t)bits[j];
+            if (bits[j] >= next) pp.active |= 1u << j;
+        }
+        next += m;
+    }
+    *out = p;
+    return true;
+}
+
+Chunks make_chunks(int n)
+{
+    const int nc = (n + 11) / 12 < 1 ? 1 : (n + 11) / 12;
+    const int b1 = std::min(n, (n + nc - 1) / nc);
+    const int b2 = std::min(n, 2 * b1);
+    Chunks c;
+    c.b1 = b1;
+    c.b2 = b2;
+    c.size0 = 1 << b1;
+    c.size1 = 1 << (b2 - b1);
+    c.size2 = 1 << (n - b2);
+    return c;
+}
+
+static const int kEnergyGrid = 1024;
+
+static int choose_K(int n) { return n >= 12 ? 12 : (n >= 10 ? 10 : 8); }
+static int choose_C(gv_precision p, int K) { return std::min(K - 1, p == GV_C64 ? 4 : 3); }
+static bool fused_ok(gv_engine e, int n) { return e == GV_ENGINE_FUSED && n >= 8; }
+
+gv_status work_layout(const gv_ansatz &a, gv_precision prec, gv_engine eng, gv_grad_mode mode,
+                      WorkLayout *out)
+{
+    WorkLayout w;
+    const size_t s = amp_bytes(prec);
+    const size_t A = (size_t)1 << a.n;
+    const int64_t P = nparams(a);
+    const int R = rot_layers(a);
+    size_t off = 0;
+    w.epart = off;
+    off += align_up(2 * kEnergyGrid * sizeof(double));
+    if (fused_ok(eng, a.n)) {
+        TilePlan plan;
+        if (!make_tile_plan(a.n, choose_K(a.n), choose_C(prec, choose_K(a.n)), &plan))
+            return set_error(GV_EUNSUPPORTED, "no tile plan for n=%d", a.n);
+        w.grid = fused_grid(prec, plan, a.n);
+        const Chunks ch = make_chunks(a.n);
+        w.dtab_stride = align_up((size_t)(ch.size0 + ch.size1 + ch.size2) * s);
+        w.ry_tab = off;
+        off += align_up((size_t)P * 2 * sizeof(double) + 8);
+        w.dtab = off;
+        off += w.dtab_stride * (size_t)(R > 0 ? R : 1);
+        w.gtab = off;
+        off += w.dtab_stride;
+    } else {
+        w.grid = kPlainGrid;
+    }
+    w.part = off;
+    off += align_up((size_t)P * w.grid * sizeof(double) + 8);
+    w.lam = off;
+    off += align_up(A * s);
+    const bool cnot = a.ent == GV_ENT_CNOT_LINEAR || a.ent == GV_ENT_CNOT_CIRCULAR;
+    if (fused_ok(eng, a.n) && cnot) {
+        w.scratch = off;
+        off += align_up(A * s);
+    }
+    if (mode == GV_GRAD_CHECKPOINT && fused_ok(eng, a.n) && R > 1) {
+        w.ckpt = off;
+        off += align_up(A * s) * (size_t)(R - 1);
+    }
+    w.total = off;
+    *out = w;
+    return GV_OK;
+}
+
+// ----------------------------------------------------------------- validation
+
+static gv_status check_ansatz(const gv_ansatz *a)
+{
+    if (!a) return set_error(GV_EINVAL, "ansatz is NULL");
+    if (a->n < 1 || a->n > kMaxQubits)
+        return set_error(GV_EINVAL, "n=%d outside 1..%d", a->n, kMaxQubits);
+    if (a->layers < 0 || a->layers > 4096) return set_error(GV_EINVAL, "layers=%d", a->layers);
+    if (a->final_rotation != 0 && a->final_rotation != 1)
+        return set_error(GV_EINVAL, "final_rotation must be 0 or 1");
+    if (a->ent < GV_ENT_NONE || a->ent > GV_ENT_CNOT_CIRCULAR)
+        return set_error(GV_EINVAL, "unknown entangler %d", a->ent);
+    return GV_OK;
+}
+
+static bool aligned(const void *p) { return ((uintptr_t)p % kAlign) == 0; }
+
+// ------------------------------------------------------------------ gate list
+struct Gate {
+    int kind;  // 0 RY, 1 RZ, 2 CZ, 3 CNOT
+    int a, b;
+    int64_t p;
+};
+
+static std::vector<Gate> gate_list(const gv_ansatz &an)
+{
+    std::vector<Gate> g;
+    const int n = an.n;
+    for (int l = 0; l < rot_layers(an); ++l) {
+        const int64_t base = (int64_t)l * 2 * n;
+        for (int q = 0; q < n; ++q) g.push_back({0, q, -1, base + q});
+        for (int q = 0; q < n; ++q) g.push_back({1, q, -1, base + n + q});
+        if (l >= an.layers) break;
+        if (an.ent == GV_ENT_CZ_LINEAR || an.ent == GV_ENT_CZ_CIRCULAR) {
+            for (int q = 0; q + 1 < n; ++q) g.push_back({2, q, q + 1, -1});
+            if (an.ent == GV_ENT_CZ_CIRCULAR && n > 2) g.push_back({2, n - 1, 0, -1});
+        } else if (an.ent == GV_ENT_CNOT_LINEAR || an.ent == GV_ENT_CNOT_CIRCULAR) {
+            if (an.ent == GV_ENT_CNOT_CIRCULAR && n > 2) g.push_back({3, n - 1, 0, -1});
+            for (int q = 0; q + 1 < n; ++q) g.push_back({3, q, q + 1, -1});
+        }
+    }
+    return g;
+}
+
+// ------------------------------------------------------------- launch chains
+
+static gv_status plain_forward(gv_state st, const gv_ansatz &an, const double *theta)
+{
+    const int prec = st->prec;
+    hipStream_t s = st->stream;
+    if (gv_status e = check_hip(plain_set_zero_state(prec, st->amps, an.n, s), "zero state"))
+        return e;
+    for (const Gate &g : gate_list(an)) {
+        hipError_t e;
+        switch (g.kind) {
+        case 0: e = plain_ry(prec, st->amps, an.n, g.a, theta, g.p, 0, s); break;
+        case 1: e = plain_rz(prec, st->amps, an.n, g.a, theta, g.p, 0, s); break;
+        case 2: e = plain_cz(prec, st->amps, an.n, g.a, g.b, s); break;
+        default: e = plain_cnot(prec, st->amps, an.n, g.a, g.b, s); break;
+        }
+        if (gv_status r = check_hip(e, "plain gate")) return r;
+    }
+    return GV_OK;
+}
+
+struct FusedCtx {
+    TilePlan plan;
+    Chunks ch;
+    FusedTables tabs;
+    WorkLayout w;
+};
+
+static gv_status fused_layer(gv_state st, const gv_ansatz &an, const FusedCtx &c, int l,
+                             void *psi, void *scratch)
+{
+    hipStream_t s = st->stream;
+    for (int p = 0; p < c.plan.npass; ++p) {
+        hipError_t e = fused_forward_pass(st->prec, psi, an, c.plan, p, l,
+                                          p == c.plan.npass - 1, c.ch, c.tabs, s);
+        if (gv_status r = check_hip(e, "forward pass")) return r;
+    }
+    const bool cnot = an.ent == GV_ENT_CNOT_LINEAR || an.ent == GV_ENT_CNOT_CIRCULAR;
+    if (cnot && l < an.layers) {
+        const size_t bytes = ((size_t)1 << an.n) * amp_bytes(st->prec);
+        if (gv_status r = check_hip(cnot_ladder_gather(st->prec, psi, scratch, an.n,
+                                                       an.ent == GV_ENT_CNOT_CIRCULAR, 0, s),
+                                    "cnot gather"))
+            return r;
+        if (gv_status r = check_hip(copy_vector(psi, scratch, bytes, s), "copy")) return r;
+    }
+    return GV_OK;
+}
+
+static gv_status fused_first_layer(gv_state st, const gv_ansatz &an, const FusedCtx &c,
+                                   void *psi, void *scratch)
+{
+    hipStream_t s = st->stream;
+    if (gv_status r = check_hip(fused_init_state(st->prec, psi, an, c.ch, c.tabs, s), "init"))
+        return r;
+    const bool cnot = an.ent == GV_ENT_CNOT_LINEAR || an.ent == GV_ENT_CNOT_CIRCULAR;
+    if (cnot && an.layers > 0) {
+        const size_t bytes = ((size_t)1 << an.n) * amp_bytes(st->prec);
+        if (gv_status r = check_hip(cnot_ladder_gather(st->prec, psi, scratch, an.n,
+                                                       an.ent == GV_ENT_CNOT_CIRCULAR, 0, s),
+                                    "cnot gather"))
+            return r;
+        if (gv_status r = check_hip(copy_vector(psi, scratch, bytes, s), "copy")) return r;
+    }
+    return GV_OK;
+}
+
+static gv_status fused_setup(gv_state st, const gv_ansatz &an, const double *theta,
+                             gv_grad_mode mode, FusedCtx *c)
+{
+    if (gv_status r = work_layout(an, st->prec, st->engine, mode, &c->w)) return r;
+    if (c->w.total > st->work_bytes)
+        return set_error(GV_ESIZE, "work buffer %zu bytes < %zu needed", st->work_bytes,
+                         c->w.total);
+    const int K = choose_K(an.n);
+    make_tile_plan(an.n, K, choose_C(st->prec, K), &c->plan);
+    c->ch = make_chunks(an.n);
+    char *w = (char *)st->work;
+    c->tabs.ry = (const double *)(w + c->w.ry_tab);
+    c->tabs.dtab = w + c->w.dtab;
+    c->tabs.dtab_stride = c->w.dtab_stride;
+    c->tabs.gtab = w + c->w.gtab;
+    return check_hip(fused_build_tables(st->prec, an, c->ch, theta, c->tabs, st->stream), "tables");
+}
+
+// forward from |0> through rotation layers [0, upto]
+static gv_status fused_forward(gv_state st, const gv_ansatz &an, const FusedCtx &c, int upto,
+                               void *psi, char *ckpt, size_t vec_bytes)
+{
+    char *scratch = (char *)st->work + c.w.scratch;
+    if (gv_status r = fused_first_layer(st, an, c, psi, scratch)) return r;
+    if (ckpt && upto > 0)
+        if (gv_status r = check_hip(copy_vector(ckpt, psi, vec_bytes, st->stream), "checkpoint"))
+            return r;
+    for (int l = 1; l <= upto; ++l) {
+        if (gv_status r = fused_layer(st, an, c, l, psi, scratch)) return r;
+        if (ckpt && l < upto)
+            if (gv_status r = check_hip(copy_vector(ckpt + (size_t)l * vec_bytes, psi, vec_bytes,
+                                                    st->stream),
+                                        "checkpoint"))
+                return r;
+    }
+    return GV_OK;
+}
+
+static gv_status energy_chain(gv_state st, gv_pauli_sum h, void *lam, double *epart,
+                              double *energy)
+{
+    hipStream_t s = st->stream;
+    if (gv_status r = check_hip(energy_diag(st->prec, st->amps, h->diag, lam, st->n, epart,
+                                            kEnergyGrid, s),
+                                "energy diag"))
+        return r;
+    if (!h->oc.empty())
+        if (gv_status r = check_hip(energy_offdiag_terms(st->prec, st->amps, lam, st->n,
+                                                         (int64_t)h->oc.size(), h->ox.data(),
+                                                         h->oz.data(), h->oc.data(), epart,
+                                                         kEnergyGrid, s),
+                                    "energy off-diagonal"))
+            return r;
+    return check_hip(reduce_energy(epart, kEnergyGrid, energy, s), "energy reduce");
+}
+
+}  // namespace gv
+
+using namespace gv;
+
+// ======================================================================= ABI
+
+extern "C" {
+
+const char *gv_version(void) { return "gv 0.1 (gfx950)"; }
+
+const char *gv_last_error(void) { return g_last_error.c_str(); }
+
+int64_t gv_num_params(const gv_ansatz *a)
+{
+    if (check_ansatz(a) != GV_OK) return -1;
+    return nparams(*a);
+}
+
+gv_status gv_query_sizes(const gv_ansatz *a, gv_precision prec, gv_engine engine,
+                         gv_grad_mode mode, size_t *state_bytes, size_t *work_bytes)
+{
+    if (gv_status r = check_ansatz(a)) return r;
+    if (prec != GV_C64 && prec != GV_C128) return set_error(GV_EINVAL, "precision");
+    if (engine != GV_ENGINE_FUSED && engine != GV_ENGINE_PLAIN) return set_error(GV_EINVAL, "engine");
+    if (mode < GV_GRAD_UNCOMPUTE || mode > GV_GRAD_RECOMPUTE) return set_error(GV_EINVAL, "mode");
+    WorkLayout w;
+    if (gv_status r = work_layout(*a, prec, engine, mode, &w)) return r;
+    if (state_bytes) *state_bytes = ((size_t)1 << a->n) * amp_bytes(prec);
+    if (work_bytes) *work_bytes = w.total;
+    return GV_OK;
+}
+
+gv_status gv_state_create(int32_t n, gv_precision prec, gv_engine engine, void *amps,
+                          size_t amps_bytes, void *work, size_t work_bytes, void *stream,
+                          gv_state *out)
+{
+    if (!out) return set_error(GV_EINVAL, "out is NULL");
+    if (n < 1 || n > kMaxQubits) return set_error(GV_EINVAL, "n=%d outside 1..%d", n, kMaxQubits);
+    if (prec != GV_C64 && prec != GV_C128) return set_error(GV_EINVAL, "precision %d", prec);
+    if (engine != GV_ENGINE_FUSED && engine != GV_ENGINE_PLAIN)
+        return set_error(GV_EINVAL, "engine %d", engine);
+    if (!amps) return set_error(GV_EINVAL, "amplitude buffer is NULL");
+    const size_t need = ((size_t)1 << n) * amp_bytes(prec);
+    if (amps_bytes < need)
+        return set_error(GV_ESIZE, "amplitude buffer %zu bytes < %zu", amps_bytes, need);
+    if (!aligned(amps) || (work && !aligned(work)))
+        return set_error(GV_EINVAL, "device buffers must be %zu-byte aligned", kAlign);
+    gv_state st = new (std::nothrow) gv_state_s;
+    if (!st) return set_error(GV_EINVAL, "out of host memory");
+    st->n = n;
+    st->prec = prec;
+    st->engine = engine;
+    st->amps = amps;
+    st->amps_bytes = amps_bytes;
+    st->work = work;
+    st->work_bytes = work ? work_bytes : 0;
+    st->stream = (hipStream_t)stream;
+    *out = st;
+    return GV_OK;
+}
+
+gv_status gv_state_destroy(gv_state st)
+{
+    delete st;
+    return GV_OK;
+}
+
+gv_status gv_state_set_stream(gv_state st, void *stream)
+{
+    if (!st) return set_error(GV_EINVAL, "state is NULL");
+    st->stream = (hipStream_t)stream;
+    return GV_OK;
+}
+
+gv_status gv_apply_ansatz(gv_state st, const double *theta, const gv_ansatz *a)
+{
+    if (!st) return set_error(GV_EINVAL, "state is NULL");
+    if (gv_status r = check_ansatz(a)) return r;
+    if (a->n != st->n) return set_error(GV_ESTATE, "ansatz n=%d but state n=%d", a->n, st->n);
+    if (!theta) return set_error(GV_EINVAL, "params is NULL");
+    if (rot_layers(*a) == 0) {
+        if (gv_status r = check_hip(plain_set_zero_state(st->prec, st->amps, a->n, st->stream),
+                                    "zero state"))
+            return r;
+    } else if (fused_ok(st->engine, a->n)) {
+        FusedCtx c;
+        if (gv_status r = fused_setup(st, *a, theta, GV_GRAD_UNCOMPUTE, &c)) return r;
+        const size_t vb = ((size_t)1 << a->n) * amp_bytes(st->prec);
+        if (gv_status r = fused_forward(st, *a, c, rot_layers(*a) - 1, st->amps, nullptr, vb))
+            return r;
+    } else {
+        if (gv_status r = plain_forward(st, *a, theta)) return r;
+    }
+    st->has_psi = true;
+    return GV_OK;
+}
+
+gv_status gv_pauli_sum_create(int32_t n, int64_t m, const uint64_t *x, const uint64_t *z,
+                              const double *c, gv_pauli_sum *out)
+{
+    if (!out) return set_error(GV_EINVAL, "out is NULL");
+    if (n < 1 || n > kMaxQubits) return set_error(GV_EINVAL, "n=%d outside 1..%d", n, kMaxQubits);
+    if (m < 0) return set_error(GV_EINVAL, "m < 0");
+    if (m > 0 && (!x || !z || !c)) return set_error(GV_EINVAL, "term arrays are NULL");
+    const uint64_t valid = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+    std::map<std::pair<uint64_t, uint64_t>, double> merged;
+    for (int64_t k = 0; k < m; ++k) {
+        if ((x[k] | z[k]) & ~valid)
+            return set_error(GV_EINVAL, "term %lld has a mask bit >= n", (long long)k);
+        if (!isfinite(c[k]))
+            return set_error(GV_EINVAL, "term %lld has a non-finite coefficient", (long long)k);
+        merged[std::make_pair(x[k], z[k])] += c[k];
+    }
+    gv_pauli_sum h = new (std::nothrow) gv_pauli_s;
+    if (!h) return set_error(GV_EINVAL, "out of host memory");
+    h->n = n;
+    for (const auto &kv : merged) {
+        if (kv.second == 0.0) continue;
+        if (kv.first.first == 0) {
+            h->dz.push_back(kv.first.second);
+            h->dc.push_back(kv.second);
+        } else {
+            h->ox.push_back(kv.first.first);
+            h->oz.push_back(kv.first.second);
+            h->oc.push_back(kv.second);
+        }
+    }
+    // greedy qubit-wise-commuting groups of the off-diagonal terms: every
+    // qubit carries one letter (X, Y or Z) per group
+    for (size_t k = 0; k < h->ox.size(); ++k) {
+        const uint64_t xk = h->ox[k], zk = h->oz[k];
+        const uint64_t X = xk & ~zk, Y = xk & zk, Z = zk & ~xk;
+        bool placed = false;
+        for (QwcGroup &g : h->groups) {
+            const uint64_t gsup = g.xmask | g.ymask | g.zmask, ksup = xk | zk;
+            const uint64_t both = gsup & ksup;
+            if (((g.xmask ^ X) & both) || ((g.ymask ^ Y) & both) || ((g.zmask ^ Z) & both))
+                continue;
+            g.xmask |= X;
+            g.ymask |= Y;
+            g.zmask |= Z;
+            g.terms.push_back((int64_t)k);
+            placed = true;
+            break;
+        }
+        if (!placed) {
+            QwcGroup g;
+            g.xmask = X;
+            g.ymask = Y;
+            g.zmask = Z;
+            g.terms.push_back((int64_t)k);
+            h->groups.push_back(g);
+        }
+    }
+    *out = h;
+    return GV_OK;
+}
+
+gv_status gv_pauli_sum_destroy(gv_pauli_sum h)
+{
+    delete h;
+    return GV_OK;
+}
+
+gv_status gv_pauli_sum_info(gv_pauli_sum h, int64_t *n_diag, int64_t *n_offdiag, int64_t *n_groups)
+{
+    if (!h) return set_error(GV_EINVAL, "pauli sum is NULL");
+    if (n_diag) *n_diag = (int64_t)h->dz.size();
+    if (n_offdiag) *n_offdiag = (int64_t)h->ox.size();
+    if (n_groups) *n_groups = (int64_t)h->groups.size();
+    return GV_OK;
+}
+
+static void pauli_layout(const gv_pauli_s *h, size_t *diag, size_t *ox, size_t *oz, size_t *oc,
+                         size_t *sz, size_t *sc, size_t *total)
+{
+    size_t off = 0;
+    *diag = off;
+    off += align_up(((size_t)1 << h->n) * sizeof(double));
+    *ox = off;
+    off += align_up(h->ox.size() * 8 + 8);
+    *oz = off;
+    off += align_up(h->oz.size() * 8 + 8);
+    *oc = off;
+    off += align_up(h->oc.size() * 8 + 8);
+    *sz = off;
+    off += align_up(h->dz.size() * 8 + 8);
+    *sc = off;
+    off += align_up(h->dc.size() * 8 + 8);
+    *total = off;
+}
+
+gv_status gv_pauli_sum_device_bytes(gv_pauli_sum h, size_t *bytes)
+{
+    if (!h || !bytes) return set_error(GV_EINVAL, "NULL argument");
+    size_t a, b, c, d, e, f;
+    pauli_layout(h, &a, &b, &c, &d, &e, &f, bytes);
+    return GV_OK;
+}
+
+gv_status gv_pauli_sum_prepare(gv_pauli_sum h, gv_state st, void *dev, size_t bytes)
+{
+    if (!h || !st || !dev) return set_error(GV_EINVAL, "NULL argument");
+    if (h->n != st->n) return set_error(GV_ESTATE, "pauli sum n=%d but state n=%d", h->n, st->n);
+    if (!aligned(dev)) return set_error(GV_EINVAL, "buffer must be %zu-byte aligned", kAlign);
+    size_t odiag, oox, ooz, ooc, osz, osc, total;
+    pauli_layout(h, &odiag, &oox, &ooz, &ooc, &osz, &osc, &total);
+    if (bytes < total) return set_error(GV_ESIZE, "buffer %zu bytes < %zu", bytes, total);
+    char *base = (char *)dev;
+    hipStream_t s = st->stream;
+    h->dev = dev;
+    h->dev_bytes = bytes;
+    h->diag = (double *)(base + odiag);
+    h->dev_ox = (uint64_t *)(base + oox);
+    h->dev_oz = (uint64_t *)(base + ooz);
+    h->dev_oc = (double *)(base + ooc);
+    h->prepared = false;
+    const int n = h->n;
+    if (!h->ox.empty()) {
+        if (gv_status r = check_hip(hipMemcpyAsync(h->dev_ox, h->ox.data(), h->ox.size() * 8,
+                                                   hipMemcpyHostToDevice, s), "copy"))
+            return r;
+        if (gv_status r = check_hip(hipMemcpyAsync(h->dev_oz, h->oz.data(), h->oz.size() * 8,
+                                                   hipMemcpyHostToDevice, s), "copy"))
+            return r;
+        if (gv_status r = check_hip(hipMemcpyAsync(h->dev_oc, h->oc.data(), h->oc.size() * 8,
+                                                   hipMemcpyHostToDevice, s), "copy"))
+            return r;
+    }
+    uint64_t *sz = (uint64_t *)(base + osz);
+    double *sc = (double *)(base + osc);
+    if (!h->dz.empty()) {
+        if (gv_status r = check_hip(hipMemcpyAsync(sz, h->dz.data(), h->dz.size() * 8,
+                                                   hipMemcpyHostToDevice, s), "copy"))
+            return r;
+        if (gv_status r = check_hip(hipMemcpyAsync(sc, h->dc.data(), h->dc.size() * 8,
+                                                   hipMemcpyHostToDevice, s), "copy"))
+            return r;
+    }
+    if (gv_status r = check_hip(fill_zero_f64(h->diag, 1ull << n, s), "zero diag")) return r;
+    if (gv_status r = check_hip(scatter_coeffs(h->diag, sz, sc, (int64_t)h->dz.size(), s), "scatter"))
+        return r;
+    if (gv_status r = check_hip(fwht_inplace(h->diag, n, s), "fwht")) return r;
+    if (gv_status r = check_hip(hipStreamSynchronize(s), "prepare sync")) return r;
+    h->prepared = true;
+    return GV_OK;
+}
+
+gv_status gv_energy(gv_state st, gv_pauli_sum h, double *energy)
+{
+    if (!st || !h || !energy) return set_error(GV_EINVAL, "NULL argument");
+    if (!h->prepared) return set_error(GV_ESTATE, "pauli sum not prepared");
+    if (h->n != st->n) return set_error(GV_ESTATE, "pauli sum n=%d but state n=%d", h->n, st->n);
+    if (!st->has_psi) return set_error(GV_ESTATE, "no state: call gv_apply_ansatz first");
+    if (st->work_bytes < align_up(2 * kEnergyGrid * sizeof(double)))
+        return set_error(GV_ESIZE, "energy needs >= %zu work bytes",
+                         align_up(2 * kEnergyGrid * sizeof(double)));
+    return energy_chain(st, h, nullptr, (double *)st->work, energy);
+}
+
+gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const gv_ansatz *a,
+                         const uint8_t *mask, gv_grad_mode mode, double *energy, double *grad)
+{
+    if (!st || !h || !theta || !energy || !grad) return set_error(GV_EINVAL, "NULL argument");
+    if (gv_status r = check_ansatz(a)) return r;
+    if (a->n != st->n) return set_error(GV_ESTATE, "ansatz n=%d but state n=%d", a->n, st->n);
+    if (!h->prepared) return set_error(GV_ESTATE, "pauli sum not prepared");
+    if (h->n != st->n) return set_error(GV_ESTATE, "pauli sum n=%d but state n=%d", h->n, st->n);
+    if (mode < GV_GRAD_UNCOMPUTE || mode > GV_GRAD_RECOMPUTE) return set_error(GV_EINVAL, "mode");
+    const int64_t P = nparams(*a);
+    const int n = a->n;
+    const size_t vb = ((size_t)1 << n) * amp_bytes(st->prec);
+    hipStream_t s = st->stream;
+    char *w = (char *)st->work;
+
+    if (!fused_ok(st->engine, n)) {
+        if (mode != GV_GRAD_UNCOMPUTE)
+            return set_error(GV_EUNSUPPORTED, "the plain engine runs the uncompute sweep only");
+        WorkLayout L;
+        if (gv_status r = work_layout(*a, st->prec, st->engine, mode, &L)) return r;
+        if (L.total > st->work_bytes)
+            return set_error(GV_ESIZE, "work buffer %zu bytes < %zu needed", st->work_bytes, L.total);
+        void *lam = w + L.lam;
+        double *part = (double *)(w + L.part);
+        if (gv_status r = plain_forward(st, *a, theta)) return r;
+        if (gv_status r = energy_chain(st, h, lam, (double *)(w + L.epart), energy)) return r;
+        const std::vector<Gate> g = gate_list(*a);
+        for (size_t k = g.size(); k-- > 0;) {
+            const Gate &G = g[k];
+            hipError_t e;
+            switch (G.kind) {
+            case 0:
+                e = plain_adj_ry(st->prec, st->amps, lam, n, G.a, theta, G.p, part + G.p * L.grid, s);
+                break;
+            case 1:
+                e = plain_adj_rz(st->prec, st->amps, lam, n, G.a, theta, G.p, part + G.p * L.grid, s);
+                break;
+            case 2:
+                e = plain_cz(st->prec, st->amps, n, G.a, G.b, s);
+                if (e == hipSuccess) e = plain_cz(st->prec, lam, n, G.a, G.b, s);
+                break;
+            default:
+                e = plain_cnot(st->prec, st->amps, n, G.a, G.b, s);
+                if (e == hipSuccess) e = plain_cnot(st->prec, lam, n, G.a, G.b, s);
+                break;
+            }
+            if (gv_status r = check_hip(e, "reverse step")) return r;
+        }
+        st->has_psi = false;
+        return check_hip(reduce_rows(part, P, L.grid, mask, grad, s), "grad reduce");
+    }
+
+    const int R = rot_layers(*a);
+    if (R == 0) {  // no parameters: psi = |0...0>
+        if (st->work_bytes < align_up(2 * kEnergyGrid * sizeof(double)))
+            return set_error(GV_ESIZE, "work buffer too small");
+        if (gv_status r = check_hip(plain_set_zero_state(st->prec, st->amps, n, s), "zero"))
+            return r;
+        st->has_psi = true;
+        return energy_chain(st, h, nullptr, (double *)w, energy);
+    }
+    FusedCtx c;
+    if (gv_status r = fused_setup(st, *a, theta, mode, &c)) return r;
+    void *psi = st->amps;
+    void *lam = w + c.w.lam;
+    char *ckpt = mode == GV_GRAD_CHECKPOINT && R > 1 ? w + c.w.ckpt : nullptr;
+    char *scratch = w + c.w.scratch;
+    double *part = (double *)(w + c.w.part);
+    const bool cnot = a->ent == GV_ENT_CNOT_LINEAR || a->ent == GV_ENT_CNOT_CIRCULAR;
+
+    if (gv_status r = fused_forward(st, *a, c, R - 1, psi, ckpt, vb)) return r;
+    if (gv_status r = energy_chain(st, h, lam, (double *)(w + c.w.epart), energy)) return r;
+
+    for (int l = R - 1; l >= 0; --l) {
+        const void *phi_src = psi;
+        if (l < R - 1) {
+            if (mode == GV_GRAD_RECOMPUTE) {
+                if (gv_status r = fused_forward(st, *a, c, l, psi, nullptr, vb)) return r;
+            } else if (mode == GV_GRAD_CHECKPOINT) {
+                phi_src = ckpt + (size_t)l * vb;
+            }
+        }
+        if (cnot && l < a->layers) {
+            const int circ = a->ent == GV_ENT_CNOT_CIRCULAR;
+            hipError_t e = cnot_ladder_gather(st->prec, phi_src, scratch, n, circ, 1, s);
+            if (e == hipSuccess) e = copy_vector(psi, scratch, vb, s);
+            if (e == hipSuccess) e = cnot_ladder_gather(st->prec, lam, scratch, n, circ, 1, s);
+            if (e == hipSuccess) e = copy_vector(lam, scratch, vb, s);
+            if (gv_status r = check_hip(e, "cnot undo")) return r;
+            phi_src = psi;
+        }
+        for (int p = 0; p < c.plan.npass; ++p) {
+            hipError_t e = fused_backward_pass(st->prec, p == 0 ? phi_src : psi, psi, lam, *a,
+                                               c.plan, p, l, p == 0, c.ch, c.tabs, part, c.w.grid, s);
+            if (gv_status r = check_hip(e, "backward pass")) return r;
+        }
+    }
+    st->has_psi = false;
+    return check_hip(reduce_rows(part, P, c.w.grid, mask, grad, s), "grad reduce");
+}
+
+}  // extern "C"

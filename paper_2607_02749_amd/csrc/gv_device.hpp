@@ -1,0 +1,49 @@
+// gv_device.hpp -- device-side helpers shared by the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gv {
+
+typedef uint64_t u64;
+
+template <typename R>
+struct alignas(2 * sizeof(R)) cx {
+    R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b)
+{
+    cx<R> o;
+    o.re = a.re * b.re - a.im * b.im;
+    o.im = a.re * b.im + a.im * b.re;
+    return o;
+}
+
+// k with a zero bit inserted at position q
+__device__ __forceinline__ u64 insert_zero(u64 k, int q)
+{
+    const u64 lo = k & ((1ull << q) - 1);
+    return ((k >> q) << (q + 1)) | lo;
+}
+
+// Sum of v over the block, in a fixed order (wave64 shuffles, then the waves
+// in index order).  Valid in thread 0.  `sh` holds >= blockDim.x/64 doubles.
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) s += sh[i];
+    }
+    return s;
+}
+
+}  // namespace gv

@@ -1,0 +1,171 @@
+// gv_internal.hpp -- host-side structures and kernel launcher declarations.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/gv.h"
+
+namespace gv {
+
+typedef uint64_t u64;
+
+constexpr int kMaxQubits = 34;
+constexpr int kPlainGrid = 1024;       // blocks of every reducing plain kernel
+constexpr int kPlainBlock = 256;
+constexpr int kMaxTileBits = 12;
+constexpr int kMaxPasses = 8;
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+inline size_t amp_bytes(gv_precision p) { return p == GV_C64 ? 8 : 16; }
+
+// ---------------------------------------------------------------- Hamiltonian
+struct QwcGroup {
+    u64 xmask = 0, ymask = 0, zmask = 0;  // per-qubit basis letters of the group
+    std::vector<int64_t> terms;            // indices into the off-diagonal arrays
+};
+
+}  // namespace gv
+
+struct gv_pauli_s {
+    int n = 0;
+    // Z-only terms after merging (identity included as z = 0)
+    std::vector<uint64_t> dz;
+    std::vector<double> dc;
+    // off-diagonal terms after merging
+    std::vector<uint64_t> ox, oz;
+    std::vector<double> oc;
+    std::vector<gv::QwcGroup> groups;
+    // device form (borrowed caller memory)
+    void *dev = nullptr;
+    size_t dev_bytes = 0;
+    double *diag = nullptr;         // 2^n doubles
+    uint64_t *dev_ox = nullptr;     // off-diagonal tables
+    uint64_t *dev_oz = nullptr;
+    double *dev_oc = nullptr;
+    bool prepared = false;
+};
+
+struct gv_state_s {
+    int n = 0;
+    gv_precision prec = GV_C64;
+    gv_engine engine = GV_ENGINE_FUSED;
+    void *amps = nullptr;
+    size_t amps_bytes = 0;
+    void *work = nullptr;
+    size_t work_bytes = 0;
+    hipStream_t stream = nullptr;
+    bool has_psi = false;
+};
+
+namespace gv {
+
+// ------------------------------------------------------------- error plumbing
+gv_status set_error(gv_status s, const char *fmt, ...);
+gv_status check_hip(hipError_t e, const char *what);
+
+// ------------------------------------------------------------------- planning
+struct PassPlan {
+    int8_t pos[kMaxTileBits];   // physical bit of tile bit j, ascending
+    uint32_t active;            // tile bits whose qubit gets its gate in this pass
+};
+
+struct TilePlan {
+    int K = 0;        // tile bits
+    int C = 0;        // contiguous low bits kept in every pass (coalescing)
+    int npass = 0;
+    PassPlan pass[kMaxPasses];
+};
+
+bool make_tile_plan(int n, int K, int C, TilePlan *out);
+
+// Diagonal-table chunks: bits [0,b1), [b1,b2), [b2,n)
+struct Chunks {
+    int b1, b2;
+    int size0, size1, size2;    // entries per table
+};
+Chunks make_chunks(int n);
+
+// Work-buffer layout for gv_energy_grad / gv_energy.
+struct WorkLayout {
+    size_t lam = 0;          // adjoint vector
+    size_t ckpt = 0;         // checkpoints, (rot_layers-1) vectors (CHECKPOINT)
+    size_t scratch = 0;      // one vector (CNOT gather)
+    size_t ry_tab = 0;       // per parameter: forward and backward (cos, sin) doubles
+    size_t dtab = 0;         // per rotation layer: forward + backward diagonal tables
+    size_t gtab = 0;         // product-state tables of the first layer
+    size_t part = 0;         // gradient partials: P rows x grid columns
+    size_t epart = 0;        // energy partials: 2 x grid
+    size_t total = 0;
+    int grid = 0;            // columns of the partial arrays
+    size_t dtab_stride = 0;  // bytes per layer of diagonal tables (fwd + bwd)
+};
+gv_status work_layout(const gv_ansatz &a, gv_precision prec, gv_engine eng, gv_grad_mode mode,
+                      WorkLayout *out);
+
+int rot_layers(const gv_ansatz &a);
+int64_t nparams(const gv_ansatz &a);
+
+// ------------------------------------------------------------------ launchers
+// All launchers enqueue on `s` and return the launch status.
+
+// plain engine (one kernel per gate), prec selects float / double amplitudes
+hipError_t plain_set_zero_state(int prec, void *psi, int n, hipStream_t s);
+hipError_t plain_ry(int prec, void *psi, int n, int q, const double *theta, int64_t p, int inv,
+                    hipStream_t s);
+hipError_t plain_rz(int prec, void *psi, int n, int q, const double *theta, int64_t p, int inv,
+                    hipStream_t s);
+hipError_t plain_cz(int prec, void *psi, int n, int a, int b, hipStream_t s);
+hipError_t plain_cnot(int prec, void *psi, int n, int ctl, int tgt, hipStream_t s);
+// adjoint step of a rotation gate: gradient partial row + inverse gate on phi and lam
+hipError_t plain_adj_ry(int prec, void *phi, void *lam, int n, int q, const double *theta,
+                        int64_t p, double *part_row, hipStream_t s);
+hipError_t plain_adj_rz(int prec, void *phi, void *lam, int n, int q, const double *theta,
+                        int64_t p, double *part_row, hipStream_t s);
+
+// Hamiltonian
+hipError_t fill_zero_f64(double *d, u64 count, hipStream_t s);
+hipError_t scatter_coeffs(double *h, const uint64_t *z, const double *c, int64_t m, hipStream_t s);
+hipError_t fwht_inplace(double *d, int n, hipStream_t s);
+// lam = D psi (lam may be null), energy partials (re, im) = sum conj(psi) D psi
+hipError_t energy_diag(int prec, const void *psi, const double *diag, void *lam, int n,
+                       double *epart, int grid, hipStream_t s);
+// lam += c P psi for every off-diagonal term, energy partials accumulated
+hipError_t energy_offdiag_terms(int prec, const void *psi, void *lam, int n, int64_t m,
+                                const uint64_t *ox, const uint64_t *oz, const double *oc,
+                                double *epart, int grid, hipStream_t s);
+// out[r] = sum_c part[r*cols + c] (masked rows -> 0), optionally scaled
+hipError_t reduce_rows(const double *part, int64_t rows, int cols, const uint8_t *mask,
+                       double *out, hipStream_t s);
+// energy_dev[0..1] = column sums of the 2 x grid energy partials
+hipError_t reduce_energy(const double *epart, int grid, double *energy, hipStream_t s);
+
+hipError_t copy_vector(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+// fused engine
+struct FusedTables {
+    const double *ry;    // [P][4]: fwd cos, fwd sin, bwd cos, bwd sin (of half angles)
+    void *dtab;          // per rotation layer diagonal tables
+    size_t dtab_stride;
+    void *gtab;          // first-layer product-state tables
+};
+hipError_t fused_build_tables(int prec, const gv_ansatz &a, const Chunks &ch, const double *theta,
+                              const FusedTables &t, hipStream_t s);
+hipError_t fused_init_state(int prec, void *psi, const gv_ansatz &a, const Chunks &ch,
+                            const FusedTables &t, hipStream_t s);
+hipError_t fused_forward_pass(int prec, void *psi, const gv_ansatz &a, const TilePlan &plan,
+                              int pass, int layer, int apply_diag, const Chunks &ch,
+                              const FusedTables &t, hipStream_t s);
+hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *lam,
+                               const gv_ansatz &a, const TilePlan &plan, int pass, int layer,
+                               int apply_diag, const Chunks &ch, const FusedTables &t,
+                               double *part, int grid, hipStream_t s);
+hipError_t cnot_ladder_gather(int prec, const void *src, void *dst, int n, int circular,
+                              int inverse, hipStream_t s);
+int fused_grid(int prec, const TilePlan &plan, int n);
+
+}  // namespace gv

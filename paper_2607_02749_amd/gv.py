@@ -1,0 +1,274 @@
+"""Python binding of ``libgv.so`` (the C ABI in ``include/gv.h``).
+
+Argument marshalling only: every step of the energy and gradient runs in the
+library's HIP kernels.  PyTorch supplies device memory (the library borrows
+it) and the current HIP stream.  If the library is missing this module raises
+instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgv.so")
+
+C64, C128 = 0, 1
+ENGINE_FUSED, ENGINE_PLAIN = 0, 1
+GRAD_UNCOMPUTE, GRAD_CHECKPOINT, GRAD_RECOMPUTE = 0, 1, 2
+ENT_NONE, ENT_CZ_LINEAR, ENT_CZ_CIRCULAR, ENT_CNOT_LINEAR, ENT_CNOT_CIRCULAR = 0, 1, 2, 3, 4
+
+_PREC = {"c64": C64, "complex64": C64, C64: C64, "c128": C128, "complex128": C128, C128: C128}
+_ENGINE = {"fused": ENGINE_FUSED, "plain": ENGINE_PLAIN, ENGINE_FUSED: ENGINE_FUSED,
+           ENGINE_PLAIN: ENGINE_PLAIN}
+_MODE = {"uncompute": GRAD_UNCOMPUTE, "checkpoint": GRAD_CHECKPOINT, "recompute": GRAD_RECOMPUTE,
+         GRAD_UNCOMPUTE: GRAD_UNCOMPUTE, GRAD_CHECKPOINT: GRAD_CHECKPOINT,
+         GRAD_RECOMPUTE: GRAD_RECOMPUTE}
+
+ALIGN = 256
+
+
+class GVError(RuntimeError):
+    pass
+
+
+class _Ansatz(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("layers", ctypes.c_int32), ("ent", ctypes.c_int32),
+                ("final_rotation", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises GVError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise GVError(f"{LIB_PATH} is missing: build it with `python -m paper_2607_02749_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    AP = ctypes.POINTER(_Ansatz)
+    L.gv_version.restype = ctypes.c_char_p
+    L.gv_last_error.restype = ctypes.c_char_p
+    L.gv_num_params.argtypes = [AP]
+    L.gv_num_params.restype = i64
+    L.gv_query_sizes.argtypes = [AP, i32, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    L.gv_state_create.argtypes = [i32, i32, i32, vp, sz, vp, sz, vp, ctypes.POINTER(vp)]
+    L.gv_state_destroy.argtypes = [vp]
+    L.gv_state_set_stream.argtypes = [vp, vp]
+    L.gv_apply_ansatz.argtypes = [vp, vp, AP]
+    L.gv_pauli_sum_create.argtypes = [i32, i64, vp, vp, vp, ctypes.POINTER(vp)]
+    L.gv_pauli_sum_destroy.argtypes = [vp]
+    L.gv_pauli_sum_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                    ctypes.POINTER(i64)]
+    L.gv_pauli_sum_device_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.gv_pauli_sum_prepare.argtypes = [vp, vp, vp, sz]
+    L.gv_energy.argtypes = [vp, vp, vp]
+    L.gv_energy_grad.argtypes = [vp, vp, vp, AP, vp, i32, vp, vp]
+    for name in ("gv_query_sizes", "gv_state_create", "gv_state_destroy", "gv_state_set_stream",
+                 "gv_apply_ansatz", "gv_pauli_sum_create", "gv_pauli_sum_destroy",
+                 "gv_pauli_sum_info", "gv_pauli_sum_device_bytes", "gv_pauli_sum_prepare",
+                 "gv_energy", "gv_energy_grad"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise GVError(f"{what} failed (status {status}): {lib().gv_last_error().decode()}")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _aligned_bytes(nbytes: int, device) -> Tuple[torch.Tensor, torch.Tensor]:
+    """A device byte buffer of at least nbytes whose start is ALIGN-aligned;
+    returns (owner, aligned view)."""
+    nbytes = max(int(nbytes), 1)
+    owner = torch.empty(nbytes + ALIGN, dtype=torch.uint8, device=device)
+    off = (-owner.data_ptr()) % ALIGN
+    return owner, owner[off:off + nbytes]
+
+
+@dataclass(frozen=True)
+class Ansatz:
+    """Hardware-efficient ansatz (Sec. IV-B): ``layers`` x [RY all, RZ all,
+    entangler], plus one [RY all, RZ all] layer when final_rotation=1."""
+    n: int
+    layers: int
+    ent: int = ENT_CZ_LINEAR
+    final_rotation: int = 0
+
+    def c(self) -> _Ansatz:
+        return _Ansatz(self.n, self.layers, self.ent, self.final_rotation)
+
+    @property
+    def num_params(self) -> int:
+        return 2 * self.n * (self.layers + self.final_rotation)
+
+
+def query_sizes(ansatz: Ansatz, precision="c64", engine="fused", mode="uncompute") -> Tuple[int, int]:
+    a = ansatz.c()
+    sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().gv_query_sizes(ctypes.byref(a), _PREC[precision], _ENGINE[engine], _MODE[mode],
+                                ctypes.byref(sb), ctypes.byref(wb)), "gv_query_sizes")
+    return sb.value, wb.value
+
+
+class State:
+    """A 2^n-amplitude state in caller (torch) memory plus the workspace the
+    gradient sweep needs for ``ansatz`` and ``mode``."""
+
+    def __init__(self, n: int, precision="c64", engine="fused", ansatz: Optional[Ansatz] = None,
+                 mode="uncompute", device="cuda", work_bytes: Optional[int] = None):
+        self.n = n
+        self.precision = _PREC[precision]
+        self.engine = _ENGINE[engine]
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        an = ansatz or Ansatz(n, 0)
+        sb, wb = query_sizes(an, self.precision, self.engine, mode)
+        if work_bytes is not None:
+            wb = work_bytes
+        self._amps_owner, self.amps = _aligned_bytes(sb, self.device)
+        self._work_owner, self.work = _aligned_bytes(wb, self.device)
+        self.work_bytes = wb
+        h = ctypes.c_void_p()
+        _check(lib().gv_state_create(n, self.precision, self.engine, _ptr(self.amps), sb,
+                                     _ptr(self.work), wb, _stream_ptr(self.device),
+                                     ctypes.byref(h)), "gv_state_create")
+        self.handle = h
+
+    def _sync_stream(self):
+        lib().gv_state_set_stream(self.handle, _stream_ptr(self.device))
+
+    def amplitudes(self) -> torch.Tensor:
+        """The amplitudes as a complex tensor view of the state buffer."""
+        real = torch.float32 if self.precision == C64 else torch.float64
+        return torch.view_as_complex(self.amps.view(real).view(-1, 2))
+
+    def apply_ansatz(self, theta: torch.Tensor, ansatz: Ansatz):
+        assert theta.dtype == torch.float64 and theta.is_contiguous() and theta.device == self.device
+        self._sync_stream()
+        a = ansatz.c()
+        _check(lib().gv_apply_ansatz(self.handle, _ptr(theta), ctypes.byref(a)), "gv_apply_ansatz")
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.gv_state_destroy(h)
+            self.handle = None
+
+
+class PauliSum:
+    """H = sum_k c_k P(x_k, z_k) (Eq. 6); masks are uint64 bit sets."""
+
+    def __init__(self, n: int, x: Sequence[int], z: Sequence[int], c: Sequence[float]):
+        self.n = n
+        self._x = np.ascontiguousarray(x, dtype=np.uint64)
+        self._z = np.ascontiguousarray(z, dtype=np.uint64)
+        self._c = np.ascontiguousarray(c, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(lib().gv_pauli_sum_create(n, len(self._c), self._x.ctypes.data, self._z.ctypes.data,
+                                         self._c.ctypes.data, ctypes.byref(h)), "gv_pauli_sum_create")
+        self.handle = h
+        self.device_buffer = None
+
+    def info(self) -> Tuple[int, int, int]:
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().gv_pauli_sum_info(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+               "gv_pauli_sum_info")
+        return a.value, b.value, c.value
+
+    def prepare(self, state: State):
+        nb = ctypes.c_size_t()
+        _check(lib().gv_pauli_sum_device_bytes(self.handle, ctypes.byref(nb)), "device_bytes")
+        self._owner, self.device_buffer = _aligned_bytes(nb.value, state.device)
+        state._sync_stream()
+        _check(lib().gv_pauli_sum_prepare(self.handle, state.handle, _ptr(self.device_buffer),
+                                          nb.value), "gv_pauli_sum_prepare")
+        return self
+
+    def diagonal(self) -> torch.Tensor:
+        """The FP64 diagonal of the Z-only part (valid after prepare)."""
+        return self.device_buffer[: 8 << self.n].view(torch.float64)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.gv_pauli_sum_destroy(h)
+            self.handle = None
+
+
+def energy(state: State, h: PauliSum) -> torch.Tensor:
+    """<psi|H|psi> of the state's current psi as float64[2] (re, im)."""
+    out = torch.empty(2, dtype=torch.float64, device=state.device)
+    state._sync_stream()
+    _check(lib().gv_energy(state.handle, h.handle, _ptr(out)), "gv_energy")
+    return out
+
+
+def energy_grad(state: State, h: PauliSum, theta: torch.Tensor, ansatz: Ansatz,
+                mask: Optional[torch.Tensor] = None, mode="uncompute",
+                out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None):
+    """Energy (float64[2]) and gradient (float64[P]) at theta."""
+    assert theta.dtype == torch.float64 and theta.is_contiguous() and theta.device == state.device
+    if mask is not None:
+        assert mask.dtype == torch.uint8 and mask.numel() == ansatz.num_params
+    if out is None:
+        e = torch.empty(2, dtype=torch.float64, device=state.device)
+        g = torch.empty(ansatz.num_params, dtype=torch.float64, device=state.device)
+    else:
+        e, g = out
+    state._sync_stream()
+    a = ansatz.c()
+    _check(lib().gv_energy_grad(state.handle, h.handle, _ptr(theta), ctypes.byref(a), _ptr(mask),
+                                _MODE[mode], _ptr(e), _ptr(g)), "gv_energy_grad")
+    return e, g
+
+
+class GVEnergy(torch.autograd.Function):
+    """E(theta) = <psi(theta)|H|psi(theta)> with its gradient from the
+    library's reverse sweep.  forward runs energy and gradient in one call
+    and keeps the gradient; backward scales it by the incoming gradient."""
+
+    @staticmethod
+    def forward(ctx, theta, state: State, h: PauliSum, ansatz: Ansatz,
+                mask: Optional[torch.Tensor] = None, mode="uncompute"):
+        e, g = energy_grad(state, h, theta.detach().contiguous(), ansatz, mask, mode)
+        ctx.save_for_backward(g)
+        return e[0].clone()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return grad_out * g, None, None, None, None, None
+
+
+def param_mask(n: int, layers: int, qubit_mask: int, final_rotation: int = 0,
+               device="cuda") -> torch.Tensor:
+    """uint8 mask of the RY and RZ parameters of the qubits in qubit_mask, in
+    every layer (the block parameter set of Eq. 11)."""
+    p = 2 * n * (layers + final_rotation)
+    m = torch.zeros(p, dtype=torch.uint8)
+    for l in range(layers + final_rotation):
+        for g in range(2):
+            for q in range(n):
+                if (qubit_mask >> q) & 1:
+                    m[l * 2 * n + g * n + q] = 1
+    return m.to(device)

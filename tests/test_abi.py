@@ -1,0 +1,103 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/gv.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2607_02749_amd import gv
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "gv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gv_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("gv_state_create", "gv_apply_ansatz", "gv_energy", "gv_energy_grad",
+                     "gv_pauli_sum_create", "gv_pauli_sum_prepare", "gv_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = gv.lib()
+    missing = [name for name in declared_functions() if not hasattr(L, name)]
+    assert not missing, missing
+
+
+def test_version_and_num_params():
+    L = gv.lib()
+    assert b"gv" in L.gv_version()
+    a = gv.Ansatz(28, 6).c()
+    assert L.gv_num_params(ctypes.byref(a)) == 336
+    a = gv.Ansatz(8, 4, gv.ENT_CNOT_CIRCULAR, 1).c()
+    assert L.gv_num_params(ctypes.byref(a)) == 2 * 8 * 5   # Eq. 8
+    bad = gv.Ansatz(0, 1).c()
+    assert L.gv_num_params(ctypes.byref(bad)) == -1
+
+
+def test_query_sizes():
+    sb, wb = gv.query_sizes(gv.Ansatz(28, 6), "c64", "fused", "uncompute")
+    assert sb == 8 << 28
+    assert wb >= 8 << 28                       # holds the adjoint vector
+    _, wck = gv.query_sizes(gv.Ansatz(28, 6), "c64", "fused", "checkpoint")
+    assert wck >= wb + 5 * (8 << 28)           # five inner layer boundaries
+    sb128, _ = gv.query_sizes(gv.Ansatz(10, 2), "c128", "plain")
+    assert sb128 == 16 << 10
+    with pytest.raises(gv.GVError):
+        gv.query_sizes(gv.Ansatz(35, 1))
+    with pytest.raises(gv.GVError):
+        gv.query_sizes(gv.Ansatz(10, 1, ent=9))
+
+
+def test_state_create_validation():
+    L = gv.lib()
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: creation only records it
+    assert L.gv_state_create(10, 0, 0, None, 1 << 20, None, 0, None, ctypes.byref(h)) == 1
+    assert L.gv_state_create(10, 0, 0, fake, 100, None, 0, None, ctypes.byref(h)) == 2
+    assert L.gv_state_create(0, 0, 0, fake, 1 << 20, None, 0, None, ctypes.byref(h)) == 1
+    assert L.gv_state_create(10, 7, 0, fake, 1 << 20, None, 0, None, ctypes.byref(h)) == 1
+    misaligned = ctypes.c_void_p((1 << 20) + 8)
+    assert L.gv_state_create(10, 0, 0, misaligned, 1 << 20, None, 0, None, ctypes.byref(h)) == 1
+    assert b"aligned" in L.gv_last_error()
+    assert L.gv_state_create(10, 0, 0, fake, 1 << 20, None, 0, None, ctypes.byref(h)) == 0
+    # calls that validate before enqueueing anything
+    a = gv.Ansatz(11, 1).c()
+    assert L.gv_apply_ansatz(h, fake, ctypes.byref(a)) == 4       # n mismatch
+    a = gv.Ansatz(10, 1).c()
+    assert L.gv_apply_ansatz(h, None, ctypes.byref(a)) == 1       # NULL params
+    e = ctypes.c_void_p(2 << 20)
+    assert L.gv_energy(h, None, e) == 1
+    assert L.gv_state_destroy(h) == 0
+
+
+def test_pauli_sum_merge_and_groups():
+    n = 4
+    x = [0, 0, 0b0011, 0b0011, 0b0100, 0b1000, 0]
+    z = [0b0001, 0b0001, 0, 0b0011, 0b0100, 0, 0]
+    c = [0.5, 0.25, 1.0, 2.0, 3.0, 0.0, 1.5]
+    h = gv.PauliSum(n, x, z, c)
+    nd, no, ng = h.info()
+    assert nd == 2          # Z0 merged (0.75) and the identity
+    assert no == 3          # XX on (0,1), YY on (0,1), Y on 2 (X on 3 has c = 0)
+    assert ng == 2          # {XX, Y2} commute qubit-wise, YY needs its own group
+    with pytest.raises(gv.GVError):
+        gv.PauliSum(n, [0], [1 << 4], [1.0])          # mask bit >= n
+    with pytest.raises(gv.GVError):
+        gv.PauliSum(n, [0], [1], [float("nan")])
+
+
+def test_pauli_sum_groups_of_generated_workload():
+    from paper_2607_02749_amd import synth
+    w = synth.make_instance(32, 1, 10, 2, 32, seed=0, m_off=2000,
+                            off_types=("XX", "YY", "XZ", "ZY"), off_groups=64)
+    h = gv.PauliSum(32, w.x, w.z, w.c)
+    nd, no, ng = h.info()
+    assert no == 2000 and ng <= 64
