@@ -168,6 +168,31 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *params_dev,
                          const gv_ansatz *ansatz, const uint8_t *grad_mask_dev,
                          gv_grad_mode mode, double *energy_dev, double *grad_dev);
 
+/* ------------------------------------------------------------------------
+ * Per-kernel-class timing.  While enabled, every launch of the state's
+ * compute calls is bracketed by HIP events recorded on the state's stream,
+ * and the algorithmic bytes of the launch (the reads and writes the step
+ * must make, e.g. read + write of psi and lambda for a reverse pass) are
+ * recorded with it.  Events are host-side objects created on demand; no
+ * device memory is allocated.  gv_profile_read waits for the recorded events.
+ */
+typedef enum {
+    GV_PROF_FORWARD_PASS = 0,   /* fused ansatz tile pass */
+    GV_PROF_BACKWARD_PASS = 1,  /* fused reverse-sweep tile pass */
+    GV_PROF_ENERGY = 2,         /* diagonal energy and lambda = H psi */
+    GV_PROF_INIT = 3,           /* first-layer product state */
+    GV_PROF_PLAIN_GATE = 4,     /* plain engine gate or reverse step */
+    GV_PROF_OTHER = 5,          /* tables, reductions, copies, gathers */
+    GV_PROF_KINDS = 6
+} gv_prof_kind;
+
+gv_status gv_profile_enable(gv_state st, int32_t enable);
+gv_status gv_profile_reset(gv_state st);
+/* launches, total milliseconds and total algorithmic bytes of one kind since
+ * the last reset.  Any output pointer may be NULL. */
+gv_status gv_profile_read(gv_state st, int32_t kind, int64_t *launches, double *ms,
+                          double *bytes);
+
 #ifdef __cplusplus
 }
 #endif

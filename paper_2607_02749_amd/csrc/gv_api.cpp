@@ -36,6 +36,40 @@ gv_status check_hip(hipError_t e, const char *what)
     return set_error(GV_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+static hipEvent_t take_event(gv_state_s *st)
+{
+    if (!st->event_pool.empty()) {
+        hipEvent_t e = st->event_pool.back();
+        st->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+ProfScope::ProfScope(gv_state_s *st, int kind, double bytes) : st_(st), kind_(kind), bytes_(bytes)
+{
+    if (!st_ || !st_->profiling) return;
+    start_ = take_event(st_);
+    if (start_ && hipEventRecord(start_, st_->stream) != hipSuccess) {
+        st_->event_pool.push_back(start_);
+        start_ = nullptr;
+    }
+}
+
+ProfScope::~ProfScope()
+{
+    if (!start_) return;
+    hipEvent_t stop = take_event(st_);
+    if (!stop || hipEventRecord(stop, st_->stream) != hipSuccess) {
+        st_->event_pool.push_back(start_);
+        if (stop) st_->event_pool.push_back(stop);
+        return;
+    }
+    st_->records.push_back({kind_, start_, stop, bytes_});
+}
+
 int rot_layers(const gv_ansatz &a) { return a.layers + a.final_rotation; }
 int64_t nparams(const gv_ansatz &a) { return 2ll * a.n * rot_layers(a); }
 
@@ -193,8 +227,10 @@ static gv_status plain_forward(gv_state st, const gv_ansatz &an, const double *t
     hipStream_t s = st->stream;
     if (gv_status e = check_hip(plain_set_zero_state(prec, st->amps, an.n, s), "zero state"))
         return e;
+    const double A = (double)(1ull << an.n), sb = (double)amp_bytes(st->prec);
     for (const Gate &g : gate_list(an)) {
         hipError_t e;
+        ProfScope ps(st, GV_PROF_PLAIN_GATE, g.kind == 2 ? 0.5 * A * sb : (g.kind == 3 ? A * sb : 2 * A * sb));
         switch (g.kind) {
         case 0: e = plain_ry(prec, st->amps, an.n, g.a, theta, g.p, 0, s); break;
         case 1: e = plain_rz(prec, st->amps, an.n, g.a, theta, g.p, 0, s); break;
@@ -217,7 +253,9 @@ static gv_status fused_layer(gv_state st, const gv_ansatz &an, const FusedCtx &c
                              void *psi, void *scratch)
 {
     hipStream_t s = st->stream;
+    const double vb = (double)((size_t)1 << an.n) * amp_bytes(st->prec);
     for (int p = 0; p < c.plan.npass; ++p) {
+        ProfScope ps(st, GV_PROF_FORWARD_PASS, 2 * vb);
         hipError_t e = fused_forward_pass(st->prec, psi, an, c.plan, p, l,
                                           p == c.plan.npass - 1, c.ch, c.tabs, s);
         if (gv_status r = check_hip(e, "forward pass")) return r;
@@ -225,6 +263,7 @@ static gv_status fused_layer(gv_state st, const gv_ansatz &an, const FusedCtx &c
     const bool cnot = an.ent == GV_ENT_CNOT_LINEAR || an.ent == GV_ENT_CNOT_CIRCULAR;
     if (cnot && l < an.layers) {
         const size_t bytes = ((size_t)1 << an.n) * amp_bytes(st->prec);
+        ProfScope ps(st, GV_PROF_OTHER, 4.0 * bytes);
         if (gv_status r = check_hip(cnot_ladder_gather(st->prec, psi, scratch, an.n,
                                                        an.ent == GV_ENT_CNOT_CIRCULAR, 0, s),
                                     "cnot gather"))
@@ -238,11 +277,15 @@ static gv_status fused_first_layer(gv_state st, const gv_ansatz &an, const Fused
                                    void *psi, void *scratch)
 {
     hipStream_t s = st->stream;
-    if (gv_status r = check_hip(fused_init_state(st->prec, psi, an, c.ch, c.tabs, s), "init"))
-        return r;
+    {
+        ProfScope ps(st, GV_PROF_INIT, (double)((size_t)1 << an.n) * amp_bytes(st->prec));
+        if (gv_status r = check_hip(fused_init_state(st->prec, psi, an, c.ch, c.tabs, s), "init"))
+            return r;
+    }
     const bool cnot = an.ent == GV_ENT_CNOT_LINEAR || an.ent == GV_ENT_CNOT_CIRCULAR;
     if (cnot && an.layers > 0) {
         const size_t bytes = ((size_t)1 << an.n) * amp_bytes(st->prec);
+        ProfScope ps(st, GV_PROF_OTHER, 4.0 * bytes);
         if (gv_status r = check_hip(cnot_ladder_gather(st->prec, psi, scratch, an.n,
                                                        an.ent == GV_ENT_CNOT_CIRCULAR, 0, s),
                                     "cnot gather"))
@@ -267,6 +310,7 @@ static gv_status fused_setup(gv_state st, const gv_ansatz &an, const double *the
     c->tabs.dtab = w + c->w.dtab;
     c->tabs.dtab_stride = c->w.dtab_stride;
     c->tabs.gtab = w + c->w.gtab;
+    ProfScope ps(st, GV_PROF_OTHER, 0.0);
     return check_hip(fused_build_tables(st->prec, an, c->ch, theta, c->tabs, st->stream), "tables");
 }
 
@@ -276,16 +320,20 @@ static gv_status fused_forward(gv_state st, const gv_ansatz &an, const FusedCtx 
 {
     char *scratch = (char *)st->work + c.w.scratch;
     if (gv_status r = fused_first_layer(st, an, c, psi, scratch)) return r;
-    if (ckpt && upto > 0)
+    if (ckpt && upto > 0) {
+        ProfScope ps(st, GV_PROF_OTHER, 2.0 * vec_bytes);
         if (gv_status r = check_hip(copy_vector(ckpt, psi, vec_bytes, st->stream), "checkpoint"))
             return r;
+    }
     for (int l = 1; l <= upto; ++l) {
         if (gv_status r = fused_layer(st, an, c, l, psi, scratch)) return r;
-        if (ckpt && l < upto)
+        if (ckpt && l < upto) {
+            ProfScope ps(st, GV_PROF_OTHER, 2.0 * vec_bytes);
             if (gv_status r = check_hip(copy_vector(ckpt + (size_t)l * vec_bytes, psi, vec_bytes,
                                                     st->stream),
                                         "checkpoint"))
                 return r;
+        }
     }
     return GV_OK;
 }
@@ -294,10 +342,15 @@ static gv_status energy_chain(gv_state st, gv_pauli_sum h, void *lam, double *ep
                               double *energy)
 {
     hipStream_t s = st->stream;
-    if (gv_status r = check_hip(energy_diag(st->prec, st->amps, h->diag, lam, st->n, epart,
-                                            kEnergyGrid, s),
-                                "energy diag"))
-        return r;
+    const double vb = (double)((size_t)1 << st->n) * amp_bytes(st->prec);
+    {
+        ProfScope ps(st, GV_PROF_ENERGY, (lam ? 2 * vb : vb) + (double)((size_t)1 << st->n) * 8);
+        if (gv_status r = check_hip(energy_diag(st->prec, st->amps, h->diag, lam, st->n, epart,
+                                                kEnergyGrid, s),
+                                    "energy diag"))
+            return r;
+    }
+    ProfScope ps(st, GV_PROF_OTHER, (double)h->oc.size() * (lam ? 3 : 1) * vb);
     if (!h->oc.empty())
         if (gv_status r = check_hip(energy_offdiag_terms(st->prec, st->amps, lam, st->n,
                                                          (int64_t)h->oc.size(), h->ox.data(),
@@ -371,6 +424,10 @@ gv_status gv_state_create(int32_t n, gv_precision prec, gv_engine engine, void *
 
 gv_status gv_state_destroy(gv_state st)
 {
+    if (st) {
+        gv_profile_reset(st);
+        for (hipEvent_t e : st->event_pool) (void)hipEventDestroy(e);
+    }
     delete st;
     return GV_OK;
 }
@@ -598,6 +655,9 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
         for (size_t k = g.size(); k-- > 0;) {
             const Gate &G = g[k];
             hipError_t e;
+            const double A = (double)(1ull << n), sb = (double)amp_bytes(st->prec);
+            ProfScope ps(st, GV_PROF_PLAIN_GATE,
+                         G.kind == 2 ? A * sb : (G.kind == 3 ? 2 * A * sb : 4 * A * sb));
             switch (G.kind) {
             case 0:
                 e = plain_adj_ry(st->prec, st->amps, lam, n, G.a, theta, G.p, part + G.p * L.grid, s);
@@ -617,6 +677,7 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
             if (gv_status r = check_hip(e, "reverse step")) return r;
         }
         st->has_psi = false;
+        ProfScope ps(st, GV_PROF_OTHER, 0.0);
         return check_hip(reduce_rows(part, P, L.grid, mask, grad, s), "grad reduce");
     }
 
@@ -651,6 +712,7 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
             }
         }
         if (cnot && l < a->layers) {
+            ProfScope ps(st, GV_PROF_OTHER, 8.0 * vb);
             const int circ = a->ent == GV_ENT_CNOT_CIRCULAR;
             hipError_t e = cnot_ladder_gather(st->prec, phi_src, scratch, n, circ, 1, s);
             if (e == hipSuccess) e = copy_vector(psi, scratch, vb, s);
@@ -660,13 +722,55 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
             phi_src = psi;
         }
         for (int p = 0; p < c.plan.npass; ++p) {
+            ProfScope ps(st, GV_PROF_BACKWARD_PASS, 4.0 * vb);
             hipError_t e = fused_backward_pass(st->prec, p == 0 ? phi_src : psi, psi, lam, *a,
                                                c.plan, p, l, p == 0, c.ch, c.tabs, part, c.w.grid, s);
             if (gv_status r = check_hip(e, "backward pass")) return r;
         }
     }
     st->has_psi = false;
+    ProfScope ps(st, GV_PROF_OTHER, 0.0);
     return check_hip(reduce_rows(part, P, c.w.grid, mask, grad, s), "grad reduce");
+}
+
+gv_status gv_profile_enable(gv_state st, int32_t enable)
+{
+    if (!st) return set_error(GV_EINVAL, "state is NULL");
+    st->profiling = enable != 0;
+    return GV_OK;
+}
+
+gv_status gv_profile_reset(gv_state st)
+{
+    if (!st) return set_error(GV_EINVAL, "state is NULL");
+    for (const gv_prof_record &r : st->records) {
+        st->event_pool.push_back(r.start);
+        st->event_pool.push_back(r.stop);
+    }
+    st->records.clear();
+    return GV_OK;
+}
+
+gv_status gv_profile_read(gv_state st, int32_t kind, int64_t *launches, double *ms, double *bytes)
+{
+    if (!st) return set_error(GV_EINVAL, "state is NULL");
+    if (kind < 0 || kind >= GV_PROF_KINDS) return set_error(GV_EINVAL, "kind %d", kind);
+    int64_t cnt = 0;
+    double tot = 0.0, b = 0.0;
+    for (const gv_prof_record &r : st->records) {
+        if (r.kind != kind) continue;
+        if (gv_status e = check_hip(hipEventSynchronize(r.stop), "event sync")) return e;
+        float t = 0.0f;
+        if (gv_status e = check_hip(hipEventElapsedTime(&t, r.start, r.stop), "event time"))
+            return e;
+        ++cnt;
+        tot += t;
+        b += r.bytes;
+    }
+    if (launches) *launches = cnt;
+    if (ms) *ms = tot;
+    if (bytes) *bytes = b;
+    return GV_OK;
 }
 
 }  // extern "C"

@@ -50,6 +50,12 @@ struct gv_pauli_s {
     bool prepared = false;
 };
 
+struct gv_prof_record {
+    int kind;
+    hipEvent_t start, stop;
+    double bytes;
+};
+
 struct gv_state_s {
     int n = 0;
     gv_precision prec = GV_C64;
@@ -60,6 +66,10 @@ struct gv_state_s {
     size_t work_bytes = 0;
     hipStream_t stream = nullptr;
     bool has_psi = false;
+    // per-kernel-class timing (gv_profile_*)
+    bool profiling = false;
+    std::vector<hipEvent_t> event_pool;
+    std::vector<gv_prof_record> records;
 };
 
 namespace gv {
@@ -67,6 +77,19 @@ namespace gv {
 // ------------------------------------------------------------- error plumbing
 gv_status set_error(gv_status s, const char *fmt, ...);
 gv_status check_hip(hipError_t e, const char *what);
+
+// Brackets the launches made during its lifetime with events when the state
+// is profiling.
+class ProfScope {
+public:
+    ProfScope(gv_state_s *st, int kind, double bytes);
+    ~ProfScope();
+private:
+    gv_state_s *st_;
+    int kind_;
+    double bytes_;
+    hipEvent_t start_ = nullptr;
+};
 
 // ------------------------------------------------------------------- planning
 struct PassPlan {

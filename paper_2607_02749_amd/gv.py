@@ -72,7 +72,11 @@ def lib():
     L.gv_pauli_sum_prepare.argtypes = [vp, vp, vp, sz]
     L.gv_energy.argtypes = [vp, vp, vp]
     L.gv_energy_grad.argtypes = [vp, vp, vp, AP, vp, i32, vp, vp]
-    for name in ("gv_query_sizes", "gv_state_create", "gv_state_destroy", "gv_state_set_stream",
+    L.gv_profile_enable.argtypes = [vp, i32]
+    L.gv_profile_reset.argtypes = [vp]
+    L.gv_profile_read.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]
+    for name in ("gv_profile_enable", "gv_profile_reset", "gv_profile_read","gv_query_sizes", "gv_state_create", "gv_state_destroy", "gv_state_set_stream",
                  "gv_apply_ansatz", "gv_pauli_sum_create", "gv_pauli_sum_destroy",
                  "gv_pauli_sum_info", "gv_pauli_sum_device_bytes", "gv_pauli_sum_prepare",
                  "gv_energy", "gv_energy_grad"):
@@ -167,6 +171,26 @@ class State:
         self._sync_stream()
         a = ansatz.c()
         _check(lib().gv_apply_ansatz(self.handle, _ptr(theta), ctypes.byref(a)), "gv_apply_ansatz")
+
+    # per-kernel-class timing (HIP events on the state's stream)
+    PROF_KINDS = {"forward_pass": 0, "backward_pass": 1, "energy": 2, "init": 3,
+                  "plain_gate": 4, "other": 5}
+
+    def profile(self, enable: bool = True):
+        _check(lib().gv_profile_enable(self.handle, int(enable)), "gv_profile_enable")
+
+    def profile_reset(self):
+        _check(lib().gv_profile_reset(self.handle), "gv_profile_reset")
+
+    def profile_read(self) -> dict:
+        """{kind: (launches, total ms, total algorithmic bytes)}"""
+        out = {}
+        for name, k in self.PROF_KINDS.items():
+            n, ms, b = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+            _check(lib().gv_profile_read(self.handle, k, ctypes.byref(n), ctypes.byref(ms),
+                                         ctypes.byref(b)), "gv_profile_read")
+            out[name] = (n.value, ms.value, b.value)
+        return out
 
     def __del__(self):
         h = getattr(self, "handle", None)
