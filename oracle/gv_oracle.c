@@ -41,6 +41,9 @@
 
 typedef double complex cplx;
 
+/* loops shorter than this run on one thread (thread start-up would dominate) */
+#define OMP_MIN 16384
+
 enum { G_RY = 0, G_RZ = 1, G_CZ = 2, G_CNOT = 3 };
 enum { ENT_NONE = 0, ENT_CZ_LINEAR = 1, ENT_CZ_CIRCULAR = 2,
        ENT_CNOT_LINEAR = 3, ENT_CNOT_CIRCULAR = 4 };
@@ -120,7 +123,7 @@ static void apply_ry(int n, int q, double t, cplx *psi)
 {
     const double c = cos(0.5 * t), s = sin(0.5 * t);
     const uint64_t half = 1ULL << (n - 1), bit = 1ULL << q;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (half > OMP_MIN)
     for (int64_t k = 0; k < (int64_t)half; ++k) {
         uint64_t i = insert0((uint64_t)k, q), j = i | bit;
         cplx a = psi[i], b = psi[j];
@@ -133,7 +136,7 @@ static void apply_rz(int n, int q, double t, cplx *psi)
 {
     const cplx e0 = cexp(-0.5 * I * t), e1 = cexp(0.5 * I * t);
     const uint64_t half = 1ULL << (n - 1), bit = 1ULL << q;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (half > OMP_MIN)
     for (int64_t k = 0; k < (int64_t)half; ++k) {
         uint64_t i = insert0((uint64_t)k, q), j = i | bit;
         psi[i] *= e0;
@@ -144,7 +147,7 @@ static void apply_rz(int n, int q, double t, cplx *psi)
 static void apply_cz(int n, int a, int b, cplx *psi)
 {
     const uint64_t dim = 1ULL << n, m = (1ULL << a) | (1ULL << b);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (dim > OMP_MIN)
     for (int64_t i = 0; i < (int64_t)dim; ++i)
         if (((uint64_t)i & m) == m) psi[i] = -psi[i];
 }
@@ -152,7 +155,7 @@ static void apply_cz(int n, int a, int b, cplx *psi)
 static void apply_cnot(int n, int ctl, int tgt, cplx *psi)
 {
     const uint64_t half = 1ULL << (n - 1), cb = 1ULL << ctl, tb = 1ULL << tgt;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (half > OMP_MIN)
     for (int64_t k = 0; k < (int64_t)half; ++k) {
         uint64_t i = insert0((uint64_t)k, tgt);   /* target bit 0 */
         if (i & cb) {
@@ -182,7 +185,7 @@ static double im_expect_y(int n, int q, const cplx *lam, const cplx *phi)
 {
     const uint64_t half = 1ULL << (n - 1), bit = 1ULL << q;
     double acc = 0.0;
-#pragma omp parallel for schedule(static) reduction(+:acc)
+#pragma omp parallel for schedule(static) reduction(+:acc) if (half > OMP_MIN)
     for (int64_t k = 0; k < (int64_t)half; ++k) {
         uint64_t i = insert0((uint64_t)k, q), j = i | bit;
         /* (Y phi)_i = -i phi_j, (Y phi)_j = +i phi_i */
@@ -197,7 +200,7 @@ static double im_expect_z(int n, int q, const cplx *lam, const cplx *phi)
 {
     const uint64_t dim = 1ULL << n, bit = 1ULL << q;
     double acc = 0.0;
-#pragma omp parallel for schedule(static) reduction(+:acc)
+#pragma omp parallel for schedule(static) reduction(+:acc) if (dim > OMP_MIN)
     for (int64_t i = 0; i < (int64_t)dim; ++i) {
         double s = ((uint64_t)i & bit) ? -1.0 : 1.0;
         acc += s * cimag(conj(lam[i]) * phi[i]);
@@ -262,7 +265,7 @@ void gvo_diag(int n, int64_t m, const uint64_t *x, const uint64_t *z,
               const double *c, double *d)
 {
     const uint64_t dim = 1ULL << n;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (dim > OMP_MIN)
     for (int64_t i = 0; i < (int64_t)dim; ++i) {
         double acc = 0.0;
         for (int64_t k = 0; k < m; ++k) {
@@ -295,7 +298,7 @@ void gvo_apply_h(int n, int64_t m, const uint64_t *x, const uint64_t *z,
     const cplx *psi = (const cplx *)psi_in;
     cplx *out = (cplx *)out_;
     static const double complex ipow[4] = { 1.0, I, -1.0, -I };
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (dim > OMP_MIN)
     for (int64_t i = 0; i < (int64_t)dim; ++i) {
         cplx acc = d ? d[i] * psi[i] : 0.0;
         for (int64_t k = 0; k < m; ++k) {
@@ -315,7 +318,7 @@ void gvo_inner(int n, const double *a_, const double *b_, double *re, double *im
     const uint64_t dim = 1ULL << n;
     const cplx *a = (const cplx *)a_, *b = (const cplx *)b_;
     double sr = 0.0, si = 0.0;
-#pragma omp parallel for schedule(static) reduction(+:sr, si)
+#pragma omp parallel for schedule(static) reduction(+:sr, si) if (dim > OMP_MIN)
     for (int64_t i = 0; i < (int64_t)dim; ++i) {
         cplx v = conj(a[i]) * b[i];
         sr += creal(v);

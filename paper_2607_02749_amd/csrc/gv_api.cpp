@@ -75,7 +75,8 @@ int64_t nparams(const gv_ansatz &a) { return 2ll * a.n * rot_layers(a); }
 
 // Tile passes of one layer: pass 0 takes bits 0..K-1; later passes keep the C
 // low bits (for contiguous runs) and take the next K-C unprocessed bits,
-// topping up with already-processed bits so every tile has K bits.
+// topping up with the already-processed bits just below them so every tile
+// has K bits and the tile's top bits stay at consecutive positions.
 bool make_tile_plan(int n, int K, int C, TilePlan *out)
 {
     if (K < 1 || K > kMaxTileBits || K > n || C < 0 || C > K) return false;
@@ -95,7 +96,7 @@ bool make_tile_plan(int n, int K, int C, TilePlan *out)
         std::vector<int> bits;
         for (int j = 0; j < C; ++j) bits.push_back(j);
         const int fill = K - C - m;
-        for (int j = 0; j < fill; ++j) bits.push_back(C + j);   // C + fill <= next
+        for (int j = 0; j < fill; ++j) bits.push_back(next - fill + j);  // next - fill >= C
         for (int j = 0; j < m; ++j) bits.push_back(next + j);
         std::sort(bits.begin(), bits.end());
         PassPlan &pp = p.pass[p.npass++];
@@ -154,6 +155,8 @@ gv_status work_layout(const gv_ansatz &a, gv_precision prec, gv_engine eng, gv_g
         off += w.dtab_stride * (size_t)(R > 0 ? R : 1);
         w.gtab = off;
         off += w.dtab_stride;
+        w.g0tab = off;
+        off += w.dtab_stride;
     } else {
         w.grid = kPlainGrid;
     }
@@ -166,9 +169,9 @@ gv_status work_layout(const gv_ansatz &a, gv_precision prec, gv_engine eng, gv_g
         w.scratch = off;
         off += align_up(A * s);
     }
-    if (mode == GV_GRAD_CHECKPOINT && fused_ok(eng, a.n) && R > 1) {
-        w.ckpt = off;
-        off += align_up(A * s) * (size_t)(R - 1);
+    if (mode == GV_GRAD_CHECKPOINT && fused_ok(eng, a.n) && R > 2) {
+        w.ckpt = off;  // states after the RY gates of layers 1 .. R-2
+        off += align_up(A * s) * (size_t)(R - 2);
     }
     w.total = off;
     *out = w;
@@ -249,50 +252,9 @@ struct FusedCtx {
     WorkLayout w;
 };
 
-static gv_status fused_layer(gv_state st, const gv_ansatz &an, const FusedCtx &c, int l,
-                             void *psi, void *scratch)
+static bool is_cnot(const gv_ansatz &a)
 {
-    hipStream_t s = st->stream;
-    const double vb = (double)((size_t)1 << an.n) * amp_bytes(st->prec);
-    for (int p = 0; p < c.plan.npass; ++p) {
-        ProfScope ps(st, GV_PROF_FORWARD_PASS, 2 * vb);
-        hipError_t e = fused_forward_pass(st->prec, psi, an, c.plan, p, l,
-                                          p == c.plan.npass - 1, c.ch, c.tabs, s);
-        if (gv_status r = check_hip(e, "forward pass")) return r;
-    }
-    const bool cnot = an.ent == GV_ENT_CNOT_LINEAR || an.ent == GV_ENT_CNOT_CIRCULAR;
-    if (cnot && l < an.layers) {
-        const size_t bytes = ((size_t)1 << an.n) * amp_bytes(st->prec);
-        ProfScope ps(st, GV_PROF_OTHER, 4.0 * bytes);
-        if (gv_status r = check_hip(cnot_ladder_gather(st->prec, psi, scratch, an.n,
-                                                       an.ent == GV_ENT_CNOT_CIRCULAR, 0, s),
-                                    "cnot gather"))
-            return r;
-        if (gv_status r = check_hip(copy_vector(psi, scratch, bytes, s), "copy")) return r;
-    }
-    return GV_OK;
-}
-
-static gv_status fused_first_layer(gv_state st, const gv_ansatz &an, const FusedCtx &c,
-                                   void *psi, void *scratch)
-{
-    hipStream_t s = st->stream;
-    {
-        ProfScope ps(st, GV_PROF_INIT, (double)((size_t)1 << an.n) * amp_bytes(st->prec));
-        if (gv_status r = check_hip(fused_init_state(st->prec, psi, an, c.ch, c.tabs, s), "init"))
-            return r;
-    }
-    const bool cnot = an.ent == GV_ENT_CNOT_LINEAR || an.ent == GV_ENT_CNOT_CIRCULAR;
-    if (cnot && an.layers > 0) {
-        const size_t bytes = ((size_t)1 << an.n) * amp_bytes(st->prec);
-        ProfScope ps(st, GV_PROF_OTHER, 4.0 * bytes);
-        if (gv_status r = check_hip(cnot_ladder_gather(st->prec, psi, scratch, an.n,
-                                                       an.ent == GV_ENT_CNOT_CIRCULAR, 0, s),
-                                    "cnot gather"))
-            return r;
-        if (gv_status r = check_hip(copy_vector(psi, scratch, bytes, s), "copy")) return r;
-    }
-    return GV_OK;
+    return a.ent == GV_ENT_CNOT_LINEAR || a.ent == GV_ENT_CNOT_CIRCULAR;
 }
 
 static gv_status fused_setup(gv_state st, const gv_ansatz &an, const double *theta,
@@ -310,32 +272,83 @@ static gv_status fused_setup(gv_state st, const gv_ansatz &an, const double *the
     c->tabs.dtab = w + c->w.dtab;
     c->tabs.dtab_stride = c->w.dtab_stride;
     c->tabs.gtab = w + c->w.gtab;
+    c->tabs.g0tab = w + c->w.g0tab;
     ProfScope ps(st, GV_PROF_OTHER, 0.0);
     return check_hip(fused_build_tables(st->prec, an, c->ch, theta, c->tabs, st->stream), "tables");
 }
 
-// forward from |0> through rotation layers [0, upto]
-static gv_status fused_forward(gv_state st, const gv_ansatz &an, const FusedCtx &c, int upto,
-                               void *psi, char *ckpt, size_t vec_bytes)
+// psi <- CNOT D_layer psi (forward) or its inverse, through the scratch vector
+static gv_status cnot_step(gv_state st, const gv_ansatz &an, const FusedCtx &c, int layer,
+                           void *v, int inverse)
 {
-    char *scratch = (char *)st->work + c.w.scratch;
-    if (gv_status r = fused_first_layer(st, an, c, psi, scratch)) return r;
-    if (ckpt && upto > 0) {
-        ProfScope ps(st, GV_PROF_OTHER, 2.0 * vec_bytes);
-        if (gv_status r = check_hip(copy_vector(ckpt, psi, vec_bytes, st->stream), "checkpoint"))
+    const size_t vb = ((size_t)1 << an.n) * amp_bytes(st->prec);
+    void *scratch = (char *)st->work + c.w.scratch;
+    ProfScope ps(st, GV_PROF_OTHER, 4.0 * vb);
+    hipError_t e = cnot_ladder_gather(st->prec, v, scratch, an, c.ch, &c.tabs, layer, inverse,
+                                      st->stream);
+    if (e == hipSuccess) e = copy_vector(v, scratch, vb, st->stream);
+    return check_hip(e, "cnot ladder");
+}
+
+// Forward from |0...0> to psi~_upto, the state after the RY gates of layer
+// `upto` and before its diagonal.  skip_last leaves out layer upto's last
+// pass (the turnaround applies it).  ckpt (may be NULL) receives psi~_l in
+// slot l-1 for l = 1 .. R-2.
+static gv_status fused_forward(gv_state st, const gv_ansatz &an, const FusedCtx &c, int upto,
+                               bool skip_last, void *psi, char *ckpt, size_t vb)
+{
+    const int np = c.plan.npass, R = rot_layers(an);
+    const bool cnot = is_cnot(an);
+    const bool gen_first = !cnot && upto >= 1;  // R_0|0..0> generated inside layer 1's pass 0
+    hipStream_t s = st->stream;
+    if (!gen_first) {
+        ProfScope ps(st, GV_PROF_INIT, (double)vb);
+        if (gv_status r = check_hip(fused_init_state(st->prec, psi, an, c.ch, c.tabs, s), "init"))
             return r;
     }
     for (int l = 1; l <= upto; ++l) {
-        if (gv_status r = fused_layer(st, an, c, l, psi, scratch)) return r;
-        if (ckpt && l < upto) {
-            ProfScope ps(st, GV_PROF_OTHER, 2.0 * vec_bytes);
-            if (gv_status r = check_hip(copy_vector(ckpt + (size_t)l * vec_bytes, psi, vec_bytes,
-                                                    st->stream),
+        int in_mode = FWD_LOAD_DIAG;
+        if (cnot) {
+            if (gv_status r = cnot_step(st, an, c, l - 1, psi, 0)) return r;
+            in_mode = FWD_LOAD;
+        } else if (l == 1) {
+            in_mode = FWD_GENERATE;
+        }
+        for (int p = 0; p < np; ++p) {
+            if (skip_last && l == upto && p == np - 1) break;
+            const int mode = p == 0 ? in_mode : FWD_LOAD;
+            ProfScope ps(st, GV_PROF_FORWARD_PASS, mode == FWD_GENERATE ? (double)vb : 2.0 * vb);
+            if (gv_status r = check_hip(fused_forward_pass(st->prec, psi, an, c.plan, p, l, mode,
+                                                           c.ch, c.tabs, s),
+                                        "forward pass"))
+                return r;
+        }
+        if (ckpt && l <= R - 2) {
+            ProfScope ps(st, GV_PROF_OTHER, 2.0 * vb);
+            if (gv_status r = check_hip(copy_vector(ckpt + (size_t)(l - 1) * vb, psi, vb, s),
                                         "checkpoint"))
                 return r;
         }
     }
     return GV_OK;
+}
+
+// psi~ of the last layer -> psi (its diagonal, and the CNOT ladder when the
+// layer carries one), or back on both vectors
+static gv_status last_layer_transform(gv_state st, const gv_ansatz &an, const FusedCtx &c,
+                                      void *psi, void *lam, int inverse)
+{
+    const int l = rot_layers(an) - 1;
+    const size_t vb = ((size_t)1 << an.n) * amp_bytes(st->prec);
+    if (is_cnot(an) && l < an.layers) {
+        if (gv_status r = cnot_step(st, an, c, l, psi, inverse)) return r;
+        if (lam)
+            if (gv_status r = cnot_step(st, an, c, l, lam, inverse)) return r;
+        return GV_OK;
+    }
+    ProfScope ps(st, GV_PROF_OTHER, (lam ? 4.0 : 2.0) * vb);
+    return check_hip(fused_diag_apply(st->prec, psi, lam, an, c.ch, c.tabs, l, inverse, st->stream),
+                     "diagonal");
 }
 
 static gv_status energy_chain(gv_state st, gv_pauli_sum h, void *lam, double *epart,
@@ -453,8 +466,9 @@ gv_status gv_apply_ansatz(gv_state st, const double *theta, const gv_ansatz *a)
         FusedCtx c;
         if (gv_status r = fused_setup(st, *a, theta, GV_GRAD_UNCOMPUTE, &c)) return r;
         const size_t vb = ((size_t)1 << a->n) * amp_bytes(st->prec);
-        if (gv_status r = fused_forward(st, *a, c, rot_layers(*a) - 1, st->amps, nullptr, vb))
+        if (gv_status r = fused_forward(st, *a, c, rot_layers(*a) - 1, false, st->amps, nullptr, vb))
             return r;
+        if (gv_status r = last_layer_transform(st, *a, c, st->amps, nullptr, 0)) return r;
     } else {
         if (gv_status r = plain_forward(st, *a, theta)) return r;
     }
@@ -694,38 +708,72 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
     if (gv_status r = fused_setup(st, *a, theta, mode, &c)) return r;
     void *psi = st->amps;
     void *lam = w + c.w.lam;
-    char *ckpt = mode == GV_GRAD_CHECKPOINT && R > 1 ? w + c.w.ckpt : nullptr;
-    char *scratch = w + c.w.scratch;
+    char *ckpt = (mode == GV_GRAD_CHECKPOINT && R > 2) ? w + c.w.ckpt : nullptr;
     double *part = (double *)(w + c.w.part);
-    const bool cnot = a->ent == GV_ENT_CNOT_LINEAR || a->ent == GV_ENT_CNOT_CIRCULAR;
+    double *epart = (double *)(w + c.w.epart);
+    const bool cnot = is_cnot(*a);
+    const int np = c.plan.npass;
+    const bool zonly = h->oc.empty();
+    // the turnaround fuses the last forward pass, the energy and the first
+    // reverse pass; it needs a diagonal H that commutes with the last layer
+    const bool turn = zonly && !cnot && R >= 2;
 
-    if (gv_status r = fused_forward(st, *a, c, R - 1, psi, ckpt, vb)) return r;
-    if (gv_status r = energy_chain(st, h, lam, (double *)(w + c.w.epart), energy)) return r;
+    if (turn) {
+        if (gv_status r = fused_forward(st, *a, c, R - 1, true, psi, ckpt, vb)) return r;
+        const int l = R - 1, p = np - 1;
+        BwdFlags fl;  // post_diag / in_mode when the turnaround is layer R-1's only pass
+        int in_mode = FWD_LOAD;
+        if (np == 1) in_mode = l == 1 ? FWD_GENERATE : FWD_LOAD_DIAG;
+        fl.post_diag = np == 1;
+        ProfScope ps(st, GV_PROF_ENERGY, 2.0 * vb + 8.0 * (double)((size_t)1 << n));
+        if (gv_status r = check_hip(fused_turnaround(st->prec, psi, lam, h->diag, *a, c.plan, p, l,
+                                                     in_mode, fl.post_diag, c.ch, c.tabs, part,
+                                                     epart, c.w.grid, s),
+                                    "turnaround"))
+            return r;
+        if (gv_status r = check_hip(reduce_energy(epart, c.w.grid, energy, s), "energy reduce"))
+            return r;
+    } else {
+        if (gv_status r = fused_forward(st, *a, c, R - 1, false, psi, ckpt, vb)) return r;
+        // a diagonal H commutes with a diagonal last layer, so then psi~ serves as psi
+        const bool need_t = !zonly || (cnot && R - 1 < a->layers);
+        if (need_t)
+            if (gv_status r = last_layer_transform(st, *a, c, psi, nullptr, 0)) return r;
+        if (gv_status r = energy_chain(st, h, lam, epart, energy)) return r;
+        if (need_t)
+            if (gv_status r = last_layer_transform(st, *a, c, psi, lam, 1)) return r;
+    }
 
     for (int l = R - 1; l >= 0; --l) {
+        const int first = (turn && l == R - 1) ? np - 2 : np - 1;
         const void *phi_src = psi;
-        if (l < R - 1) {
-            if (mode == GV_GRAD_RECOMPUTE) {
-                if (gv_status r = fused_forward(st, *a, c, l, psi, nullptr, vb)) return r;
-            } else if (mode == GV_GRAD_CHECKPOINT) {
-                phi_src = ckpt + (size_t)l * vb;
+        const bool phi_gen = l == 0;
+        if (!phi_gen && l <= R - 2 && first >= 0) {
+            if (mode == GV_GRAD_CHECKPOINT) {
+                phi_src = ckpt + (size_t)(l - 1) * vb;
+            } else if (mode == GV_GRAD_RECOMPUTE) {
+                if (gv_status r = fused_forward(st, *a, c, l, false, psi, nullptr, vb)) return r;
             }
         }
-        if (cnot && l < a->layers) {
-            ProfScope ps(st, GV_PROF_OTHER, 8.0 * vb);
-            const int circ = a->ent == GV_ENT_CNOT_CIRCULAR;
-            hipError_t e = cnot_ladder_gather(st->prec, phi_src, scratch, n, circ, 1, s);
-            if (e == hipSuccess) e = copy_vector(psi, scratch, vb, s);
-            if (e == hipSuccess) e = cnot_ladder_gather(st->prec, lam, scratch, n, circ, 1, s);
-            if (e == hipSuccess) e = copy_vector(lam, scratch, vb, s);
-            if (gv_status r = check_hip(e, "cnot undo")) return r;
-            phi_src = psi;
-        }
-        for (int p = 0; p < c.plan.npass; ++p) {
-            ProfScope ps(st, GV_PROF_BACKWARD_PASS, 4.0 * vb);
-            hipError_t e = fused_backward_pass(st->prec, p == 0 ? phi_src : psi, psi, lam, *a,
-                                               c.plan, p, l, p == 0, c.ch, c.tabs, part, c.w.grid, s);
+        // does layer l-1 read phi from the state buffer?
+        const bool next_phi_needed = l - 1 >= 1 && mode == GV_GRAD_UNCOMPUTE;
+        for (int p = first; p >= 0; --p) {
+            BwdFlags fl;
+            fl.phi_generate = phi_gen && p == first;
+            fl.post_diag = p == 0 && l > 0 && !cnot;
+            fl.store_phi = p > 0 || next_phi_needed;
+            fl.store_lam = !(l == 0 && p == 0);
+            const double bytes = (fl.phi_generate ? 1.0 : 2.0) * vb +
+                                 ((fl.store_phi ? 1.0 : 0.0) + (fl.store_lam ? 1.0 : 0.0)) * vb;
+            ProfScope ps(st, GV_PROF_BACKWARD_PASS, bytes);
+            hipError_t e = fused_backward_pass(st->prec, p == first ? phi_src : psi, psi, lam, *a,
+                                               c.plan, p, l, fl, c.ch, c.tabs, part, c.w.grid, s);
             if (gv_status r = check_hip(e, "backward pass")) return r;
+        }
+        if (cnot && l > 0) {
+            if (gv_status r = cnot_step(st, *a, c, l - 1, lam, 1)) return r;
+            if (next_phi_needed)
+                if (gv_status r = cnot_step(st, *a, c, l - 1, psi, 1)) return r;
         }
     }
     st->has_psi = false;

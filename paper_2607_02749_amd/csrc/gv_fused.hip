@@ -1,28 +1,37 @@
 // gv_fused.hip -- the fused engine for the ansatz of Sec. IV-B (Eq. 7, Eq. 8)
 // and its reverse sweep.
 //
-// A layer of the ansatz is R_l = (x)_q RY(theta_{l,q}) followed by the
-// diagonal D_l = (prod_q RZ(phi_{l,q})) * (CZ ladder).  R_l factorises over
-// qubits, so it is applied in a few HBM sweeps ("passes"): a pass loads a
-// tile of 2^K amplitudes whose index bits pos[0..K) vary (the low C bits are
-// always in the tile so that every access is a run of >= 2^C contiguous
-// amplitudes), applies the RY of every tile qubit that is new in this pass,
-// and writes the tile back in place.  Inside a tile, each thread holds 2^LOGR
-// amplitudes in registers; the tile bits a thread's registers span change
-// between "assignments" by an exchange through LDS, so every tile bit is a
-// register bit in one assignment and its 2x2 rotation runs in registers.
-// D_l is applied in the last pass of the layer from three per-layer tables
-// indexed by chunks of the amplitude index (FP64-built, rounded once).
-// The first layer acts on |0...0>, so its state is a product state times
-// D_0 and is written directly from tables.
+// Layer l of the ansatz is R_l = (x)_q RY(theta_{l,q}) followed by the
+// diagonal D_l = (prod_q RZ(phi_{l,q})) * (CZ ladder) (for the CNOT ladder,
+// D_l holds only the RZ phases and the ladder is an index permutation).
+// R_l factorises over qubits, so it is applied in a few HBM sweeps
+// ("passes"): a pass loads a tile of 2^K amplitudes whose index bits
+// pos[0..K) vary (the low C bits are always in the tile, so every access is a
+// run of >= 2^C contiguous amplitudes), applies the RY of every tile qubit
+// that is new in this pass, and writes the tile back in place.  Inside a tile
+// each thread holds 2^LOGR amplitudes in registers; the tile bits a thread's
+// registers span change between "assignments" by an exchange through LDS, so
+// every tile bit is a register bit in one assignment and its 2x2 rotation
+// runs in registers.
 //
-// Reverse sweep (gradient): with phi = psi and lam = H psi, each layer is
-// undone with the same tiles.  For a tile qubit q of layer l, at the start of
-// its pass Im<lam|Z_q|phi> is the gradient of RZ(phi_{l,q}) (it commutes with
-// every diagonal factor and with the RY of other qubits), and just before its
-// RY is undone Im<lam|Y_q|phi> is the gradient of RY(theta_{l,q}).  Products
-// are taken in the amplitude precision over at most 2^LOGR terms per thread;
-// everything above that is FP64 with a fixed reduction order.
+// What sits in HBM between layers is the state just before a diagonal,
+// psi~_l = R_l D_{l-1} ... ; the diagonal D_{l-1} is applied on the fly when
+// the first pass of layer l loads its tiles (from three per-layer tables
+// indexed by chunks of the amplitude index, FP64-built and rounded once).
+// The first layer's state R_0|0...0> is a product state and is generated
+// from tables instead of being read.
+//
+// Reverse sweep (gradient): with phi = psi~_l and lam its adjoint partner,
+// for a tile qubit q of layer l, Im<lam|Z_q|phi> at the start of its pass is
+// the gradient of RZ(phi_{l,q}) (it commutes with every diagonal factor and
+// with the RY of other qubits), and Im<lam|Y_q|phi> just before its RY is
+// undone is the gradient of RY(theta_{l,q}).  The last pass of layer l
+// undoes D_{l-1} as it stores.  For a Z-only Hamiltonian the last forward
+// pass, the energy E = sum_i D_i |psi_i|^2, lam = D psi and the first
+// reverse pass run as one "turnaround" kernel.
+//
+// Products are taken in the amplitude precision over at most 2^LOGR terms
+// per thread; everything above that is FP64 with a fixed reduction order.
 #include <string.h>
 
 #include "gv_device.hpp"
@@ -32,24 +41,36 @@ namespace gv {
 
 namespace {
 
+// diagonal tables of one layer: T0 | T1 | T2 over index chunks
+struct DiagTab {
+    const void *tab;
+    int b1, b2;
+    int s1off, s2off;
+    u64 m0, m1;
+    int nx;                  // cross-chunk CZ pairs (sign flips)
+    int8_t xa[3], xb[3];
+};
+
+enum { IN_LOAD = 0, IN_LOAD_DIAG = 1, IN_GENERATE = 2 };
+
 struct FusedArgs {
     int n;
-    int layer;              // rotation layer whose gates this pass applies
-    int nparam_layer;       // 2n
+    int layer;               // rotation layer whose RY gates this pass applies
+    int nparam_layer;        // 2n
     int8_t pos[kMaxTileBits];
     uint32_t active;
-    int apply_diag;
-    int nruns;              // tile id -> outside bits, as runs of contiguous bits
+    int in_mode;             // forward: IN_*; reverse: 0 load phi, 2 generate phi
+    int post_diag;           // reverse: times conj(dt) before the store
+    int store_phi, store_lam;
+    int nruns;               // tile id -> outside bits, as runs of contiguous bits
     int8_t run_src[kMaxTileBits + 1], run_w[kMaxTileBits + 1], run_dst[kMaxTileBits + 1];
     u64 ntiles;
-    const double *ry;       // [P][2] cos, sin of half angles
-    const void *dtab;       // this layer's tables T0 | T1 | T2
-    int b1, b2;
-    int s1off, s2off;       // entry offsets of T1, T2
-    u64 m0, m1;             // chunk masks (after shifting)
-    int nx;                 // cross-chunk CZ pairs
-    int8_t xa[3], xb[3];
-    double *part;           // reverse sweep: P x grid partials
+    const double *ry;        // [P][2] cos, sin of half angles
+    DiagTab dt;              // diagonal applied on load (forward) / store (reverse)
+    DiagTab gt;              // product-state tables (IN_GENERATE)
+    const double *hdiag;     // turnaround: diagonal of the Hamiltonian
+    double *part;            // P x grid gradient partials
+    double *epart;           // turnaround: 2 x grid energy partials
     int grid;
 };
 
@@ -70,8 +91,8 @@ struct Tile {
         for (int b = 0; b < a; ++b) prev |= bits(b);
         return bits(a) & ~prev;
     }
-    // tile-local index of register r of thread t in an assignment with
-    // register bits [lo, lo + LOGR)
+    // tile-local index of register r of thread t in the assignment whose
+    // register bits are [l, l + LOGR)
     __device__ static __forceinline__ int u_of(int t, int r, int l)
     {
         return (t & ((1 << l) - 1)) | (r << l) | ((t >> l) << (l + LOGR));
@@ -87,8 +108,8 @@ __device__ __forceinline__ u64 tile_base(u64 tile, const FusedArgs &a)
     return b;
 }
 
-// physical offset of the thread bits of assignment lo (tile bits outside
-// [lo, lo + LOGR) take thread-id bits in ascending order)
+// physical offset of the thread bits of the assignment with register bits
+// [l, l + LOGR) (the other tile bits take thread-id bits in ascending order)
 template <int K, int LOGR>
 __device__ __forceinline__ u64 thread_off(int t, int l, const FusedArgs &a)
 {
@@ -103,28 +124,55 @@ __device__ __forceinline__ u64 thread_off(int t, int l, const FusedArgs &a)
     return off;
 }
 
-template <int LOGR>
-__device__ __forceinline__ u64 reg_off(int r, const u64 (&rb)[LOGR])
-{
-    u64 o = 0;
+// physical offset of register r: with CONTIG the register bits of the
+// assignment sit at consecutive positions (the planner guarantees it for
+// K >= 10), so the offset is r shifted by the first position
+template <int LOGR, bool CONTIG>
+struct RegMap {
+    u64 rb[CONTIG ? 1 : LOGR];
+    int sh;
+    __device__ __forceinline__ void init(const int8_t *p)
+    {
+        sh = p[0];
+        if constexpr (!CONTIG)
 #pragma unroll
-    for (int k = 0; k < LOGR; ++k)
-        if ((r >> k) & 1) o |= rb[k];
-    return o;
+            for (int k = 0; k < LOGR; ++k) rb[k] = 1ull << p[k];
+    }
+    __device__ __forceinline__ u64 off(int r) const
+    {
+        if constexpr (CONTIG) {
+            return (u64)r << sh;
+        } else {
+            u64 o = 0;
+#pragma unroll
+            for (int k = 0; k < LOGR; ++k)
+                if ((r >> k) & 1) o |= rb[k];
+            return o;
+        }
+    }
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> diag_entry(u64 i, const DiagTab &d)
+{
+    const cx<R> *T = (const cx<R> *)d.tab;
+    cx<R> v = cmul(cmul(T[i & d.m0], T[d.s1off + ((i >> d.b1) & d.m1)]), T[d.s2off + (i >> d.b2)]);
+    int par = 0;
+    for (int k = 0; k < d.nx; ++k) par ^= (int)((i >> d.xa[k]) & (i >> d.xb[k]) & 1);
+    if (par) {
+        v.re = -v.re;
+        v.im = -v.im;
+    }
+    return v;
 }
 
 template <typename R>
-__device__ __forceinline__ cx<R> diag_entry(u64 i, const FusedArgs &a)
+__device__ __forceinline__ cx<R> cmul_conj(cx<R> a, cx<R> d)  // a * conj(d)
 {
-    const cx<R> *T = (const cx<R> *)a.dtab;
-    cx<R> d = cmul(cmul(T[i & a.m0], T[a.s1off + ((i >> a.b1) & a.m1)]), T[a.s2off + (i >> a.b2)]);
-    int par = 0;
-    for (int k = 0; k < a.nx; ++k) par ^= (int)((i >> a.xa[k]) & (i >> a.xb[k]) & 1);
-    if (par) {
-        d.re = -d.re;
-        d.im = -d.im;
-    }
-    return d;
+    cx<R> o;
+    o.re = a.re * d.re + a.im * d.im;
+    o.im = a.im * d.re - a.re * d.im;
+    return o;
 }
 
 // RY on the pair (x, y): (c x - s y, s x + c y)
@@ -158,8 +206,8 @@ __device__ __forceinline__ void fwd_assign(cx<R> (&v)[1 << LOGR], const FusedArg
 }
 
 // reverse step of the tile bits new in assignment AI: gradient partial of
-// RY (Im<lam|Y_q|phi> = Re(conj(l1) f0) - Re(conj(l0) f1) over pairs), then
-// RY(-theta) on both vectors
+// RY (Im<lam|Y_q|phi> = Re(conj(l1) f0) - Re(conj(l0) f1) over the pairs),
+// then RY(-theta) on both vectors
 template <typename R, int K, int LOGR, int AI>
 __device__ __forceinline__ void bwd_assign(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
                                            double (&accY)[K], const FusedArgs &a)
@@ -210,6 +258,7 @@ struct FwdChain {
     }
 };
 
+// reverse assignments AI = 1 .. NA-1, each after an exchange from AI-1
 template <typename R, int K, int LOGR, int AI>
 struct BwdChain {
     __device__ static __forceinline__ void run(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
@@ -224,52 +273,87 @@ struct BwdChain {
     }
 };
 
-template <typename R, int K, int LOGR>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_pass(cx<R> *psi, FusedArgs a)
+// reverse assignments in the order AI, AI-1, ..., 0 (each after an exchange
+// from AI+1), used by the turnaround whose data ends the forward part in the
+// last assignment
+template <typename R, int K, int LOGR, int AI>
+struct BwdChainRev {
+    __device__ static __forceinline__ void run(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
+                                               double (&accY)[K], cx<R> *lds, int t,
+                                               const FusedArgs &a)
+    {
+        using T = Tile<K, LOGR>;
+        exchange<R, K, LOGR>(f, lds, t, T::lo(AI + 1), T::lo(AI));
+        exchange<R, K, LOGR>(l, lds, t, T::lo(AI + 1), T::lo(AI));
+        bwd_assign<R, K, LOGR, AI>(f, l, accY, a);
+        if constexpr (AI > 0) BwdChainRev<R, K, LOGR, AI - 1>::run(f, l, accY, lds, t, a);
+    }
+};
+
+template <typename R, int K, int LOGR, bool CONTIG>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_pass(void *psi_, FusedArgs a)
 {
+    cx<R> *psi = (cx<R> *)psi_;
     using T = Tile<K, LOGR>;
     __shared__ cx<R> lds[T::LDS];
     const int t = threadIdx.x;
     constexpr int LD = T::lo(0), ST = T::lo(T::NA - 1);
     const u64 toff_ld = thread_off<K, LOGR>(t, LD, a), toff_st = thread_off<K, LOGR>(t, ST, a);
-    u64 rb_ld[LOGR], rb_st[LOGR];
-#pragma unroll
-    for (int k = 0; k < LOGR; ++k) {
-        rb_ld[k] = 1ull << a.pos[LD + k];
-        rb_st[k] = 1ull << a.pos[ST + k];
-    }
+    RegMap<LOGR, CONTIG> mld, mst;
+    mld.init(a.pos + LD);
+    mst.init(a.pos + ST);
     for (u64 tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
         const u64 base = tile_base(tile, a);
         cx<R> v[T::NR];
+        if (a.in_mode == IN_GENERATE) {
 #pragma unroll
-        for (int r = 0; r < T::NR; ++r) v[r] = psi[base | toff_ld | reg_off<LOGR>(r, rb_ld)];
+            for (int r = 0; r < T::NR; ++r) v[r] = diag_entry<R>(base | toff_ld | mld.off(r), a.gt);
+        } else {
+#pragma unroll
+            for (int r = 0; r < T::NR; ++r) v[r] = psi[base | toff_ld | mld.off(r)];
+            if (a.in_mode == IN_LOAD_DIAG) {
+#pragma unroll
+                for (int r = 0; r < T::NR; ++r)
+                    v[r] = cmul(v[r], diag_entry<R>(base | toff_ld | mld.off(r), a.dt));
+            }
+        }
         fwd_assign<R, K, LOGR, 0>(v, a);
         if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(v, lds, t, a);
 #pragma unroll
-        for (int r = 0; r < T::NR; ++r) {
-            const u64 i = base | toff_st | reg_off<LOGR>(r, rb_st);
-            if (a.apply_diag) v[r] = cmul(v[r], diag_entry<R>(i, a));
-            psi[i] = v[r];
-        }
+        for (int r = 0; r < T::NR; ++r) psi[base | toff_st | mst.off(r)] = v[r];
     }
 }
 
-template <typename R, int K, int LOGR>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const cx<R> *phi_in, cx<R> *phi,
-                                                              cx<R> *lam, FusedArgs a)
+template <typename R, int K>
+__device__ __forceinline__ void write_partials(const double (&accY)[K], const double (&accZ)[K],
+                                               bool zeroZ, double *sh, const FusedArgs &a)
 {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (!((a.active >> j) & 1)) continue;
+        const int64_t row = (int64_t)a.layer * a.nparam_layer + a.pos[j];
+        const double y = block_sum(accY[j], sh);
+        if (threadIdx.x == 0) a.part[row * a.grid + blockIdx.x] = y;
+        const double z = zeroZ ? 0.0 : block_sum(accZ[j], sh);
+        if (threadIdx.x == 0) a.part[(row + a.n) * a.grid + blockIdx.x] = z;
+    }
+}
+
+template <typename R, int K, int LOGR, bool CONTIG>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const void *phi_in_, void *phi_,
+                                                              void *lam_, FusedArgs a)
+{
+    const cx<R> *phi_in = (const cx<R> *)phi_in_;
+    cx<R> *phi = (cx<R> *)phi_, *lam = (cx<R> *)lam_;
     using T = Tile<K, LOGR>;
     __shared__ cx<R> lds[T::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
     const int t = threadIdx.x;
     constexpr int LD = T::lo(0), ST = T::lo(T::NA - 1);
     const u64 toff_ld = thread_off<K, LOGR>(t, LD, a), toff_st = thread_off<K, LOGR>(t, ST, a);
-    u64 rb_ld[LOGR], rb_st[LOGR];
-#pragma unroll
-    for (int k = 0; k < LOGR; ++k) {
-        rb_ld[k] = 1ull << a.pos[LD + k];
-        rb_st[k] = 1ull << a.pos[ST + k];
-    }
+    RegMap<LOGR, CONTIG> mld, mst;
+    mld.init(a.pos + LD);
+    mst.init(a.pos + ST);
     double accY[K], accZ[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) accY[j] = accZ[j] = 0.0;
@@ -279,15 +363,9 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const cx<R> *phi_i
         cx<R> f[T::NR], l[T::NR];
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
-            const u64 i = base | toff_ld | reg_off<LOGR>(r, rb_ld);
-            f[r] = phi_in[i];
+            const u64 i = base | toff_ld | mld.off(r);
+            f[r] = a.in_mode == IN_GENERATE ? diag_entry<R>(i, a.gt) : phi_in[i];
             l[r] = lam[i];
-            if (a.apply_diag) {
-                cx<R> d = diag_entry<R>(i, a);
-                d.im = -d.im;
-                f[r] = cmul(f[r], d);
-                l[r] = cmul(l[r], d);
-            }
         }
         // RZ gradients of the active tile qubits: sum_i z_q(i) Im(conj(lam_i) phi_i)
         {
@@ -316,20 +394,86 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const cx<R> *phi_i
         if constexpr (T::NA > 1) BwdChain<R, K, LOGR, 1>::run(f, l, accY, lds, t, a);
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
-            const u64 i = base | toff_st | reg_off<LOGR>(r, rb_st);
-            phi[i] = f[r];
-            lam[i] = l[r];
+            const u64 i = base | toff_st | mst.off(r);
+            if (a.post_diag) {
+                const cx<R> d = diag_entry<R>(i, a.dt);
+                f[r] = cmul_conj(f[r], d);
+                l[r] = cmul_conj(l[r], d);
+            }
+            if (a.store_phi) phi[i] = f[r];
+            if (a.store_lam) lam[i] = l[r];
         }
     }
-    // FP64 block sums of the gradient partials, one column per block
+    write_partials<R, K>(accY, accZ, false, sh, a);
+}
+
+// Last forward pass of the last layer + energy + first reverse pass, for a
+// Z-only Hamiltonian with diagonal D: in each tile psi gets the pass's RY
+// gates, E += sum D_i |psi_i|^2, lam = D psi, then the reverse step of the
+// same gates runs on (psi, lam) and only lam is stored (phi after the
+// reverse step equals the loaded tile, which stays in HBM).  RZ gradients of
+// the tile qubits are zero here: Im(conj(D_i psi_i) psi_i) = 0.  When this is
+// the layer's only pass, the load applies the previous layer's diagonal (or
+// generates the first layer's state) and the store undoes that diagonal on
+// lam.
+template <typename R, int K, int LOGR, bool CONTIG>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_pass(const void *psi_, void *lam_,
+                                                               FusedArgs a)
+{
+    const cx<R> *psi = (const cx<R> *)psi_;
+    cx<R> *lam = (cx<R> *)lam_;
+    using T = Tile<K, LOGR>;
+    __shared__ cx<R> lds[T::LDS];
+    __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
+    const int t = threadIdx.x;
+    constexpr int LD = T::lo(0), ST = T::lo(T::NA - 1);
+    const u64 toff_ld = thread_off<K, LOGR>(t, LD, a), toff_st = thread_off<K, LOGR>(t, ST, a);
+    RegMap<LOGR, CONTIG> mld, mst;
+    mld.init(a.pos + LD);
+    mst.init(a.pos + ST);
+    double accY[K], accZ[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        if (!((a.active >> j) & 1)) continue;
-        const int64_t row = (int64_t)a.layer * a.nparam_layer + a.pos[j];
-        const double y = block_sum(accY[j], sh);
-        if (t == 0) a.part[row * a.grid + blockIdx.x] = y;
-        const double z = block_sum(accZ[j], sh);
-        if (t == 0) a.part[(row + a.n) * a.grid + blockIdx.x] = z;
+    for (int j = 0; j < K; ++j) accY[j] = accZ[j] = 0.0;
+    double eacc = 0.0;
+
+    for (u64 tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const u64 base = tile_base(tile, a);
+        cx<R> f[T::NR], l[T::NR];
+        if (a.in_mode == IN_GENERATE) {
+#pragma unroll
+            for (int r = 0; r < T::NR; ++r) f[r] = diag_entry<R>(base | toff_ld | mld.off(r), a.gt);
+        } else {
+#pragma unroll
+            for (int r = 0; r < T::NR; ++r) f[r] = psi[base | toff_ld | mld.off(r)];
+            if (a.in_mode == IN_LOAD_DIAG) {
+#pragma unroll
+                for (int r = 0; r < T::NR; ++r)
+                    f[r] = cmul(f[r], diag_entry<R>(base | toff_ld | mld.off(r), a.dt));
+            }
+        }
+        fwd_assign<R, K, LOGR, 0>(f, a);
+        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(f, lds, t, a);
+        // energy and lam in the last assignment's layout
+#pragma unroll
+        for (int r = 0; r < T::NR; ++r) {
+            const double d = a.hdiag[base | toff_st | mst.off(r)];
+            eacc += d * ((double)f[r].re * f[r].re + (double)f[r].im * f[r].im);
+            l[r].re = (R)d * f[r].re;
+            l[r].im = (R)d * f[r].im;
+        }
+        bwd_assign<R, K, LOGR, T::NA - 1>(f, l, accY, a);
+        if constexpr (T::NA > 1) BwdChainRev<R, K, LOGR, T::NA - 2>::run(f, l, accY, lds, t, a);
+#pragma unroll
+        for (int r = 0; r < T::NR; ++r) {
+            const u64 i = base | toff_ld | mld.off(r);
+            lam[i] = a.post_diag ? cmul_conj(l[r], diag_entry<R>(i, a.dt)) : l[r];
+        }
+    }
+    write_partials<R, K>(accY, accZ, true, sh, a);
+    const double e = block_sum(eacc, sh);
+    if (t == 0) {
+        a.epart[blockIdx.x] = e;
+        a.epart[a.grid + blockIdx.x] = 0.0;
     }
 }
 
@@ -350,15 +494,16 @@ __global__ void k_ry_table(const double *theta, int64_t np, double *ry)
 struct TabArgs {
     int n;
     int rot_layers;
-    int cz_layers;          // layers (entangled ones carry CZ when cz != 0)
+    int cz_layers;          // layers that carry the CZ ladder
     int cz;                 // 1 linear CZ, 2 circular CZ, 0 none
-    int b[4];               // chunk bounds b0=0, b1, b2, b3=n
-    int off[4];             // entry offsets of the chunks within a layer's table set
+    int b[4];               // chunk bounds 0, b1, b2, n
+    int off[4];             // entry offsets of the chunks within a table set
     size_t stride;          // bytes per layer
 };
 
 // in-chunk phase of RZ and CZ for entry v of chunk c in layer l:
-// prod_{q in chunk} exp(-+ i phi_q / 2) * (-1)^{CZ pairs inside the chunk}
+// prod_{q in chunk} exp(-+ i phi_q / 2), and the parity of the CZ pairs
+// inside the chunk
 __device__ __forceinline__ void chunk_phase(const double *theta, const TabArgs &ta, int l, int c,
                                             u64 v, double &ang, int &par)
 {
@@ -404,10 +549,11 @@ __global__ void k_diag_tables(const double *theta, TabArgs ta, char *dtab)
     }
 }
 
-// first-layer product-state tables: prod_{q in chunk} (bit ? sin : cos)(theta_q/2)
-// times the chunk's diagonal phase of layer 0
+// first-layer tables: g0 = prod_{q in chunk} (bit ? sin : cos)(theta_q / 2)
+// (the product state R_0|0...0>), g = g0 times the chunk's diagonal phase of
+// layer 0 (the state D_0 R_0|0...0>)
 template <typename R>
-__global__ void k_init_tables(const double *theta, TabArgs ta, cx<R> *gtab)
+__global__ void k_init_tables(const double *theta, TabArgs ta, cx<R> *gtab, cx<R> *g0tab)
 {
     const int per = ta.off[3];
     for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < per; w += gridDim.x * blockDim.x) {
@@ -416,12 +562,17 @@ __global__ void k_init_tables(const double *theta, TabArgs ta, cx<R> *gtab)
         double ang;
         int par;
         chunk_phase(theta, ta, 0, c, v, ang, par);
-        double mag = par ? -1.0 : 1.0;
+        double mag = 1.0;
         for (int q = ta.b[c]; q < ta.b[c + 1]; ++q) {
             double s, co;
             sincos(0.5 * theta[q], &s, &co);
             mag *= ((v >> (q - ta.b[c])) & 1) ? s : co;
         }
+        cx<R> g0;
+        g0.re = (R)mag;
+        g0.im = (R)0;
+        g0tab[w] = g0;
+        if (par) mag = -mag;
         double s, co;
         sincos(ang, &s, &co);
         cx<R> out;
@@ -431,35 +582,54 @@ __global__ void k_init_tables(const double *theta, TabArgs ta, cx<R> *gtab)
     }
 }
 
+// psi_i = table product (the first layer's state)
 template <typename R>
-__global__ void k_init_state(cx<R> *psi, FusedArgs a, u64 dim)
+__global__ void k_table_state(cx<R> *psi, DiagTab d, u64 dim)
 {
     for (u64 i = blockIdx.x * (u64)blockDim.x + threadIdx.x; i < dim;
          i += (u64)gridDim.x * blockDim.x)
-        psi[i] = diag_entry<R>(i, a);
+        psi[i] = diag_entry<R>(i, d);
 }
 
-// CNOT ladder as an index permutation.  Forward ladder F = f o g with
-// f = prefix XOR of the index bits (CNOT(q -> q+1) for q = 0, 1, ...) and
-// g = CNOT(n-1 -> 0) for the circular form (identity otherwise).
-// forward:  dst[j] = src[g(f^-1(j))];  inverse: dst[i] = src[f(g(i))].
+// v0 (and v1) times the layer diagonal, or its conjugate
 template <typename R>
-__global__ void k_cnot_gather(const cx<R> *src, cx<R> *dst, int n, int circular, int inverse)
+__global__ void k_diag_apply(cx<R> *v0, cx<R> *v1, DiagTab d, u64 dim, int conj)
+{
+    for (u64 i = blockIdx.x * (u64)blockDim.x + threadIdx.x; i < dim;
+         i += (u64)gridDim.x * blockDim.x) {
+        cx<R> e = diag_entry<R>(i, d);
+        if (conj) e.im = -e.im;
+        v0[i] = cmul(v0[i], e);
+        if (v1) v1[i] = cmul(v1[i], e);
+    }
+}
+
+// CNOT ladder as an index permutation, fused with the layer diagonal.
+// Forward ladder F = f o g with f = prefix XOR of the index bits (CNOT(q ->
+// q+1) for q = 0, 1, ...) and g = CNOT(n-1 -> 0) for the circular form.
+// forward:  dst[j] = D(s) src[s], s = g(f^-1(j))  (the state CNOT D psi~)
+// inverse:  dst[i] = conj(D(i)) src[f(g(i))]       (undoes both)
+template <typename R>
+__global__ void k_cnot_gather(const cx<R> *src, cx<R> *dst, int n, int circular, int inverse,
+                              DiagTab d, int with_diag)
 {
     const u64 dim = 1ull << n, mask = dim - 1;
     for (u64 o = blockIdx.x * (u64)blockDim.x + threadIdx.x; o < dim;
          o += (u64)gridDim.x * blockDim.x) {
-        u64 i;
         if (!inverse) {
-            i = o ^ ((o << 1) & mask);
+            u64 i = o ^ ((o << 1) & mask);
             if (circular) i ^= (i >> (n - 1)) & 1;
+            cx<R> v = src[i];
+            if (with_diag) v = cmul(v, diag_entry<R>(i, d));
+            dst[o] = v;
         } else {
             u64 v = o;
             if (circular) v ^= (v >> (n - 1)) & 1;
             for (int sh = 1; sh < 64; sh <<= 1) v ^= v << sh;
-            i = v & mask;
+            cx<R> x = src[v & mask];
+            if (with_diag) x = cmul_conj(x, diag_entry<R>(o, d));
+            dst[o] = x;
         }
-        dst[o] = src[i];
     }
 }
 
@@ -487,32 +657,42 @@ void fill_runs(FusedArgs &a, const PassPlan &pp, int K, int n)
     }
 }
 
-void fill_diag(FusedArgs &a, const gv_ansatz &an, const Chunks &ch, const void *tab, int layer)
+// table set of layer `layer` (cz: whether this layer carries the CZ ladder)
+DiagTab make_diagtab(const gv_ansatz &an, const Chunks &ch, const void *tab, bool cz_layer)
 {
-    a.dtab = tab;
-    a.b1 = ch.b1;
-    a.b2 = ch.b2;
-    a.s1off = ch.size0;
-    a.s2off = ch.size0 + ch.size1;
-    a.m0 = (u64)ch.size0 - 1;
-    a.m1 = (u64)ch.size1 - 1;
-    a.nx = 0;
+    DiagTab d;
+    memset(&d, 0, sizeof(d));
+    d.tab = tab;
+    d.b1 = ch.b1;
+    d.b2 = ch.b2;
+    d.s1off = ch.size0;
+    d.s2off = ch.size0 + ch.size1;
+    d.m0 = (u64)ch.size0 - 1;
+    d.m1 = (u64)ch.size1 - 1;
+    d.nx = 0;
     const int n = an.n;
-    const bool cz = (an.ent == GV_ENT_CZ_LINEAR || an.ent == GV_ENT_CZ_CIRCULAR) && layer < an.layers;
-    if (!cz) return;
+    const bool cz = (an.ent == GV_ENT_CZ_LINEAR || an.ent == GV_ENT_CZ_CIRCULAR) && cz_layer;
+    if (!cz) return d;
     if (ch.b1 < n) {
-        a.xa[a.nx] = (int8_t)(ch.b1 - 1);
-        a.xb[a.nx++] = (int8_t)ch.b1;
+        d.xa[d.nx] = (int8_t)(ch.b1 - 1);
+        d.xb[d.nx++] = (int8_t)ch.b1;
     }
     if (ch.b2 < n) {
-        a.xa[a.nx] = (int8_t)(ch.b2 - 1);
-        a.xb[a.nx++] = (int8_t)ch.b2;
+        d.xa[d.nx] = (int8_t)(ch.b2 - 1);
+        d.xb[d.nx++] = (int8_t)ch.b2;
     }
-    // circular pair (n-1, 0) lies in one chunk only when there is one chunk
+    // the circular pair (n-1, 0) lies inside one chunk only when there is one chunk
     if (an.ent == GV_ENT_CZ_CIRCULAR && n > 2 && ch.b1 < n) {
-        a.xa[a.nx] = (int8_t)(n - 1);
-        a.xb[a.nx++] = 0;
+        d.xa[d.nx] = (int8_t)(n - 1);
+        d.xb[d.nx++] = 0;
     }
+    return d;
+}
+
+DiagTab layer_tab(const gv_ansatz &an, const Chunks &ch, const FusedTables &t, int layer)
+{
+    return make_diagtab(an, ch, (const char *)t.dtab + (size_t)layer * t.dtab_stride,
+                        layer < an.layers);
 }
 
 TabArgs make_tab_args(const gv_ansatz &an, const Chunks &ch, size_t stride)
@@ -534,25 +714,8 @@ TabArgs make_tab_args(const gv_ansatz &an, const Chunks &ch, size_t stride)
     return ta;
 }
 
-template <typename R, int K, int LOGR>
-hipError_t launch_fwd(void *psi, const FusedArgs &a, int grid, hipStream_t s)
-{
-    hipLaunchKernelGGL((k_fwd_pass<R, K, LOGR>), dim3(grid), dim3(1 << (K - LOGR)), 0, s,
-                       (cx<R> *)psi, a);
-    return hipGetLastError();
-}
-
-template <typename R, int K, int LOGR>
-hipError_t launch_bwd(const void *phi_in, void *phi, void *lam, const FusedArgs &a, int grid,
-                      hipStream_t s)
-{
-    hipLaunchKernelGGL((k_bwd_pass<R, K, LOGR>), dim3(grid), dim3(1 << (K - LOGR)), 0, s,
-                       (const cx<R> *)phi_in, (cx<R> *)phi, (cx<R> *)lam, a);
-    return hipGetLastError();
-}
-
 FusedArgs base_args(const gv_ansatz &an, const TilePlan &plan, int pass, int layer,
-                    int apply_diag, const Chunks &ch, const FusedTables &t, int prec)
+                    const FusedTables &t)
 {
     FusedArgs a;
     memset(&a, 0, sizeof(a));
@@ -561,14 +724,49 @@ FusedArgs base_args(const gv_ansatz &an, const TilePlan &plan, int pass, int lay
     a.nparam_layer = 2 * an.n;
     for (int j = 0; j < plan.K; ++j) a.pos[j] = plan.pass[pass].pos[j];
     a.active = plan.pass[pass].active;
-    a.apply_diag = apply_diag;
     fill_runs(a, plan.pass[pass], plan.K, an.n);
     a.ntiles = 1ull << (an.n - plan.K);
     a.ry = t.ry;
-    fill_diag(a, an, ch, (const char *)t.dtab + (size_t)layer * t.dtab_stride, layer);
-    (void)prec;
+    a.store_phi = a.store_lam = 1;
     return a;
 }
+
+inline int elem_grid(u64 dim)
+{
+    const u64 b = (dim + 255) / 256;
+    return (int)(b < 8192 ? b : 8192);
+}
+
+#define GV_LAUNCH_K(KERNEL, PREC, GRID, K, ...)                                                   \
+    do {                                                                                          \
+        switch (K) {                                                                              \
+        case 12:                                                                                  \
+            if (PREC == GV_C64)                                                                   \
+                hipLaunchKernelGGL((KERNEL<float, 12, 4, true>), dim3(GRID), dim3(256), 0, s,     \
+                                   __VA_ARGS__);                                                  \
+            else                                                                                  \
+                hipLaunchKernelGGL((KERNEL<double, 12, 4, true>), dim3(GRID), dim3(256), 0, s,    \
+                                   __VA_ARGS__);                                                  \
+            break;                                                                                \
+        case 10:                                                                                  \
+            if (PREC == GV_C64)                                                                   \
+                hipLaunchKernelGGL((KERNEL<float, 10, 4, true>), dim3(GRID), dim3(64), 0, s,      \
+                                   __VA_ARGS__);                                                  \
+            else                                                                                  \
+                hipLaunchKernelGGL((KERNEL<double, 10, 4, true>), dim3(GRID), dim3(64), 0, s,     \
+                                   __VA_ARGS__);                                                  \
+            break;                                                                                \
+        case 8:                                                                                   \
+            if (PREC == GV_C64)                                                                   \
+                hipLaunchKernelGGL((KERNEL<float, 8, 3, false>), dim3(GRID), dim3(32), 0, s,      \
+                                   __VA_ARGS__);                                                  \
+            else                                                                                  \
+                hipLaunchKernelGGL((KERNEL<double, 8, 3, false>), dim3(GRID), dim3(32), 0, s,     \
+                                   __VA_ARGS__);                                                  \
+            break;                                                                                \
+        default: return hipErrorInvalidValue;                                                     \
+        }                                                                                         \
+    } while (0)
 
 }  // namespace
 
@@ -595,12 +793,12 @@ hipError_t fused_build_tables(int prec, const gv_ansatz &an, const Chunks &ch,
         hipLaunchKernelGGL(k_diag_tables<float>, dim3(g), dim3(256), 0, s, theta, ta,
                            (char *)t.dtab);
         hipLaunchKernelGGL(k_init_tables<float>, dim3((ta.off[3] + 255) / 256), dim3(256), 0, s,
-                           theta, ta, (cx<float> *)t.gtab);
+                           theta, ta, (cx<float> *)t.gtab, (cx<float> *)t.g0tab);
     } else {
         hipLaunchKernelGGL(k_diag_tables<double>, dim3(g), dim3(256), 0, s, theta, ta,
                            (char *)t.dtab);
         hipLaunchKernelGGL(k_init_tables<double>, dim3((ta.off[3] + 255) / 256), dim3(256), 0, s,
-                           theta, ta, (cx<double> *)t.gtab);
+                           theta, ta, (cx<double> *)t.gtab, (cx<double> *)t.g0tab);
     }
     return hipGetLastError();
 }
@@ -608,69 +806,101 @@ hipError_t fused_build_tables(int prec, const gv_ansatz &an, const Chunks &ch,
 hipError_t fused_init_state(int prec, void *psi, const gv_ansatz &an, const Chunks &ch,
                             const FusedTables &t, hipStream_t s)
 {
-    FusedArgs a;
-    memset(&a, 0, sizeof(a));
-    a.n = an.n;
-    fill_diag(a, an, ch, t.gtab, 0);
+    // the product state R_0|0...0> (no phases: the first pass of layer 1,
+    // or the energy step, applies D_0)
+    const DiagTab d = make_diagtab(an, ch, t.g0tab, false);
     const u64 dim = 1ull << an.n;
-    const u64 b = (dim + 255) / 256;
-    const int g = (int)(b < 8192 ? b : 8192);
     if (prec == GV_C64)
-        hipLaunchKernelGGL(k_init_state<float>, dim3(g), dim3(256), 0, s, (cx<float> *)psi, a, dim);
+        hipLaunchKernelGGL(k_table_state<float>, dim3(elem_grid(dim)), dim3(256), 0, s,
+                           (cx<float> *)psi, d, dim);
     else
-        hipLaunchKernelGGL(k_init_state<double>, dim3(g), dim3(256), 0, s, (cx<double> *)psi, a,
-                           dim);
+        hipLaunchKernelGGL(k_table_state<double>, dim3(elem_grid(dim)), dim3(256), 0, s,
+                           (cx<double> *)psi, d, dim);
     return hipGetLastError();
 }
 
 hipError_t fused_forward_pass(int prec, void *psi, const gv_ansatz &an, const TilePlan &plan,
-                              int pass, int layer, int apply_diag, const Chunks &ch,
+                              int pass, int layer, int in_mode, const Chunks &ch,
                               const FusedTables &t, hipStream_t s)
 {
-    FusedArgs a = base_args(an, plan, pass, layer, apply_diag, ch, t, prec);
+    FusedArgs a = base_args(an, plan, pass, layer, t);
+    a.in_mode = in_mode;
+    if (in_mode == IN_LOAD_DIAG) a.dt = layer_tab(an, ch, t, layer - 1);
+    if (in_mode == IN_GENERATE) a.gt = make_diagtab(an, ch, t.gtab, 0 < an.layers);
     const int grid = fused_grid(prec, plan, an.n);
-    switch (plan.K) {
-    case 12: return prec == GV_C64 ? launch_fwd<float, 12, 4>(psi, a, grid, s)
-                                   : launch_fwd<double, 12, 4>(psi, a, grid, s);
-    case 10: return prec == GV_C64 ? launch_fwd<float, 10, 4>(psi, a, grid, s)
-                                   : launch_fwd<double, 10, 4>(psi, a, grid, s);
-    case 8: return prec == GV_C64 ? launch_fwd<float, 8, 3>(psi, a, grid, s)
-                                  : launch_fwd<double, 8, 3>(psi, a, grid, s);
-    default: return hipErrorInvalidValue;
-    }
+    GV_LAUNCH_K(k_fwd_pass, prec, grid, plan.K, psi, a);
+    return hipGetLastError();
 }
 
 hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *lam,
                                const gv_ansatz &an, const TilePlan &plan, int pass, int layer,
-                               int apply_diag, const Chunks &ch, const FusedTables &t,
+                               const BwdFlags &fl, const Chunks &ch, const FusedTables &t,
                                double *part, int grid, hipStream_t s)
 {
-    FusedArgs a = base_args(an, plan, pass, layer, apply_diag, ch, t, prec);
+    FusedArgs a = base_args(an, plan, pass, layer, t);
+    a.in_mode = fl.phi_generate ? IN_GENERATE : IN_LOAD;
+    if (fl.phi_generate) a.gt = make_diagtab(an, ch, t.g0tab, false);
+    a.post_diag = fl.post_diag;
+    if (fl.post_diag) a.dt = layer_tab(an, ch, t, layer - 1);
+    a.store_phi = fl.store_phi;
+    a.store_lam = fl.store_lam;
     a.part = part;
     a.grid = grid;
-    switch (plan.K) {
-    case 12: return prec == GV_C64 ? launch_bwd<float, 12, 4>(phi_in, phi, lam, a, grid, s)
-                                   : launch_bwd<double, 12, 4>(phi_in, phi, lam, a, grid, s);
-    case 10: return prec == GV_C64 ? launch_bwd<float, 10, 4>(phi_in, phi, lam, a, grid, s)
-                                   : launch_bwd<double, 10, 4>(phi_in, phi, lam, a, grid, s);
-    case 8: return prec == GV_C64 ? launch_bwd<float, 8, 3>(phi_in, phi, lam, a, grid, s)
-                                  : launch_bwd<double, 8, 3>(phi_in, phi, lam, a, grid, s);
-    default: return hipErrorInvalidValue;
-    }
+    GV_LAUNCH_K(k_bwd_pass, prec, grid, plan.K, phi_in, phi, lam, a);
+    return hipGetLastError();
 }
 
-hipError_t cnot_ladder_gather(int prec, const void *src, void *dst, int n, int circular,
-                              int inverse, hipStream_t s)
+hipError_t fused_turnaround(int prec, const void *psi, void *lam, const double *hdiag,
+                            const gv_ansatz &an, const TilePlan &plan, int pass, int layer,
+                            int in_mode, int post_diag, const Chunks &ch, const FusedTables &t,
+                            double *part, double *epart, int grid, hipStream_t s)
 {
-    const u64 dim = 1ull << n;
-    const u64 b = (dim + 255) / 256;
-    const int g = (int)(b < 8192 ? b : 8192);
+    FusedArgs a = base_args(an, plan, pass, layer, t);
+    a.in_mode = in_mode;
+    if (in_mode == IN_LOAD_DIAG || post_diag) a.dt = layer_tab(an, ch, t, layer - 1);
+    if (in_mode == IN_GENERATE) a.gt = make_diagtab(an, ch, t.gtab, 0 < an.layers);
+    a.post_diag = post_diag;
+    a.hdiag = hdiag;
+    a.part = part;
+    a.epart = epart;
+    a.grid = grid;
+    GV_LAUNCH_K(k_turn_pass, prec, grid, plan.K, psi, lam, a);
+    return hipGetLastError();
+}
+
+hipError_t fused_diag_apply(int prec, void *v0, void *v1, const gv_ansatz &an, const Chunks &ch,
+                            const FusedTables &t, int layer, int conj, hipStream_t s)
+{
+    const DiagTab d = layer_tab(an, ch, t, layer);
+    const u64 dim = 1ull << an.n;
     if (prec == GV_C64)
-        hipLaunchKernelGGL(k_cnot_gather<float>, dim3(g), dim3(256), 0, s, (const cx<float> *)src,
-                           (cx<float> *)dst, n, circular, inverse);
+        hipLaunchKernelGGL(k_diag_apply<float>, dim3(elem_grid(dim)), dim3(256), 0, s,
+                           (cx<float> *)v0, (cx<float> *)v1, d, dim, conj);
     else
-        hipLaunchKernelGGL(k_cnot_gather<double>, dim3(g), dim3(256), 0, s,
-                           (const cx<double> *)src, (cx<double> *)dst, n, circular, inverse);
+        hipLaunchKernelGGL(k_diag_apply<double>, dim3(elem_grid(dim)), dim3(256), 0, s,
+                           (cx<double> *)v0, (cx<double> *)v1, d, dim, conj);
+    return hipGetLastError();
+}
+
+hipError_t cnot_ladder_gather(int prec, const void *src, void *dst, const gv_ansatz &an,
+                              const Chunks &ch, const FusedTables *t, int layer, int inverse,
+                              hipStream_t s)
+{
+    const int n = an.n;
+    const int circular = an.ent == GV_ENT_CNOT_CIRCULAR && n > 2;
+    DiagTab d;
+    memset(&d, 0, sizeof(d));
+    const int with_diag = t != nullptr;
+    if (t) d = layer_tab(an, ch, *t, layer);
+    const u64 dim = 1ull << n;
+    if (prec == GV_C64)
+        hipLaunchKernelGGL(k_cnot_gather<float>, dim3(elem_grid(dim)), dim3(256), 0, s,
+                           (const cx<float> *)src, (cx<float> *)dst, n, circular, inverse, d,
+                           with_diag);
+    else
+        hipLaunchKernelGGL(k_cnot_gather<double>, dim3(elem_grid(dim)), dim3(256), 0, s,
+                           (const cx<double> *)src, (cx<double> *)dst, n, circular, inverse, d,
+                           with_diag);
     return hipGetLastError();
 }
 

@@ -120,7 +120,8 @@ struct WorkLayout {
     size_t scratch = 0;      // one vector (CNOT gather)
     size_t ry_tab = 0;       // per parameter: forward and backward (cos, sin) doubles
     size_t dtab = 0;         // per rotation layer: forward + backward diagonal tables
-    size_t gtab = 0;         // product-state tables of the first layer
+    size_t gtab = 0;         // first-layer tables D_0 R_0|0..0>
+    size_t g0tab = 0;        // first-layer tables R_0|0..0>
     size_t part = 0;         // gradient partials: P rows x grid columns
     size_t epart = 0;        // energy partials: 2 x grid
     size_t total = 0;
@@ -171,24 +172,40 @@ hipError_t copy_vector(void *dst, const void *src, size_t bytes, hipStream_t s);
 
 // fused engine
 struct FusedTables {
-    const double *ry;    // [P][4]: fwd cos, fwd sin, bwd cos, bwd sin (of half angles)
-    void *dtab;          // per rotation layer diagonal tables
+    const double *ry;    // [P][2]: cos, sin of half angles
+    void *dtab;          // per rotation layer diagonal tables (RZ phases, CZ signs)
     size_t dtab_stride;
-    void *gtab;          // first-layer product-state tables
+    void *gtab;          // D_0 R_0|0...0> tables
+    void *g0tab;         // R_0|0...0> tables
 };
+struct BwdFlags {
+    int phi_generate = 0;   // phi = R_0|0...0> from tables instead of a load
+    int post_diag = 0;      // undo D_{layer-1} before the store
+    int store_phi = 1, store_lam = 1;
+};
+// forward pass input modes
+enum { FWD_LOAD = 0, FWD_LOAD_DIAG = 1, FWD_GENERATE = 2 };
 hipError_t fused_build_tables(int prec, const gv_ansatz &a, const Chunks &ch, const double *theta,
                               const FusedTables &t, hipStream_t s);
 hipError_t fused_init_state(int prec, void *psi, const gv_ansatz &a, const Chunks &ch,
                             const FusedTables &t, hipStream_t s);
 hipError_t fused_forward_pass(int prec, void *psi, const gv_ansatz &a, const TilePlan &plan,
-                              int pass, int layer, int apply_diag, const Chunks &ch,
+                              int pass, int layer, int in_mode, const Chunks &ch,
                               const FusedTables &t, hipStream_t s);
 hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *lam,
                                const gv_ansatz &a, const TilePlan &plan, int pass, int layer,
-                               int apply_diag, const Chunks &ch, const FusedTables &t,
+                               const BwdFlags &fl, const Chunks &ch, const FusedTables &t,
                                double *part, int grid, hipStream_t s);
-hipError_t cnot_ladder_gather(int prec, const void *src, void *dst, int n, int circular,
-                              int inverse, hipStream_t s);
+hipError_t fused_turnaround(int prec, const void *psi, void *lam, const double *hdiag,
+                            const gv_ansatz &a, const TilePlan &plan, int pass, int layer,
+                            int in_mode, int post_diag, const Chunks &ch, const FusedTables &t,
+                            double *part, double *epart, int grid, hipStream_t s);
+hipError_t fused_diag_apply(int prec, void *v0, void *v1, const gv_ansatz &a, const Chunks &ch,
+                            const FusedTables &t, int layer, int conj, hipStream_t s);
+// CNOT ladder gather; with t != NULL the layer diagonal is fused in
+hipError_t cnot_ladder_gather(int prec, const void *src, void *dst, const gv_ansatz &a,
+                              const Chunks &ch, const FusedTables *t, int layer, int inverse,
+                              hipStream_t s);
 int fused_grid(int prec, const TilePlan &plan, int n);
 
 }  // namespace gv

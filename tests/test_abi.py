@@ -47,7 +47,7 @@ def test_query_sizes():
     assert sb == 8 << 28
     assert wb >= 8 << 28                       # holds the adjoint vector
     _, wck = gv.query_sizes(gv.Ansatz(28, 6), "c64", "fused", "checkpoint")
-    assert wck >= wb + 5 * (8 << 28)           # five inner layer boundaries
+    assert wck >= wb + 4 * (8 << 28)           # states after layers 1..4 (layer 0 is regenerated)
     sb128, _ = gv.query_sizes(gv.Ansatz(10, 2), "c128", "plain")
     assert sb128 == 16 << 10
     with pytest.raises(gv.GVError):

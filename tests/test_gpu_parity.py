@@ -200,3 +200,15 @@ def test_workload_n22_both_precisions():
     for precision in ("c128", "c64"):
         e, g, _, _ = run_gpu(inst, precision)
         check(e, g, e_ref, g_ref, precision, "n=22")
+
+
+@pytest.mark.parametrize("n", [10, 12, 13, 16])
+@pytest.mark.parametrize("layers", [1, 2, 3])
+@pytest.mark.parametrize("mode", ["uncompute", "checkpoint", "recompute"])
+def test_z_only_turnaround(n, layers, mode):
+    # Z-only Hamiltonians take the fused last-pass / energy / first-reverse-pass path
+    inst = synth.make_instance(n, layers, 15 * n, 5, 3, seed=500 + 7 * n + layers,
+                               final_rotation=int(layers == 2))
+    for precision in ("c128", "c64"):
+        e, g, _, _ = run_gpu(inst, precision, mode=mode)
+        check(e, g, *oracle_eg(inst), precision, f"zonly n={n} L={layers} {mode}")
