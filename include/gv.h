@@ -147,9 +147,11 @@ gv_status gv_pauli_sum_device_bytes(gv_pauli_sum h, size_t *bytes);
 
 /* Build the device form of H into caller memory `dev` (>= device_bytes,
  * 256-byte aligned): the diagonal D_i = sum_{k: x_k = 0} c_k (-1)^{|i & z_k|}
- * by an in-place fast Walsh-Hadamard transform, and the off-diagonal tables.
+ * by an in-place fast Walsh-Hadamard transform, and the off-diagonal terms
+ * grouped by flip mask into the tile passes of the state's engine and
+ * precision (states of another precision or engine then get GV_ESTATE).
  * Runs on the state's stream and waits for it (a setup call).  `dev` is
- * borrowed until gv_pauli_sum_destroy. */
+ * borrowed until gv_pauli_sum_destroy or the next prepare. */
 gv_status gv_pauli_sum_prepare(gv_pauli_sum h, gv_state st, void *dev, size_t bytes);
 
 /* <psi|H|psi> of the state's current psi.  energy_dev: 2 device doubles
@@ -183,7 +185,8 @@ typedef enum {
     GV_PROF_INIT = 3,           /* first-layer product state */
     GV_PROF_PLAIN_GATE = 4,     /* plain engine gate or reverse step */
     GV_PROF_OTHER = 5,          /* tables, reductions, copies, gathers */
-    GV_PROF_KINDS = 6
+    GV_PROF_OFFDIAG = 6,        /* off-diagonal terms: lambda += H_off psi */
+    GV_PROF_KINDS = 7
 } gv_prof_kind;
 
 gv_status gv_profile_enable(gv_state st, int32_t enable);

@@ -111,23 +111,25 @@ bool make_tile_plan(int n, int K, int C, TilePlan *out)
     return true;
 }
 
-Chunks make_chunks(int n)
+Chunks make_chunks(int n, int K, int LOGR)
 {
-    const int nc = (n + 11) / 12 < 1 ? 1 : (n + 11) / 12;
-    const int b1 = std::min(n, (n + nc - 1) / nc);
-    const int b2 = std::min(n, 2 * b1);
+    // chunk 0: the thread bits and chunk 1: the register bits of pass 0's load
+    // assignment; chunks 2 and 3 split the remaining bits in halves
     Chunks c;
-    c.b1 = b1;
-    c.b2 = b2;
-    c.size0 = 1 << b1;
-    c.size1 = 1 << (b2 - b1);
-    c.size2 = 1 << (n - b2);
+    c.b[0] = 0;
+    c.b[1] = std::min(n, K - LOGR);
+    c.b[2] = std::min(n, K);
+    c.b[3] = std::min(n, K + (n - K + 1) / 2);
+    c.b[4] = n;
+    c.off[0] = 0;
+    for (int k = 0; k < 4; ++k) c.off[k + 1] = c.off[k] + (1 << (c.b[k + 1] - c.b[k]));
     return c;
 }
 
 static const int kEnergyGrid = 1024;
 
 static int choose_K(int n) { return n >= 12 ? 12 : (n >= 10 ? 10 : 8); }
+static int choose_logr(int K) { return K == 8 ? 3 : 4; }
 static int choose_C(gv_precision p, int K) { return std::min(K - 1, p == GV_C64 ? 4 : 3); }
 static bool fused_ok(gv_engine e, int n) { return e == GV_ENGINE_FUSED && n >= 8; }
 
@@ -147,8 +149,9 @@ gv_status work_layout(const gv_ansatz &a, gv_precision prec, gv_engine eng, gv_g
         if (!make_tile_plan(a.n, choose_K(a.n), choose_C(prec, choose_K(a.n)), &plan))
             return set_error(GV_EUNSUPPORTED, "no tile plan for n=%d", a.n);
         w.grid = fused_grid(prec, plan, a.n);
-        const Chunks ch = make_chunks(a.n);
-        w.dtab_stride = align_up((size_t)(ch.size0 + ch.size1 + ch.size2) * s);
+        const int K = choose_K(a.n);
+        const Chunks ch = make_chunks(a.n, K, choose_logr(K));
+        w.dtab_stride = align_up((size_t)ch.off[4] * s);
         w.ry_tab = off;
         off += align_up((size_t)P * 2 * sizeof(double) + 8);
         w.dtab = off;
@@ -266,7 +269,7 @@ static gv_status fused_setup(gv_state st, const gv_ansatz &an, const double *the
                          c->w.total);
     const int K = choose_K(an.n);
     make_tile_plan(an.n, K, choose_C(st->prec, K), &c->plan);
-    c->ch = make_chunks(an.n);
+    c->ch = make_chunks(an.n, K, choose_logr(K));
     char *w = (char *)st->work;
     c->tabs.ry = (const double *)(w + c->w.ry_tab);
     c->tabs.dtab = w + c->w.dtab;
@@ -363,14 +366,33 @@ static gv_status energy_chain(gv_state st, gv_pauli_sum h, void *lam, double *ep
                                     "energy diag"))
             return r;
     }
-    ProfScope ps(st, GV_PROF_OTHER, (double)h->oc.size() * (lam ? 3 : 1) * vb);
-    if (!h->oc.empty())
+    const bool cover = !h->off_passes.empty() && fused_ok(st->engine, st->n) &&
+                       h->cover_K == choose_K(st->n) &&
+                       h->cover_C == choose_C(st->prec, choose_K(st->n));
+    if (!h->off_passes.empty() && !cover)
+        return set_error(GV_ESTATE, "pauli sum was prepared for another precision or engine");
+    for (const OffPass &op : h->off_passes) {
+        ProfScope ps(st, GV_PROF_OFFDIAG, (lam ? 3.0 : 1.0) * vb);
+        if (gv_status r = check_hip(offdiag_pass(st->prec, st->amps, lam, st->n, h->cover_K, op,
+                                                 h->dev_cls, h->dev_terms, epart, kEnergyGrid, s),
+                                    "off-diagonal pass"))
+            return r;
+    }
+    if (!h->loose_terms.empty()) {
+        std::vector<uint64_t> lx, lz;
+        std::vector<double> lc;
+        for (int64_t k : h->loose_terms) {
+            lx.push_back(h->ox[k]);
+            lz.push_back(h->oz[k]);
+            lc.push_back(h->oc[k]);
+        }
+        ProfScope ps(st, GV_PROF_OFFDIAG, (double)lx.size() * (lam ? 3 : 1) * vb);
         if (gv_status r = check_hip(energy_offdiag_terms(st->prec, st->amps, lam, st->n,
-                                                         (int64_t)h->oc.size(), h->ox.data(),
-                                                         h->oz.data(), h->oc.data(), epart,
-                                                         kEnergyGrid, s),
+                                                         (int64_t)lx.size(), lx.data(), lz.data(),
+                                                         lc.data(), epart, kEnergyGrid, s),
                                     "energy off-diagonal"))
             return r;
+    }
     return check_hip(reduce_energy(epart, kEnergyGrid, energy, s), "energy reduce");
 }
 
@@ -552,18 +574,16 @@ gv_status gv_pauli_sum_info(gv_pauli_sum h, int64_t *n_diag, int64_t *n_offdiag,
     return GV_OK;
 }
 
-static void pauli_layout(const gv_pauli_s *h, size_t *diag, size_t *ox, size_t *oz, size_t *oc,
+static void pauli_layout(const gv_pauli_s *h, size_t *diag, size_t *cls, size_t *terms,
                          size_t *sz, size_t *sc, size_t *total)
 {
     size_t off = 0;
     *diag = off;
     off += align_up(((size_t)1 << h->n) * sizeof(double));
-    *ox = off;
-    off += align_up(h->ox.size() * 8 + 8);
-    *oz = off;
-    off += align_up(h->oz.size() * 8 + 8);
-    *oc = off;
-    off += align_up(h->oc.size() * 8 + 8);
+    *cls = off;
+    off += align_up(h->ox.size() * sizeof(OffClass) + 8);
+    *terms = off;
+    off += align_up(h->ox.size() * sizeof(OffTerm) + 8);
     *sz = off;
     off += align_up(h->dz.size() * 8 + 8);
     *sc = off;
@@ -571,11 +591,81 @@ static void pauli_layout(const gv_pauli_s *h, size_t *diag, size_t *ox, size_t *
     *total = off;
 }
 
+// Group the off-diagonal terms by flip mask and cover the classes with tiles
+// of K index bits that keep bits 0..C-1: a class joins a tile when its flip
+// bits fit; every class sits in exactly one tile.  Classes whose flip bits
+// cannot fit any tile are applied term by term.
+static void build_cover(gv_pauli_s *h, int K, int C)
+{
+    h->classes.clear();
+    h->class_terms.clear();
+    h->off_passes.clear();
+    h->loose_terms.clear();
+    h->cover_K = K;
+    h->cover_C = C;
+    const int n = h->n;
+    std::map<uint64_t, std::vector<int64_t>> by_x;
+    for (size_t k = 0; k < h->ox.size(); ++k) by_x[h->ox[k]].push_back((int64_t)k);
+    const uint64_t low = (C >= 64) ? ~0ull : ((1ull << C) - 1);
+    std::vector<uint64_t> pending;
+    for (const auto &kv : by_x) {
+        if (__builtin_popcountll(kv.first & ~low) > K - C) {
+            for (int64_t k : kv.second) h->loose_terms.push_back(k);
+        } else {
+            pending.push_back(kv.first);
+        }
+    }
+    while (!pending.empty()) {
+        uint64_t tile = low;
+        std::vector<uint64_t> chosen, rest;
+        for (uint64_t x : pending) {
+            if (__builtin_popcountll(tile | x) <= K) {
+                tile |= x;
+                chosen.push_back(x);
+            } else {
+                rest.push_back(x);
+            }
+        }
+        for (int q = 0; q < n && __builtin_popcountll(tile) < K; ++q) tile |= 1ull << q;
+        OffPass op;
+        int j = 0;
+        int8_t where[64];
+        for (int q = 0; q < n; ++q)
+            if ((tile >> q) & 1) {
+                where[q] = (int8_t)j;
+                op.pos[j++] = (int8_t)q;
+            }
+        op.c0 = (int)h->classes.size();
+        for (uint64_t x : chosen) {
+            OffClass cl;
+            cl.x = x;
+            cl.xu = 0;
+            for (int q = 0; q < n; ++q)
+                if ((x >> q) & 1) cl.xu |= 1u << where[q];
+            cl.t0 = (int32_t)h->class_terms.size();
+            for (int64_t k : by_x[x]) {
+                OffTerm tm;
+                tm.z = h->oz[k];
+                tm.c = h->oc[k];
+                tm.ph = __builtin_popcountll(h->ox[k] & h->oz[k]) & 3;
+                tm.pad = 0;
+                h->class_terms.push_back(tm);
+            }
+            cl.t1 = (int32_t)h->class_terms.size();
+            cl.pad = 0;
+            h->classes.push_back(cl);
+        }
+        op.c1 = (int)h->classes.size();
+        h->off_passes.push_back(op);
+        pending.swap(rest);
+    }
+}
+
 gv_status gv_pauli_sum_device_bytes(gv_pauli_sum h, size_t *bytes)
 {
     if (!h || !bytes) return set_error(GV_EINVAL, "NULL argument");
-    size_t a, b, c, d, e, f;
-    pauli_layout(h, &a, &b, &c, &d, &e, &f, bytes);
+    size_t a, b, c, d, e;
+    pauli_layout(h, &a, &b, &c, &d, &e, bytes);
     return GV_OK;
 }
 
@@ -584,27 +674,36 @@ gv_status gv_pauli_sum_prepare(gv_pauli_sum h, gv_state st, void *dev, size_t by
     if (!h || !st || !dev) return set_error(GV_EINVAL, "NULL argument");
     if (h->n != st->n) return set_error(GV_ESTATE, "pauli sum n=%d but state n=%d", h->n, st->n);
     if (!aligned(dev)) return set_error(GV_EINVAL, "buffer must be %zu-byte aligned", kAlign);
-    size_t odiag, oox, ooz, ooc, osz, osc, total;
-    pauli_layout(h, &odiag, &oox, &ooz, &ooc, &osz, &osc, &total);
+    size_t odiag, ocls, oterms, osz, osc, total;
+    pauli_layout(h, &odiag, &ocls, &oterms, &osz, &osc, &total);
     if (bytes < total) return set_error(GV_ESIZE, "buffer %zu bytes < %zu", bytes, total);
     char *base = (char *)dev;
     hipStream_t s = st->stream;
     h->dev = dev;
     h->dev_bytes = bytes;
     h->diag = (double *)(base + odiag);
-    h->dev_ox = (uint64_t *)(base + oox);
-    h->dev_oz = (uint64_t *)(base + ooz);
-    h->dev_oc = (double *)(base + ooc);
+    h->dev_cls = (OffClass *)(base + ocls);
+    h->dev_terms = (OffTerm *)(base + oterms);
     h->prepared = false;
     const int n = h->n;
-    if (!h->ox.empty()) {
-        if (gv_status r = check_hip(hipMemcpyAsync(h->dev_ox, h->ox.data(), h->ox.size() * 8,
+    if (fused_ok(st->engine, n)) {
+        const int K = choose_K(n);
+        build_cover(h, K, choose_C(st->prec, K));
+    } else {
+        h->classes.clear();
+        h->class_terms.clear();
+        h->off_passes.clear();
+        h->loose_terms.clear();
+        for (size_t k = 0; k < h->ox.size(); ++k) h->loose_terms.push_back((int64_t)k);
+        h->cover_K = h->cover_C = 0;
+    }
+    if (!h->classes.empty()) {
+        if (gv_status r = check_hip(hipMemcpyAsync(h->dev_cls, h->classes.data(),
+                                                   h->classes.size() * sizeof(OffClass),
                                                    hipMemcpyHostToDevice, s), "copy"))
             return r;
-        if (gv_status r = check_hip(hipMemcpyAsync(h->dev_oz, h->oz.data(), h->oz.size() * 8,
-                                                   hipMemcpyHostToDevice, s), "copy"))
-            return r;
-        if (gv_status r = check_hip(hipMemcpyAsync(h->dev_oc, h->oc.data(), h->oc.size() * 8,
+        if (gv_status r = check_hip(hipMemcpyAsync(h->dev_terms, h->class_terms.data(),
+                                                   h->class_terms.size() * sizeof(OffTerm),
                                                    hipMemcpyHostToDevice, s), "copy"))
             return r;
     }
@@ -718,63 +817,77 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
     // reverse pass; it needs a diagonal H that commutes with the last layer
     const bool turn = zonly && !cnot && R >= 2;
 
+    // What the state and lam buffers hold at the start of a layer's reverse
+    // sweep: the point before the layer's diagonal (PRE) or after it (POST).
+    bool phi_post, lam_post;
     if (turn) {
         if (gv_status r = fused_forward(st, *a, c, R - 1, true, psi, ckpt, vb)) return r;
         const int l = R - 1, p = np - 1;
-        BwdFlags fl;  // post_diag / in_mode when the turnaround is layer R-1's only pass
-        int in_mode = FWD_LOAD;
-        if (np == 1) in_mode = l == 1 ? FWD_GENERATE : FWD_LOAD_DIAG;
-        fl.post_diag = np == 1;
+        const int in_mode = np > 1 ? FWD_LOAD : (l == 1 ? FWD_GENERATE : FWD_LOAD_DIAG);
         ProfScope ps(st, GV_PROF_ENERGY, 2.0 * vb + 8.0 * (double)((size_t)1 << n));
         if (gv_status r = check_hip(fused_turnaround(st->prec, psi, lam, h->diag, *a, c.plan, p, l,
-                                                     in_mode, fl.post_diag, c.ch, c.tabs, part,
-                                                     epart, c.w.grid, s),
+                                                     in_mode, c.ch, c.tabs, part, epart,
+                                                     c.w.grid, s),
                                     "turnaround"))
             return r;
         if (gv_status r = check_hip(reduce_energy(epart, c.w.grid, energy, s), "energy reduce"))
             return r;
+        phi_post = lam_post = false;
     } else {
         if (gv_status r = fused_forward(st, *a, c, R - 1, false, psi, ckpt, vb)) return r;
-        // a diagonal H commutes with a diagonal last layer, so then psi~ serves as psi
+        // a diagonal H commutes with a diagonal last layer: then psi~ serves as psi
         const bool need_t = !zonly || (cnot && R - 1 < a->layers);
         if (need_t)
             if (gv_status r = last_layer_transform(st, *a, c, psi, nullptr, 0)) return r;
         if (gv_status r = energy_chain(st, h, lam, epart, energy)) return r;
-        if (need_t)
-            if (gv_status r = last_layer_transform(st, *a, c, psi, lam, 1)) return r;
+        phi_post = lam_post = need_t;
     }
 
     for (int l = R - 1; l >= 0; --l) {
-        const int first = (turn && l == R - 1) ? np - 2 : np - 1;
-        const void *phi_src = psi;
+        // passes of this layer still to undo (the turnaround did the last one)
+        const int npl = (turn && l == R - 1) ? np - 1 : np;
+        const bool cnot_layer = cnot && l < a->layers;
         const bool phi_gen = l == 0;
-        if (!phi_gen && l <= R - 2 && first >= 0) {
+        const void *phi_src = psi;
+        if (!phi_gen && l <= R - 2 && npl > 0) {
             if (mode == GV_GRAD_CHECKPOINT) {
                 phi_src = ckpt + (size_t)(l - 1) * vb;
+                phi_post = false;
             } else if (mode == GV_GRAD_RECOMPUTE) {
                 if (gv_status r = fused_forward(st, *a, c, l, false, psi, nullptr, vb)) return r;
+                phi_post = false;
             }
+        }
+        if (phi_gen) phi_post = false;
+        if (cnot_layer && npl > 0) {  // undo the ladder (and the diagonal) by gathers
+            if (lam_post)
+                if (gv_status r = cnot_step(st, *a, c, l, lam, 1)) return r;
+            if (phi_post)
+                if (gv_status r = cnot_step(st, *a, c, l, psi, 1)) return r;
+            phi_post = lam_post = false;
         }
         // does layer l-1 read phi from the state buffer?
         const bool next_phi_needed = l - 1 >= 1 && mode == GV_GRAD_UNCOMPUTE;
-        for (int p = first; p >= 0; --p) {
+        for (int p = 0; p < npl; ++p) {
+            const bool last = p == npl - 1;
             BwdFlags fl;
-            fl.phi_generate = phi_gen && p == first;
-            fl.post_diag = p == 0 && l > 0 && !cnot;
-            fl.store_phi = p > 0 || next_phi_needed;
-            fl.store_lam = !(l == 0 && p == 0);
+            fl.phi_generate = phi_gen && p == 0;
+            fl.diag_phi = p == 0 && phi_post;
+            fl.diag_lam = p == 0 && lam_post;
+            fl.store_phi = !last || next_phi_needed;
+            fl.store_lam = !(l == 0 && last);
             const double bytes = (fl.phi_generate ? 1.0 : 2.0) * vb +
                                  ((fl.store_phi ? 1.0 : 0.0) + (fl.store_lam ? 1.0 : 0.0)) * vb;
             ProfScope ps(st, GV_PROF_BACKWARD_PASS, bytes);
-            hipError_t e = fused_backward_pass(st->prec, p == first ? phi_src : psi, psi, lam, *a,
+            hipError_t e = fused_backward_pass(st->prec, p == 0 ? phi_src : psi, psi, lam, *a,
                                                c.plan, p, l, fl, c.ch, c.tabs, part, c.w.grid, s);
             if (gv_status r = check_hip(e, "backward pass")) return r;
         }
-        if (cnot && l > 0) {
-            if (gv_status r = cnot_step(st, *a, c, l - 1, lam, 1)) return r;
-            if (next_phi_needed)
-                if (gv_status r = cnot_step(st, *a, c, l - 1, psi, 1)) return r;
-        }
+        // after undoing layer l's RY gates both vectors sit after layer l-1's
+        // diagonal, except phi when the turnaround was layer l's only pass
+        // (the state buffer then still holds the layer's input, before it)
+        lam_post = true;
+        phi_post = npl > 0;
     }
     st->has_psi = false;
     ProfScope ps(st, GV_PROF_OTHER, 0.0);

@@ -41,14 +41,19 @@ namespace gv {
 
 namespace {
 
-// diagonal tables of one layer: T0 | T1 | T2 over index chunks
+// Diagonal tables of one layer over four chunks of the amplitude index,
+// chunk c covering bits [b_c, b_{c+1}) with b_0 = 0, b_1 = K - LOGR, b_2 = K
+// (so in the contiguous pass 0, chunk 0 is the thread bits and chunk 1 the
+// register bits of the load assignment) and b_4 = n.  Entry v of chunk c is
+// the product of the RZ phases of the chunk's qubits and the sign of the CZ
+// pairs inside the chunk; CZ pairs that straddle chunks are listed apart.
 struct DiagTab {
     const void *tab;
-    int b1, b2;
-    int s1off, s2off;
-    u64 m0, m1;
-    int nx;                  // cross-chunk CZ pairs (sign flips)
-    int8_t xa[3], xb[3];
+    int b1, b2, b3;
+    int off1, off2, off3;
+    u64 m0, m1, m2;
+    int npair;
+    int8_t pa[4], pb[4];
 };
 
 enum { IN_LOAD = 0, IN_LOAD_DIAG = 1, IN_GENERATE = 2 };
@@ -59,15 +64,16 @@ struct FusedArgs {
     int nparam_layer;        // 2n
     int8_t pos[kMaxTileBits];
     uint32_t active;
-    int in_mode;             // forward: IN_*; reverse: 0 load phi, 2 generate phi
-    int post_diag;           // reverse: times conj(dt) before the store
+    int in_mode;             // forward / turnaround: IN_* (diag and generate only in pass 0)
+    int diag_phi, diag_lam;  // reverse, pass 0: times conj(dt) on load
+    int phi_gen;             // reverse, pass 0: phi from gt instead of a load
     int store_phi, store_lam;
     int nruns;               // tile id -> outside bits, as runs of contiguous bits
     int8_t run_src[kMaxTileBits + 1], run_w[kMaxTileBits + 1], run_dst[kMaxTileBits + 1];
     u64 ntiles;
     const double *ry;        // [P][2] cos, sin of half angles
-    DiagTab dt;              // diagonal applied on load (forward) / store (reverse)
-    DiagTab gt;              // product-state tables (IN_GENERATE)
+    DiagTab dt;              // layer diagonal (or the first layer's generator in forward)
+    DiagTab gt;              // reverse: generator of R_0|0...0>
     const double *hdiag;     // turnaround: diagonal of the Hamiltonian
     double *part;            // P x grid gradient partials
     double *epart;           // turnaround: 2 x grid energy partials
@@ -153,18 +159,73 @@ struct RegMap {
 };
 
 template <typename R>
+__device__ __forceinline__ cx<R> cneg(cx<R> v)
+{
+    v.re = -v.re;
+    v.im = -v.im;
+    return v;
+}
+
+template <typename R>
 __device__ __forceinline__ cx<R> diag_entry(u64 i, const DiagTab &d)
 {
     const cx<R> *T = (const cx<R> *)d.tab;
-    cx<R> v = cmul(cmul(T[i & d.m0], T[d.s1off + ((i >> d.b1) & d.m1)]), T[d.s2off + (i >> d.b2)]);
+    cx<R> v = cmul(cmul(T[i & d.m0], T[d.off1 + ((i >> d.b1) & d.m1)]),
+                   cmul(T[d.off2 + ((i >> d.b2) & d.m2)], T[d.off3 + (i >> d.b3)]));
     int par = 0;
-    for (int k = 0; k < d.nx; ++k) par ^= (int)((i >> d.xa[k]) & (i >> d.xb[k]) & 1);
-    if (par) {
-        v.re = -v.re;
-        v.im = -v.im;
-    }
-    return v;
+    for (int k = 0; k < d.npair; ++k) par ^= (int)((i >> d.pa[k]) & (i >> d.pb[k]) & 1);
+    return par ? cneg(v) : v;
 }
+
+// The diagonal over the tiles of pass 0 (tile bits = index bits 0..K-1) in
+// the load assignment: thread t's bits are chunk 0, register r's bits chunk
+// 1, the tile id's bits chunks 2 and 3.  D = T0[t] T1[r] T2 T3 times the
+// signs of the straddling CZ pairs, collected per (thread, tile) as a mask
+// over the registers.
+template <typename R, int K, int LOGR>
+struct P0Diag {
+    static constexpr int NR = 1 << LOGR;
+    cx<R> t0;        // T0[t], per thread
+    cx<R> w;         // T0[t] T2 T3, per thread and tile
+    uint32_t neg;    // bit r: register r's entry is negated
+    __device__ __forceinline__ void init(const DiagTab &d, int t)
+    {
+        t0 = ((const cx<R> *)d.tab)[t];
+    }
+    __device__ static __forceinline__ uint32_t reg_pattern(int k)
+    {
+        uint32_t m = 0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            if ((r >> k) & 1) m |= 1u << r;
+        return m;
+    }
+    __device__ static __forceinline__ uint32_t src_mask(int q, int t, u64 base)
+    {
+        constexpr uint32_t ALL = (NR >= 32) ? 0xffffffffu : ((1u << NR) - 1u);
+        if (q < K - LOGR) return ((t >> q) & 1) ? ALL : 0u;
+        if (q < K) {
+            uint32_t m = 0;
+#pragma unroll
+            for (int k = 0; k < LOGR; ++k)
+                if (q - (K - LOGR) == k) m = reg_pattern(k);
+            return m;
+        }
+        return ((base >> q) & 1) ? ALL : 0u;
+    }
+    __device__ __forceinline__ void tile(const DiagTab &d, u64 base, int t)
+    {
+        const cx<R> *T = (const cx<R> *)d.tab;
+        w = cmul(t0, cmul(T[d.off2 + ((base >> d.b2) & d.m2)], T[d.off3 + (base >> d.b3)]));
+        neg = 0;
+        for (int k = 0; k < d.npair; ++k) neg ^= src_mask(d.pa[k], t, base) & src_mask(d.pb[k], t, base);
+    }
+    __device__ __forceinline__ cx<R> at(const DiagTab &d, int r) const
+    {
+        const cx<R> v = cmul(w, ((const cx<R> *)d.tab)[d.off1 + r]);
+        return ((neg >> r) & 1) ? cneg(v) : v;
+    }
+};
 
 template <typename R>
 __device__ __forceinline__ cx<R> cmul_conj(cx<R> a, cx<R> d)  // a * conj(d)
@@ -290,11 +351,34 @@ struct BwdChainRev {
     }
 };
 
+// Load a pass's tile in the load assignment.  In pass 0 the loaded values
+// may be multiplied by the layer diagonal (IN_LOAD_DIAG) or replaced by the
+// generated first-layer state (IN_GENERATE).
+template <typename R, int K, int LOGR, bool CONTIG>
+__device__ __forceinline__ void load_tile(cx<R> (&v)[1 << LOGR], const cx<R> *src, u64 base,
+                                          u64 toff, const RegMap<LOGR, CONTIG> &m, int mode,
+                                          P0Diag<R, K, LOGR> &pd, const DiagTab &d, int t)
+{
+    constexpr int NR = 1 << LOGR;
+    if (mode != IN_LOAD) pd.tile(d, base, t);
+    if (mode == IN_GENERATE) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = pd.at(d, r);
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = src[base | toff | m.off(r)];
+        if (mode == IN_LOAD_DIAG) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) v[r] = cmul(v[r], pd.at(d, r));
+        }
+    }
+}
+
 template <typename R, int K, int LOGR, bool CONTIG>
 __global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_pass(void *psi_, FusedArgs a)
 {
-    cx<R> *psi = (cx<R> *)psi_;
     using T = Tile<K, LOGR>;
+    cx<R> *psi = (cx<R> *)psi_;
     __shared__ cx<R> lds[T::LDS];
     const int t = threadIdx.x;
     constexpr int LD = T::lo(0), ST = T::lo(T::NA - 1);
@@ -302,21 +386,12 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_pass(void *psi_, FusedA
     RegMap<LOGR, CONTIG> mld, mst;
     mld.init(a.pos + LD);
     mst.init(a.pos + ST);
+    P0Diag<R, K, LOGR> pd;
+    if (a.in_mode != IN_LOAD) pd.init(a.dt, t);
     for (u64 tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
         const u64 base = tile_base(tile, a);
         cx<R> v[T::NR];
-        if (a.in_mode == IN_GENERATE) {
-#pragma unroll
-            for (int r = 0; r < T::NR; ++r) v[r] = diag_entry<R>(base | toff_ld | mld.off(r), a.gt);
-        } else {
-#pragma unroll
-            for (int r = 0; r < T::NR; ++r) v[r] = psi[base | toff_ld | mld.off(r)];
-            if (a.in_mode == IN_LOAD_DIAG) {
-#pragma unroll
-                for (int r = 0; r < T::NR; ++r)
-                    v[r] = cmul(v[r], diag_entry<R>(base | toff_ld | mld.off(r), a.dt));
-            }
-        }
+        load_tile<R, K, LOGR, CONTIG>(v, psi, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
         fwd_assign<R, K, LOGR, 0>(v, a);
         if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(v, lds, t, a);
 #pragma unroll
@@ -343,9 +418,9 @@ template <typename R, int K, int LOGR, bool CONTIG>
 __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const void *phi_in_, void *phi_,
                                                               void *lam_, FusedArgs a)
 {
+    using T = Tile<K, LOGR>;
     const cx<R> *phi_in = (const cx<R> *)phi_in_;
     cx<R> *phi = (cx<R> *)phi_, *lam = (cx<R> *)lam_;
-    using T = Tile<K, LOGR>;
     __shared__ cx<R> lds[T::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
     const int t = threadIdx.x;
@@ -354,6 +429,10 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const void *phi_in
     RegMap<LOGR, CONTIG> mld, mst;
     mld.init(a.pos + LD);
     mst.init(a.pos + ST);
+    P0Diag<R, K, LOGR> pd, pg;
+    const bool any_diag = a.diag_phi || a.diag_lam;
+    if (any_diag) pd.init(a.dt, t);
+    if (a.phi_gen) pg.init(a.gt, t);
     double accY[K], accZ[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) accY[j] = accZ[j] = 0.0;
@@ -361,11 +440,24 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const void *phi_in
     for (u64 tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
         const u64 base = tile_base(tile, a);
         cx<R> f[T::NR], l[T::NR];
+        if (a.phi_gen) {
+            pg.tile(a.gt, base, t);
 #pragma unroll
-        for (int r = 0; r < T::NR; ++r) {
-            const u64 i = base | toff_ld | mld.off(r);
-            f[r] = a.in_mode == IN_GENERATE ? diag_entry<R>(i, a.gt) : phi_in[i];
-            l[r] = lam[i];
+            for (int r = 0; r < T::NR; ++r) f[r] = pg.at(a.gt, r);
+        } else {
+#pragma unroll
+            for (int r = 0; r < T::NR; ++r) f[r] = phi_in[base | toff_ld | mld.off(r)];
+        }
+#pragma unroll
+        for (int r = 0; r < T::NR; ++r) l[r] = lam[base | toff_ld | mld.off(r)];
+        if (any_diag) {
+            pd.tile(a.dt, base, t);
+#pragma unroll
+            for (int r = 0; r < T::NR; ++r) {
+                const cx<R> d = pd.at(a.dt, r);
+                if (a.diag_phi) f[r] = cmul_conj(f[r], d);
+                if (a.diag_lam) l[r] = cmul_conj(l[r], d);
+            }
         }
         // RZ gradients of the active tile qubits: sum_i z_q(i) Im(conj(lam_i) phi_i)
         {
@@ -395,11 +487,6 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const void *phi_in
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
             const u64 i = base | toff_st | mst.off(r);
-            if (a.post_diag) {
-                const cx<R> d = diag_entry<R>(i, a.dt);
-                f[r] = cmul_conj(f[r], d);
-                l[r] = cmul_conj(l[r], d);
-            }
             if (a.store_phi) phi[i] = f[r];
             if (a.store_lam) lam[i] = l[r];
         }
@@ -414,15 +501,14 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const void *phi_in
 // reverse step equals the loaded tile, which stays in HBM).  RZ gradients of
 // the tile qubits are zero here: Im(conj(D_i psi_i) psi_i) = 0.  When this is
 // the layer's only pass, the load applies the previous layer's diagonal (or
-// generates the first layer's state) and the store undoes that diagonal on
-// lam.
+// generates the first layer's state).
 template <typename R, int K, int LOGR, bool CONTIG>
 __global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_pass(const void *psi_, void *lam_,
                                                                FusedArgs a)
 {
+    using T = Tile<K, LOGR>;
     const cx<R> *psi = (const cx<R> *)psi_;
     cx<R> *lam = (cx<R> *)lam_;
-    using T = Tile<K, LOGR>;
     __shared__ cx<R> lds[T::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
     const int t = threadIdx.x;
@@ -431,6 +517,8 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_pass(const void *psi_,
     RegMap<LOGR, CONTIG> mld, mst;
     mld.init(a.pos + LD);
     mst.init(a.pos + ST);
+    P0Diag<R, K, LOGR> pd;
+    if (a.in_mode != IN_LOAD) pd.init(a.dt, t);
     double accY[K], accZ[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) accY[j] = accZ[j] = 0.0;
@@ -439,18 +527,7 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_pass(const void *psi_,
     for (u64 tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
         const u64 base = tile_base(tile, a);
         cx<R> f[T::NR], l[T::NR];
-        if (a.in_mode == IN_GENERATE) {
-#pragma unroll
-            for (int r = 0; r < T::NR; ++r) f[r] = diag_entry<R>(base | toff_ld | mld.off(r), a.gt);
-        } else {
-#pragma unroll
-            for (int r = 0; r < T::NR; ++r) f[r] = psi[base | toff_ld | mld.off(r)];
-            if (a.in_mode == IN_LOAD_DIAG) {
-#pragma unroll
-                for (int r = 0; r < T::NR; ++r)
-                    f[r] = cmul(f[r], diag_entry<R>(base | toff_ld | mld.off(r), a.dt));
-            }
-        }
+        load_tile<R, K, LOGR, CONTIG>(f, psi, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
         fwd_assign<R, K, LOGR, 0>(f, a);
         if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(f, lds, t, a);
         // energy and lam in the last assignment's layout
@@ -464,16 +541,112 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_pass(const void *psi_,
         bwd_assign<R, K, LOGR, T::NA - 1>(f, l, accY, a);
         if constexpr (T::NA > 1) BwdChainRev<R, K, LOGR, T::NA - 2>::run(f, l, accY, lds, t, a);
 #pragma unroll
-        for (int r = 0; r < T::NR; ++r) {
-            const u64 i = base | toff_ld | mld.off(r);
-            lam[i] = a.post_diag ? cmul_conj(l[r], diag_entry<R>(i, a.dt)) : l[r];
-        }
+        for (int r = 0; r < T::NR; ++r) lam[base | toff_ld | mld.off(r)] = l[r];
     }
     write_partials<R, K>(accY, accZ, true, sh, a);
     const double e = block_sum(eacc, sh);
     if (t == 0) {
         a.epart[blockIdx.x] = e;
         a.epart[a.grid + blockIdx.x] = 0.0;
+    }
+}
+
+
+// ------------------------------------------------------- off-diagonal terms
+
+struct OffArgs {
+    int n;
+    int8_t pos[kMaxTileBits];
+    int nruns;
+    int8_t run_src[kMaxTileBits + 1], run_w[kMaxTileBits + 1], run_dst[kMaxTileBits + 1];
+    u64 ntiles;
+    const OffClass *cls;
+    int c0, c1;
+    const OffTerm *terms;
+    double *epart;
+    int estride;
+};
+
+// One cover pass: the psi tile sits in LDS, so for every class (flip mask x
+// inside the tile) each amplitude reads its partner psi_{i^x} there and adds
+// F(i^x) psi_{i^x} to lam_i; the class factor F is summed over the class's
+// terms in the amplitude precision.  The pass's share of <psi|H|psi> goes to
+// FP64 partials.
+template <typename R, int K, int LOGR>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_offdiag_pass(const void *psi_, void *lam_,
+                                                                  OffArgs a)
+{
+    using T = Tile<K, LOGR>;
+    const cx<R> *psi = (const cx<R> *)psi_;
+    cx<R> *lam = (cx<R> *)lam_;
+    __shared__ cx<R> lds[T::LDS];
+    __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
+    const int t = threadIdx.x;
+    constexpr int LD = T::lo(0);
+    FusedArgs fa;  // only the tile geometry is used
+    for (int j = 0; j < K; ++j) fa.pos[j] = a.pos[j];
+    fa.nruns = a.nruns;
+    for (int k = 0; k < a.nruns; ++k) {
+        fa.run_src[k] = a.run_src[k];
+        fa.run_w[k] = a.run_w[k];
+        fa.run_dst[k] = a.run_dst[k];
+    }
+    const u64 toff = thread_off<K, LOGR>(t, LD, fa);
+    RegMap<LOGR, false> m;
+    m.init(a.pos + LD);
+    double er = 0.0, ei = 0.0;
+    for (u64 tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const u64 base = tile_base(tile, fa);
+        cx<R> v[T::NR], acc[T::NR];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < T::NR; ++r) {
+            v[r] = psi[base | toff | m.off(r)];
+            lds[T::pad(T::u_of(t, r, LD))] = v[r];
+            acc[r].re = acc[r].im = R(0);
+        }
+        __syncthreads();
+        for (int c = a.c0; c < a.c1; ++c) {
+            const OffClass C = a.cls[c];
+            R A[T::NR], B[T::NR];
+#pragma unroll
+            for (int r = 0; r < T::NR; ++r) A[r] = B[r] = R(0);
+            for (int k = C.t0; k < C.t1; ++k) {
+                const OffTerm tm = a.terms[k];
+                const R cc = (R)tm.c;
+#pragma unroll
+                for (int r = 0; r < T::NR; ++r) {
+                    const u64 ip = (base | toff | m.off(r)) ^ C.x;
+                    const R sg = (__popcll(ip & tm.z) & 1) ? -cc : cc;
+                    if (tm.ph & 1) B[r] += (tm.ph & 2) ? -sg : sg;
+                    else A[r] += (tm.ph & 2) ? -sg : sg;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < T::NR; ++r) {
+                const cx<R> pv = lds[T::pad(T::u_of(t, r, LD) ^ (int)C.xu)];
+                acc[r].re += A[r] * pv.re - B[r] * pv.im;
+                acc[r].im += A[r] * pv.im + B[r] * pv.re;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < T::NR; ++r) {
+            er += (double)v[r].re * acc[r].re + (double)v[r].im * acc[r].im;
+            ei += (double)v[r].re * acc[r].im - (double)v[r].im * acc[r].re;
+            if (lam) {
+                const u64 i = base | toff | m.off(r);
+                cx<R> o = lam[i];
+                o.re += acc[r].re;
+                o.im += acc[r].im;
+                lam[i] = o;
+            }
+        }
+    }
+    const double tr = block_sum(er, sh);
+    const double ti = block_sum(ei, sh);
+    if (t == 0) {
+        a.epart[blockIdx.x] += tr;
+        a.epart[a.estride + blockIdx.x] += ti;
     }
 }
 
@@ -496,10 +669,15 @@ struct TabArgs {
     int rot_layers;
     int cz_layers;          // layers that carry the CZ ladder
     int cz;                 // 1 linear CZ, 2 circular CZ, 0 none
-    int b[4];               // chunk bounds 0, b1, b2, n
-    int off[4];             // entry offsets of the chunks within a table set
+    int b[5];               // chunk bounds 0, b1, b2, b3, n
+    int off[5];             // entry offsets of the chunks within a table set
     size_t stride;          // bytes per layer
 };
+
+__device__ __forceinline__ int chunk_of(const TabArgs &ta, int w)
+{
+    return w < ta.off[1] ? 0 : (w < ta.off[2] ? 1 : (w < ta.off[3] ? 2 : 3));
+}
 
 // in-chunk phase of RZ and CZ for entry v of chunk c in layer l:
 // prod_{q in chunk} exp(-+ i phi_q / 2), and the parity of the CZ pairs
@@ -526,12 +704,12 @@ __device__ __forceinline__ void chunk_phase(const double *theta, const TabArgs &
 template <typename R>
 __global__ void k_diag_tables(const double *theta, TabArgs ta, char *dtab)
 {
-    const int per = ta.off[3];
+    const int per = ta.off[4];
     const int64_t total = (int64_t)per * ta.rot_layers;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int l = (int)(e / per), w = (int)(e % per);
-        const int c = w < ta.off[1] ? 0 : (w < ta.off[2] ? 1 : 2);
+        const int c = chunk_of(ta, w);
         const u64 v = (u64)(w - ta.off[c]);
         double ang;
         int par;
@@ -555,9 +733,9 @@ __global__ void k_diag_tables(const double *theta, TabArgs ta, char *dtab)
 template <typename R>
 __global__ void k_init_tables(const double *theta, TabArgs ta, cx<R> *gtab, cx<R> *g0tab)
 {
-    const int per = ta.off[3];
+    const int per = ta.off[4];
     for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < per; w += gridDim.x * blockDim.x) {
-        const int c = w < ta.off[1] ? 0 : (w < ta.off[2] ? 1 : 2);
+        const int c = chunk_of(ta, w);
         const u64 v = (u64)(w - ta.off[c]);
         double ang;
         int par;
@@ -657,34 +835,39 @@ void fill_runs(FusedArgs &a, const PassPlan &pp, int K, int n)
     }
 }
 
-// table set of layer `layer` (cz: whether this layer carries the CZ ladder)
+// table set at `tab` for a layer (cz_layer: whether it carries the CZ ladder)
 DiagTab make_diagtab(const gv_ansatz &an, const Chunks &ch, const void *tab, bool cz_layer)
 {
     DiagTab d;
     memset(&d, 0, sizeof(d));
     d.tab = tab;
-    d.b1 = ch.b1;
-    d.b2 = ch.b2;
-    d.s1off = ch.size0;
-    d.s2off = ch.size0 + ch.size1;
-    d.m0 = (u64)ch.size0 - 1;
-    d.m1 = (u64)ch.size1 - 1;
-    d.nx = 0;
+    d.b1 = ch.b[1];
+    d.b2 = ch.b[2];
+    d.b3 = ch.b[3];
+    d.off1 = ch.off[1];
+    d.off2 = ch.off[2];
+    d.off3 = ch.off[3];
+    d.m0 = (u64)(ch.off[1] - ch.off[0]) - 1;
+    d.m1 = (u64)(ch.off[2] - ch.off[1]) - 1;
+    d.m2 = (u64)(ch.off[3] - ch.off[2]) - 1;
+    d.npair = 0;
     const int n = an.n;
     const bool cz = (an.ent == GV_ENT_CZ_LINEAR || an.ent == GV_ENT_CZ_CIRCULAR) && cz_layer;
     if (!cz) return d;
-    if (ch.b1 < n) {
-        d.xa[d.nx] = (int8_t)(ch.b1 - 1);
-        d.xb[d.nx++] = (int8_t)ch.b1;
+    // CZ(q-1, q) across every chunk bound q strictly inside [1, n)
+    for (int c = 1; c <= 3; ++c) {
+        const int q = ch.b[c];
+        if (q <= 0 || q >= n) continue;
+        bool dup = false;
+        for (int k = 0; k < d.npair; ++k) dup |= d.pb[k] == q;
+        if (dup) continue;
+        d.pa[d.npair] = (int8_t)(q - 1);
+        d.pb[d.npair++] = (int8_t)q;
     }
-    if (ch.b2 < n) {
-        d.xa[d.nx] = (int8_t)(ch.b2 - 1);
-        d.xb[d.nx++] = (int8_t)ch.b2;
-    }
-    // the circular pair (n-1, 0) lies inside one chunk only when there is one chunk
-    if (an.ent == GV_ENT_CZ_CIRCULAR && n > 2 && ch.b1 < n) {
-        d.xa[d.nx] = (int8_t)(n - 1);
-        d.xb[d.nx++] = 0;
+    // the circular pair (n-1, 0) lies inside a chunk only when chunk 0 holds every bit
+    if (an.ent == GV_ENT_CZ_CIRCULAR && n > 2 && ch.b[1] < n) {
+        d.pa[d.npair] = (int8_t)(n - 1);
+        d.pb[d.npair++] = 0;
     }
     return d;
 }
@@ -702,14 +885,10 @@ TabArgs make_tab_args(const gv_ansatz &an, const Chunks &ch, size_t stride)
     ta.rot_layers = rot_layers(an);
     ta.cz_layers = an.layers;
     ta.cz = an.ent == GV_ENT_CZ_LINEAR ? 1 : (an.ent == GV_ENT_CZ_CIRCULAR ? 2 : 0);
-    ta.b[0] = 0;
-    ta.b[1] = ch.b1;
-    ta.b[2] = ch.b2;
-    ta.b[3] = an.n;
-    ta.off[0] = 0;
-    ta.off[1] = ch.size0;
-    ta.off[2] = ch.size0 + ch.size1;
-    ta.off[3] = ch.size0 + ch.size1 + ch.size2;
+    for (int c = 0; c < 5; ++c) {
+        ta.b[c] = ch.b[c];
+        ta.off[c] = ch.off[c];
+    }
     ta.stride = stride;
     return ta;
 }
@@ -787,17 +966,17 @@ hipError_t fused_build_tables(int prec, const gv_ansatz &an, const Chunks &ch,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     TabArgs ta = make_tab_args(an, ch, t.dtab_stride);
-    const int64_t total = (int64_t)ta.off[3] * ta.rot_layers;
+    const int64_t total = (int64_t)ta.off[4] * ta.rot_layers;
     const int g = (int)((total + 255) / 256 < 2048 ? (total + 255) / 256 : 2048);
     if (prec == GV_C64) {
         hipLaunchKernelGGL(k_diag_tables<float>, dim3(g), dim3(256), 0, s, theta, ta,
                            (char *)t.dtab);
-        hipLaunchKernelGGL(k_init_tables<float>, dim3((ta.off[3] + 255) / 256), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_init_tables<float>, dim3((ta.off[4] + 255) / 256), dim3(256), 0, s,
                            theta, ta, (cx<float> *)t.gtab, (cx<float> *)t.g0tab);
     } else {
         hipLaunchKernelGGL(k_diag_tables<double>, dim3(g), dim3(256), 0, s, theta, ta,
                            (char *)t.dtab);
-        hipLaunchKernelGGL(k_init_tables<double>, dim3((ta.off[3] + 255) / 256), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_init_tables<double>, dim3((ta.off[4] + 255) / 256), dim3(256), 0, s,
                            theta, ta, (cx<double> *)t.gtab, (cx<double> *)t.g0tab);
     }
     return hipGetLastError();
@@ -823,10 +1002,11 @@ hipError_t fused_forward_pass(int prec, void *psi, const gv_ansatz &an, const Ti
                               int pass, int layer, int in_mode, const Chunks &ch,
                               const FusedTables &t, hipStream_t s)
 {
+    if (in_mode != IN_LOAD && pass != 0) return hipErrorInvalidValue;
     FusedArgs a = base_args(an, plan, pass, layer, t);
     a.in_mode = in_mode;
     if (in_mode == IN_LOAD_DIAG) a.dt = layer_tab(an, ch, t, layer - 1);
-    if (in_mode == IN_GENERATE) a.gt = make_diagtab(an, ch, t.gtab, 0 < an.layers);
+    if (in_mode == IN_GENERATE) a.dt = make_diagtab(an, ch, t.gtab, 0 < an.layers);
     const int grid = fused_grid(prec, plan, an.n);
     GV_LAUNCH_K(k_fwd_pass, prec, grid, plan.K, psi, a);
     return hipGetLastError();
@@ -837,11 +1017,13 @@ hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *la
                                const BwdFlags &fl, const Chunks &ch, const FusedTables &t,
                                double *part, int grid, hipStream_t s)
 {
+    if ((fl.phi_generate || fl.diag_phi || fl.diag_lam) && pass != 0) return hipErrorInvalidValue;
     FusedArgs a = base_args(an, plan, pass, layer, t);
-    a.in_mode = fl.phi_generate ? IN_GENERATE : IN_LOAD;
+    a.phi_gen = fl.phi_generate;
     if (fl.phi_generate) a.gt = make_diagtab(an, ch, t.g0tab, false);
-    a.post_diag = fl.post_diag;
-    if (fl.post_diag) a.dt = layer_tab(an, ch, t, layer - 1);
+    a.diag_phi = fl.diag_phi;
+    a.diag_lam = fl.diag_lam;
+    if (fl.diag_phi || fl.diag_lam) a.dt = layer_tab(an, ch, t, layer);
     a.store_phi = fl.store_phi;
     a.store_lam = fl.store_lam;
     a.part = part;
@@ -852,14 +1034,14 @@ hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *la
 
 hipError_t fused_turnaround(int prec, const void *psi, void *lam, const double *hdiag,
                             const gv_ansatz &an, const TilePlan &plan, int pass, int layer,
-                            int in_mode, int post_diag, const Chunks &ch, const FusedTables &t,
-                            double *part, double *epart, int grid, hipStream_t s)
+                            int in_mode, const Chunks &ch, const FusedTables &t, double *part,
+                            double *epart, int grid, hipStream_t s)
 {
+    if (in_mode != IN_LOAD && pass != 0) return hipErrorInvalidValue;
     FusedArgs a = base_args(an, plan, pass, layer, t);
     a.in_mode = in_mode;
-    if (in_mode == IN_LOAD_DIAG || post_diag) a.dt = layer_tab(an, ch, t, layer - 1);
-    if (in_mode == IN_GENERATE) a.gt = make_diagtab(an, ch, t.gtab, 0 < an.layers);
-    a.post_diag = post_diag;
+    if (in_mode == IN_LOAD_DIAG) a.dt = layer_tab(an, ch, t, layer - 1);
+    if (in_mode == IN_GENERATE) a.dt = make_diagtab(an, ch, t.gtab, 0 < an.layers);
     a.hdiag = hdiag;
     a.part = part;
     a.epart = epart;
@@ -901,6 +1083,60 @@ hipError_t cnot_ladder_gather(int prec, const void *src, void *dst, const gv_ans
         hipLaunchKernelGGL(k_cnot_gather<double>, dim3(elem_grid(dim)), dim3(256), 0, s,
                            (const cx<double> *)src, (cx<double> *)dst, n, circular, inverse, d,
                            with_diag);
+    return hipGetLastError();
+}
+
+hipError_t offdiag_pass(int prec, const void *psi, void *lam, int n, int K, const OffPass &op,
+                        const OffClass *cls, const OffTerm *terms, double *epart, int estride,
+                        hipStream_t s)
+{
+    OffArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n = n;
+    PassPlan pp;
+    for (int j = 0; j < K; ++j) pp.pos[j] = op.pos[j];
+    pp.active = 0;
+    FusedArgs fa;
+    memset(&fa, 0, sizeof(fa));
+    fill_runs(fa, pp, K, n);
+    for (int j = 0; j < K; ++j) a.pos[j] = op.pos[j];
+    a.nruns = fa.nruns;
+    for (int k = 0; k < fa.nruns; ++k) {
+        a.run_src[k] = fa.run_src[k];
+        a.run_w[k] = fa.run_w[k];
+        a.run_dst[k] = fa.run_dst[k];
+    }
+    a.ntiles = 1ull << (n - K);
+    a.cls = cls;
+    a.c0 = op.c0;
+    a.c1 = op.c1;
+    a.terms = terms;
+    a.epart = epart;
+    a.estride = estride;
+    const u64 want = prec == GV_C64 ? 1024 : 512;
+    const int grid = (int)(a.ntiles < want ? a.ntiles : want);
+    if (grid > estride) return hipErrorInvalidValue;
+    switch (K) {
+    case 12:
+        if (prec == GV_C64)
+            hipLaunchKernelGGL((k_offdiag_pass<float, 12, 4>), dim3(grid), dim3(256), 0, s, psi, lam, a);
+        else
+            hipLaunchKernelGGL((k_offdiag_pass<double, 12, 4>), dim3(grid), dim3(256), 0, s, psi, lam, a);
+        break;
+    case 10:
+        if (prec == GV_C64)
+            hipLaunchKernelGGL((k_offdiag_pass<float, 10, 4>), dim3(grid), dim3(64), 0, s, psi, lam, a);
+        else
+            hipLaunchKernelGGL((k_offdiag_pass<double, 10, 4>), dim3(grid), dim3(64), 0, s, psi, lam, a);
+        break;
+    case 8:
+        if (prec == GV_C64)
+            hipLaunchKernelGGL((k_offdiag_pass<float, 8, 3>), dim3(grid), dim3(32), 0, s, psi, lam, a);
+        else
+            hipLaunchKernelGGL((k_offdiag_pass<double, 8, 3>), dim3(grid), dim3(32), 0, s, psi, lam, a);
+        break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

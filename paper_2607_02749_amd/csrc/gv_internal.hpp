@@ -29,6 +29,27 @@ struct QwcGroup {
     std::vector<int64_t> terms;            // indices into the off-diagonal arrays
 };
 
+// Off-diagonal terms that flip the same index bits x form a class: on the
+// amplitude pair (i, i ^ x) their sum acts as one complex factor
+// F(i ^ x) = sum_k c_k i^{ph_k} (-1)^{popcount((i ^ x) & z_k)}.
+struct OffClass {
+    u64 x;          // flip mask
+    uint32_t xu;    // the same mask in the tile-local bits of its cover pass
+    int32_t t0, t1; // its terms [t0, t1) in the term table
+    int32_t pad;
+};
+struct OffTerm {
+    u64 z;
+    double c;
+    int32_t ph;     // popcount(x & z) mod 4: the i^ph factor of P(x, z)
+    int32_t pad;
+};
+// A cover pass: a tile whose bits hold every flip bit of its classes.
+struct OffPass {
+    int8_t pos[kMaxTileBits];
+    int c0, c1;     // classes [c0, c1)
+};
+
 }  // namespace gv
 
 struct gv_pauli_s {
@@ -40,13 +61,19 @@ struct gv_pauli_s {
     std::vector<uint64_t> ox, oz;
     std::vector<double> oc;
     std::vector<gv::QwcGroup> groups;
+    // off-diagonal classes in cover-pass order (built by prepare for a tile
+    // size) and the terms no cover pass holds (applied one by one)
+    std::vector<gv::OffClass> classes;
+    std::vector<gv::OffTerm> class_terms;
+    std::vector<gv::OffPass> off_passes;
+    std::vector<int64_t> loose_terms;
+    int cover_K = 0, cover_C = 0;
+    gv::OffClass *dev_cls = nullptr;
+    gv::OffTerm *dev_terms = nullptr;
     // device form (borrowed caller memory)
     void *dev = nullptr;
     size_t dev_bytes = 0;
     double *diag = nullptr;         // 2^n doubles
-    uint64_t *dev_ox = nullptr;     // off-diagonal tables
-    uint64_t *dev_oz = nullptr;
-    double *dev_oc = nullptr;
     bool prepared = false;
 };
 
@@ -106,12 +133,13 @@ struct TilePlan {
 
 bool make_tile_plan(int n, int K, int C, TilePlan *out);
 
-// Diagonal-table chunks: bits [0,b1), [b1,b2), [b2,n)
+// Diagonal-table chunks: chunk c covers index bits [b[c], b[c+1]); its
+// entries start at off[c] (off[4] = entries per layer)
 struct Chunks {
-    int b1, b2;
-    int size0, size1, size2;    // entries per table
+    int b[5];
+    int off[5];
 };
-Chunks make_chunks(int n);
+Chunks make_chunks(int n, int K, int LOGR);
 
 // Work-buffer layout for gv_energy_grad / gv_energy.
 struct WorkLayout {
@@ -170,6 +198,13 @@ hipError_t reduce_energy(const double *epart, int grid, double *energy, hipStrea
 
 hipError_t copy_vector(void *dst, const void *src, size_t bytes, hipStream_t s);
 
+// one cover pass of off-diagonal classes: lam += (sum of the classes) psi
+// (lam may be NULL); energy partials epart[b], epart[estride + b] += the
+// pass's contribution to <psi|H|psi>
+hipError_t offdiag_pass(int prec, const void *psi, void *lam, int n, int K, const OffPass &op,
+                        const OffClass *cls, const OffTerm *terms, double *epart, int estride,
+                        hipStream_t s);
+
 // fused engine
 struct FusedTables {
     const double *ry;    // [P][2]: cos, sin of half angles
@@ -179,8 +214,9 @@ struct FusedTables {
     void *g0tab;         // R_0|0...0> tables
 };
 struct BwdFlags {
-    int phi_generate = 0;   // phi = R_0|0...0> from tables instead of a load
-    int post_diag = 0;      // undo D_{layer-1} before the store
+    int phi_generate = 0;   // phi = R_0|0...0> from tables instead of a load (pass 0)
+    int diag_phi = 0;       // undo the layer's diagonal on phi as it loads (pass 0)
+    int diag_lam = 0;       // undo the layer's diagonal on lam as it loads (pass 0)
     int store_phi = 1, store_lam = 1;
 };
 // forward pass input modes
@@ -198,8 +234,8 @@ hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *la
                                double *part, int grid, hipStream_t s);
 hipError_t fused_turnaround(int prec, const void *psi, void *lam, const double *hdiag,
                             const gv_ansatz &a, const TilePlan &plan, int pass, int layer,
-                            int in_mode, int post_diag, const Chunks &ch, const FusedTables &t,
-                            double *part, double *epart, int grid, hipStream_t s);
+                            int in_mode, const Chunks &ch, const FusedTables &t, double *part,
+                            double *epart, int grid, hipStream_t s);
 hipError_t fused_diag_apply(int prec, void *v0, void *v1, const gv_ansatz &a, const Chunks &ch,
                             const FusedTables &t, int layer, int conj, hipStream_t s);
 // CNOT ladder gather; with t != NULL the layer diagonal is fused in

@@ -174,7 +174,7 @@ class State:
 
     # per-kernel-class timing (HIP events on the state's stream)
     PROF_KINDS = {"forward_pass": 0, "backward_pass": 1, "energy": 2, "init": 3,
-                  "plain_gate": 4, "other": 5}
+                  "plain_gate": 4, "other": 5, "offdiag": 6}
 
     def profile(self, enable: bool = True):
         _check(lib().gv_profile_enable(self.handle, int(enable)), "gv_profile_enable")

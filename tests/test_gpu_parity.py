@@ -212,3 +212,20 @@ def test_z_only_turnaround(n, layers, mode):
     for precision in ("c128", "c64"):
         e, g, _, _ = run_gpu(inst, precision, mode=mode)
         check(e, g, *oracle_eg(inst), precision, f"zonly n={n} L={layers} {mode}")
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_random_pauli_strings(precision):
+    # arbitrary flip masks, including ones wider than a tile (applied term by term)
+    rng = np.random.default_rng(77)
+    n = 14
+    m = 60
+    x = rng.integers(0, 1 << n, size=m, dtype=np.uint64)
+    x[:5] = 0
+    z = rng.integers(0, 1 << n, size=m, dtype=np.uint64)
+    c = rng.normal(size=m)
+    th = rng.uniform(-np.pi, np.pi, 2 * n * 3)
+    inst = synth.Instance(n=n, layers=3, ent=synth.ENT_CZ_LINEAR, final_rotation=0, x=x, z=z, c=c,
+                          theta=th)
+    e, g, _, _ = run_gpu(inst, precision)
+    check(e, g, *oracle_eg(inst), precision, "random strings")
