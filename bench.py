@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mode", default="uncompute", choices=["uncompute", "checkpoint", "recompute"])
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also time a 2 GiB device-to-device copy (the practical HBM ceiling, and "
+                         "the reference kernel for scaling byte counters)")
     return ap.parse_args()
 
 
@@ -141,6 +144,23 @@ def main():
     st.profile(False)
     log("timed", args.steps, "steps in", wall, "s")
 
+    copy = None
+    if args.copy_probe:
+        src = torch.empty(1 << 31, dtype=torch.uint8, device=st.device)
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / 5
+        copy = {"bytes": 2 * src.numel(), "ms": ms, "GBps": 2 * src.numel() / (ms * 1e-3) / 1e9}
+        del src, dst
+
     value = args.steps / wall
     kinds = {k: v for k, v in prof.items() if v[0] > 0}
     dom = max(kinds, key=lambda k: kinds[k][1])
@@ -213,6 +233,7 @@ def main():
         "kernels": breakdown,
         "parity_vs_oracle": parity,
         "plain_c128": plain,
+        "copy_probe": copy,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

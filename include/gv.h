@@ -154,6 +154,11 @@ gv_status gv_pauli_sum_device_bytes(gv_pauli_sum h, size_t *bytes);
  * borrowed until gv_pauli_sum_destroy or the next prepare. */
 gv_status gv_pauli_sum_prepare(gv_pauli_sum h, gv_state st, void *dev, size_t bytes);
 
+/* The same without a state: build the device form for states of precision
+ * `prec` on `engine` (and for batches), on `stream`. */
+gv_status gv_pauli_sum_prepare_for(gv_pauli_sum h, gv_precision prec, gv_engine engine,
+                                   void *stream, void *dev, size_t bytes);
+
 /* <psi|H|psi> of the state's current psi.  energy_dev: 2 device doubles
  * (real part, imaginary part; the latter is rounding noise for real c_k).
  * Needs work memory for reduction partials (FUSED: always; PLAIN: >= 1 MiB). */
@@ -171,6 +176,53 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *params_dev,
                          gv_grad_mode mode, double *energy_dev, double *grad_dev);
 
 /* ------------------------------------------------------------------------
+ * Batches: Graph-VQE optimises qubit blocks concurrently, each block's
+ * restricted cost being the full energy with only that block's parameters
+ * free (Sec. IV-D, Eq. 11), and computes gradients only for a block's
+ * parameters.  A batch runs many such independent evaluations -- each with
+ * its own ansatz size, angles, Hamiltonian and qubit block -- in one
+ * persistent kernel: each block of the grid takes whole instances from an
+ * atomic queue (largest first by default) and runs their forward sweep,
+ * energy and reverse sweep.  The grid and order come from gv_batch_tuning
+ * (an autotuner picks them; see paper_2607_02749_amd/autotune.py).
+ * Limits: 12 <= n <= 30; CZ or no entangler; every Hamiltonian prepared with
+ * gv_pauli_sum_prepare_for(h, prec, GV_ENGINE_FUSED, ...).
+ */
+typedef struct {
+    gv_ansatz ansatz;
+    const double *params_dev;  /* P = 2 n (layers + final_rotation) device doubles */
+    gv_pauli_sum h;            /* prepared for the batch precision, fused engine */
+    uint64_t qubit_mask;       /* gradient for the RY/RZ angles of these qubits */
+    double *energy_dev;        /* out: 2 device doubles (re, im) */
+    double *grad_dev;          /* out: P device doubles, 0 outside qubit_mask */
+} gv_instance;
+
+typedef struct {
+    int32_t blocks_per_cu;     /* persistent blocks per compute unit, 1..8 (default 2) */
+    int32_t order;             /* 0: largest instance first (default), 1: input order */
+} gv_batch_tuning;
+
+typedef struct gv_batch_s *gv_batch;
+
+/* Workspace bytes for a batch (per-instance states, tables, descriptors). */
+gv_status gv_batch_query(int32_t count, const gv_instance *inst, gv_precision prec,
+                         size_t *work_bytes);
+/* Plan a batch over caller memory `work` (256-byte aligned, >= query).
+ * tuning may be NULL.  use_graph != 0 records the launches once as a HIP
+ * graph that gv_batch_run replays; between runs the caller may rewrite the
+ * parameter arrays in place.  The instance array is copied; the pointers in
+ * it must stay valid for the batch's lifetime. */
+gv_status gv_batch_create(int32_t count, const gv_instance *inst, gv_precision prec,
+                          const gv_batch_tuning *tuning, void *work_dev, size_t work_bytes,
+                          void *stream, int32_t use_graph, gv_batch *out);
+/* Enqueue one evaluation of every instance on the batch's stream. */
+gv_status gv_batch_run(gv_batch b);
+gv_status gv_batch_destroy(gv_batch b);
+/* create + run + destroy (no graph). */
+gv_status gv_batch_energy_grad(int32_t count, const gv_instance *inst, gv_precision prec,
+                               void *work_dev, size_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Per-kernel-class timing.  While enabled, every launch of the state's
  * compute calls is bracketed by HIP events recorded on the state's stream,
  * and the algorithmic bytes of the launch (the reads and writes the step
@@ -186,7 +238,8 @@ typedef enum {
     GV_PROF_PLAIN_GATE = 4,     /* plain engine gate or reverse step */
     GV_PROF_OTHER = 5,          /* tables, reductions, copies, gathers */
     GV_PROF_OFFDIAG = 6,        /* off-diagonal terms: lambda += H_off psi */
-    GV_PROF_KINDS = 7
+    GV_PROF_FIRST_LAYER = 7,    /* first rotation layer's gradients from lambda */
+    GV_PROF_KINDS = 8
 } gv_prof_kind;
 
 gv_status gv_profile_enable(gv_state st, int32_t enable);

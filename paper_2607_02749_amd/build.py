@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgv.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["gv_api.cpp", "gv_plain.hip", "gv_ham.hip", "gv_fused.hip"]
+SOURCES = ["gv_api.cpp", "gv_batch.cpp", "gv_plain.hip", "gv_ham.hip", "gv_fused.hip"]
 
 ARCH = "gfx950"
 FLAGS = [

@@ -669,16 +669,17 @@ gv_status gv_pauli_sum_device_bytes(gv_pauli_sum h, size_t *bytes)
     return GV_OK;
 }
 
-gv_status gv_pauli_sum_prepare(gv_pauli_sum h, gv_state st, void *dev, size_t bytes)
+static gv_status prepare_impl(gv_pauli_sum h, gv_precision prec, gv_engine engine, hipStream_t s,
+                              void *dev, size_t bytes)
 {
-    if (!h || !st || !dev) return set_error(GV_EINVAL, "NULL argument");
-    if (h->n != st->n) return set_error(GV_ESTATE, "pauli sum n=%d but state n=%d", h->n, st->n);
+    if (!dev) return set_error(GV_EINVAL, "NULL buffer");
+    if (prec != GV_C64 && prec != GV_C128) return set_error(GV_EINVAL, "precision %d", prec);
+    if (engine != GV_ENGINE_FUSED && engine != GV_ENGINE_PLAIN) return set_error(GV_EINVAL, "engine");
     if (!aligned(dev)) return set_error(GV_EINVAL, "buffer must be %zu-byte aligned", kAlign);
     size_t odiag, ocls, oterms, osz, osc, total;
     pauli_layout(h, &odiag, &ocls, &oterms, &osz, &osc, &total);
     if (bytes < total) return set_error(GV_ESIZE, "buffer %zu bytes < %zu", bytes, total);
     char *base = (char *)dev;
-    hipStream_t s = st->stream;
     h->dev = dev;
     h->dev_bytes = bytes;
     h->diag = (double *)(base + odiag);
@@ -686,9 +687,9 @@ gv_status gv_pauli_sum_prepare(gv_pauli_sum h, gv_state st, void *dev, size_t by
     h->dev_terms = (OffTerm *)(base + oterms);
     h->prepared = false;
     const int n = h->n;
-    if (fused_ok(st->engine, n)) {
+    if (fused_ok(engine, n)) {
         const int K = choose_K(n);
-        build_cover(h, K, choose_C(st->prec, K));
+        build_cover(h, K, choose_C(prec, K));
     } else {
         h->classes.clear();
         h->class_terms.clear();
@@ -724,6 +725,20 @@ gv_status gv_pauli_sum_prepare(gv_pauli_sum h, gv_state st, void *dev, size_t by
     if (gv_status r = check_hip(hipStreamSynchronize(s), "prepare sync")) return r;
     h->prepared = true;
     return GV_OK;
+}
+
+gv_status gv_pauli_sum_prepare(gv_pauli_sum h, gv_state st, void *dev, size_t bytes)
+{
+    if (!h || !st) return set_error(GV_EINVAL, "NULL argument");
+    if (h->n != st->n) return set_error(GV_ESTATE, "pauli sum n=%d but state n=%d", h->n, st->n);
+    return prepare_impl(h, st->prec, st->engine, st->stream, dev, bytes);
+}
+
+gv_status gv_pauli_sum_prepare_for(gv_pauli_sum h, gv_precision prec, gv_engine engine,
+                                   void *stream, void *dev, size_t bytes)
+{
+    if (!h) return set_error(GV_EINVAL, "NULL argument");
+    return prepare_impl(h, prec, engine, (hipStream_t)stream, dev, bytes);
 }
 
 gv_status gv_energy(gv_state st, gv_pauli_sum h, double *energy)
@@ -865,6 +880,14 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
             if (phi_post)
                 if (gv_status r = cnot_step(st, *a, c, l, psi, 1)) return r;
             phi_post = lam_post = false;
+        }
+        if (phi_gen && npl > 0) {  // layer 0: one read of lam gives every gradient of the layer
+            ProfScope ps(st, GV_PROF_FIRST_LAYER, (double)vb);
+            if (gv_status r = check_hip(fused_layer0_grad(st->prec, lam, *a, c.plan, lam_post ? 1 : 0,
+                                                          c.ch, c.tabs, part, c.w.grid, s),
+                                        "first-layer gradients"))
+                return r;
+            break;
         }
         // does layer l-1 read phi from the state buffer?
         const bool next_phi_needed = l - 1 >= 1 && mode == GV_GRAD_UNCOMPUTE;

@@ -1,0 +1,282 @@
+// gv_batch.cpp -- the batch ABI: many uneven instances (Graph-VQE's
+// concurrent block updates, Sec. IV-D, Eq. 11) in one persistent kernel,
+// optionally recorded once as a HIP graph and replayed.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "gv_internal.hpp"
+
+struct gv_batch_s {
+    int count = 0;
+    gv_precision prec = GV_C64;
+    void *work = nullptr;
+    size_t work_bytes = 0;
+    hipStream_t stream = nullptr;
+    gv::BatchInst *dev_insts = nullptr;
+    int *dev_order = nullptr;
+    unsigned *counter = nullptr;
+    int grid = 0;
+    bool graph = false;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace gv {
+
+namespace {
+
+constexpr int kBatchK = 12, kBatchLogR = 4;
+
+struct BatchLayout {
+    size_t counter, insts, order, total;
+    std::vector<size_t> offp, ry, dtab, gtab, g0tab, psi, lam;
+    std::vector<size_t> stride;
+};
+
+gv_status check_instances(int count, const gv_instance *inst, gv_precision prec)
+{
+    if (count < 0) return set_error(GV_EINVAL, "count < 0");
+    if (count > 0 && !inst) return set_error(GV_EINVAL, "instances is NULL");
+    if (prec != GV_C64 && prec != GV_C128) return set_error(GV_EINVAL, "precision %d", prec);
+    const int C = std::min(kBatchK - 1, prec == GV_C64 ? 4 : 3);
+    for (int i = 0; i < count; ++i) {
+        const gv_instance &I = inst[i];
+        const gv_ansatz &a = I.ansatz;
+        if (a.n < kBatchK || a.n > 30)
+            return set_error(GV_EUNSUPPORTED, "instance %d: n=%d outside %d..30", i, a.n, kBatchK);
+        if (a.layers < 0 || a.layers > 4096 || (a.final_rotation != 0 && a.final_rotation != 1))
+            return set_error(GV_EINVAL, "instance %d: bad ansatz", i);
+        if (a.layers + a.final_rotation < 1)
+            return set_error(GV_EUNSUPPORTED, "instance %d: no rotation layer", i);
+        if (a.ent != GV_ENT_NONE && a.ent != GV_ENT_CZ_LINEAR && a.ent != GV_ENT_CZ_CIRCULAR)
+            return set_error(GV_EUNSUPPORTED, "instance %d: batches take CZ or no entangler", i);
+        if (!I.params_dev || !I.energy_dev || !I.grad_dev || !I.h)
+            return set_error(GV_EINVAL, "instance %d: NULL pointer", i);
+        if (a.n < 64 && (I.qubit_mask >> a.n))
+            return set_error(GV_EINVAL, "instance %d: qubit mask bit >= n", i);
+        const gv_pauli_s *h = I.h;
+        if (!h->prepared || h->n != a.n)
+            return set_error(GV_ESTATE, "instance %d: Hamiltonian not prepared for n=%d", i, a.n);
+        if (!h->loose_terms.empty())
+            return set_error(GV_EUNSUPPORTED, "instance %d: off-diagonal terms too wide for a tile", i);
+        if (!h->ox.empty() && (h->cover_K != kBatchK || h->cover_C != C))
+            return set_error(GV_ESTATE, "instance %d: Hamiltonian prepared for another precision", i);
+    }
+    return GV_OK;
+}
+
+BatchLayout batch_layout(int count, const gv_instance *inst, gv_precision prec)
+{
+    BatchLayout L;
+    const size_t s = amp_bytes(prec);
+    size_t off = 0;
+    L.counter = off;
+    off += kAlign;
+    L.insts = off;
+    off += align_up((size_t)count * sizeof(BatchInst) + 8);
+    L.order = off;
+    off += align_up((size_t)count * sizeof(int) + 8);
+    for (int i = 0; i < count; ++i) {
+        const gv_ansatz &a = inst[i].ansatz;
+        const Chunks ch = make_chunks(a.n, kBatchK, kBatchLogR);
+        const size_t stride = align_up((size_t)ch.off[4] * s);
+        const int R = a.layers + a.final_rotation;
+        L.stride.push_back(stride);
+        L.offp.push_back(off);
+        off += align_up(inst[i].h->off_passes.size() * sizeof(BatchOffPass) + 8);
+        L.ry.push_back(off);
+        off += align_up((size_t)2 * a.n * R * 2 * sizeof(double) + 8);
+        L.dtab.push_back(off);
+        off += stride * (size_t)R;
+        L.gtab.push_back(off);
+        off += stride;
+        L.g0tab.push_back(off);
+        off += stride;
+        L.psi.push_back(off);
+        off += align_up(((size_t)1 << a.n) * s);
+        L.lam.push_back(off);
+        off += align_up(((size_t)1 << a.n) * s);
+    }
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+}  // namespace gv
+
+using namespace gv;
+
+extern "C" {
+
+gv_status gv_batch_query(int32_t count, const gv_instance *inst, gv_precision prec,
+                         size_t *work_bytes)
+{
+    if (!work_bytes) return set_error(GV_EINVAL, "work_bytes is NULL");
+    if (gv_status r = check_instances(count, inst, prec)) return r;
+    *work_bytes = batch_layout(count, inst, prec).total;
+    return GV_OK;
+}
+
+gv_status gv_batch_create(int32_t count, const gv_instance *inst, gv_precision prec,
+                          const gv_batch_tuning *tuning, void *work, size_t work_bytes,
+                          void *stream, int32_t use_graph, gv_batch *out)
+{
+    if (!out) return set_error(GV_EINVAL, "out is NULL");
+    if (gv_status r = check_instances(count, inst, prec)) return r;
+    if (!work || ((uintptr_t)work % kAlign)) return set_error(GV_EINVAL, "work must be 256-byte aligned");
+    const BatchLayout L = batch_layout(count, inst, prec);
+    if (work_bytes < L.total)
+        return set_error(GV_ESIZE, "work buffer %zu bytes < %zu needed", work_bytes, L.total);
+    gv_batch_tuning tu = {2, 0};
+    if (tuning) tu = *tuning;
+    if (tu.blocks_per_cu < 1 || tu.blocks_per_cu > 8 || tu.order < 0 || tu.order > 1)
+        return set_error(GV_EINVAL, "tuning out of range");
+
+    char *w = (char *)work;
+    const int C = std::min(kBatchK - 1, prec == GV_C64 ? 4 : 3);
+    std::vector<BatchInst> hi(count);
+    std::vector<std::vector<BatchOffPass>> offp(count);
+    std::vector<double> cost(count);
+    for (int i = 0; i < count; ++i) {
+        const gv_instance &I = inst[i];
+        const gv_ansatz &a = I.ansatz;
+        const gv_pauli_s *h = I.h;
+        BatchInst &b = hi[i];
+        memset(&b, 0, sizeof(b));
+        TilePlan plan;
+        if (!make_tile_plan(a.n, kBatchK, C, &plan))
+            return set_error(GV_EUNSUPPORTED, "instance %d: no tile plan", i);
+        const Chunks ch = make_chunks(a.n, kBatchK, kBatchLogR);
+        b.n = a.n;
+        b.layers = a.layers;
+        b.rot = a.layers + a.final_rotation;
+        b.np = plan.npass;
+        b.noff = (int)h->off_passes.size();
+        b.zonly = h->ox.empty();
+        b.cz = a.ent == GV_ENT_CZ_LINEAR ? 1 : (a.ent == GV_ENT_CZ_CIRCULAR ? 2 : 0);
+        b.ntiles = 1ull << (a.n - kBatchK);
+        b.qmask = I.qubit_mask;
+        b.theta = I.params_dev;
+        b.energy = I.energy_dev;
+        b.grad = I.grad_dev;
+        b.hdiag = h->diag;
+        b.cls = h->dev_cls;
+        b.terms = h->dev_terms;
+        b.offp = (const BatchOffPass *)(w + L.offp[i]);
+        b.psi = w + L.psi[i];
+        b.lam = w + L.lam[i];
+        b.ry = (double *)(w + L.ry[i]);
+        b.dtab = w + L.dtab[i];
+        b.dtab_stride = L.stride[i];
+        b.gtab = w + L.gtab[i];
+        b.g0tab = w + L.g0tab[i];
+        b.dt_cz = make_diagtab(a, ch, b.dtab, true);
+        b.dt_plain = make_diagtab(a, ch, b.dtab, false);
+        b.gt = make_diagtab(a, ch, b.gtab, a.layers > 0);
+        b.g0 = make_diagtab(a, ch, b.g0tab, false);
+        b.ta = make_tab_args(a, ch, L.stride[i]);
+        for (int p = 0; p < plan.npass; ++p) {
+            pass_runs(plan.pass[p].pos, kBatchK, a.n, &b.pass[p]);
+            b.pass[p].active = plan.pass[p].active;
+        }
+        for (const OffPass &op : h->off_passes) {
+            BatchOffPass bo;
+            memset(&bo, 0, sizeof(bo));
+            pass_runs(op.pos, kBatchK, a.n, &bo.tile);
+            bo.c0 = op.c0;
+            bo.c1 = op.c1;
+            offp[i].push_back(bo);
+        }
+        cost[i] = (double)(1ull << a.n) * (double)(b.rot * b.np * 3 + b.noff);
+    }
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    if (tu.order == 0)
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+
+    gv_batch b = new (std::nothrow) gv_batch_s;
+    if (!b) return set_error(GV_EINVAL, "out of host memory");
+    b->count = count;
+    b->prec = prec;
+    b->work = work;
+    b->work_bytes = work_bytes;
+    b->stream = (hipStream_t)stream;
+    b->dev_insts = (BatchInst *)(w + L.insts);
+    b->dev_order = (int *)(w + L.order);
+    b->counter = (unsigned *)(w + L.counter);
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    b->grid = std::max(1, std::min(count, tu.blocks_per_cu * cus));
+
+    hipError_t e = hipSuccess;
+    if (count > 0) {
+        e = hipMemcpy(b->dev_insts, hi.data(), hi.size() * sizeof(BatchInst), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(b->dev_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice);
+        for (int i = 0; i < count && e == hipSuccess; ++i)
+            if (!offp[i].empty())
+                e = hipMemcpy(w + L.offp[i], offp[i].data(), offp[i].size() * sizeof(BatchOffPass),
+                              hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && use_graph) {
+        e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e1 = batch_tables(prec, b->dev_insts, count, b->capture_stream);
+            hipError_t e2 = e1 == hipSuccess ? batch_run(prec, b->dev_insts, b->dev_order, count,
+                                                         b->counter, b->grid, b->capture_stream)
+                                             : e1;
+            e = hipStreamEndCapture(b->capture_stream, &b->g);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->g, nullptr, nullptr, 0);
+        b->graph = e == hipSuccess;
+    }
+    if (e != hipSuccess) {
+        gv_batch_destroy(b);
+        return check_hip(e, "batch setup");
+    }
+    *out = b;
+    return GV_OK;
+}
+
+gv_status gv_batch_run(gv_batch b)
+{
+    if (!b) return set_error(GV_EINVAL, "batch is NULL");
+    if (b->graph) return check_hip(hipGraphLaunch(b->exec, b->stream), "graph launch");
+    hipError_t e = batch_tables(b->prec, b->dev_insts, b->count, b->stream);
+    if (e == hipSuccess)
+        e = batch_run(b->prec, b->dev_insts, b->dev_order, b->count, b->counter, b->grid, b->stream);
+    return check_hip(e, "batch launch");
+}
+
+gv_status gv_batch_destroy(gv_batch b)
+{
+    if (!b) return GV_OK;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->g) (void)hipGraphDestroy(b->g);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    delete b;
+    return GV_OK;
+}
+
+gv_status gv_batch_energy_grad(int32_t count, const gv_instance *inst, gv_precision prec,
+                               void *work, size_t work_bytes, void *stream)
+{
+    gv_batch b = nullptr;
+    if (gv_status r = gv_batch_create(count, inst, prec, nullptr, work, work_bytes, stream, 0, &b))
+        return r;
+    gv_status r = gv_batch_run(b);
+    gv_batch_destroy(b);
+    return r;
+}
+
+}  // extern "C"

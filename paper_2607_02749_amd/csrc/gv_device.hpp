@@ -32,8 +32,11 @@ __device__ __forceinline__ u64 insert_zero(u64 k, int q)
 // in index order).  Valid in thread 0.  `sh` holds >= blockDim.x/64 doubles.
 __device__ __forceinline__ double block_sum(double v, double *sh)
 {
+    // blocks of fewer than 64 threads fill part of a wave: skip the shifts
+    // that would read the missing lanes
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    for (int o = 32; o > 0; o >>= 1)
+        if (o < (int)blockDim.x) v += __shfl_down(v, o, 64);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) sh[w] = v;

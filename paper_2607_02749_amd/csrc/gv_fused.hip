@@ -47,14 +47,7 @@ namespace {
 // register bits of the load assignment) and b_4 = n.  Entry v of chunk c is
 // the product of the RZ phases of the chunk's qubits and the sign of the CZ
 // pairs inside the chunk; CZ pairs that straddle chunks are listed apart.
-struct DiagTab {
-    const void *tab;
-    int b1, b2, b3;
-    int off1, off2, off3;
-    u64 m0, m1, m2;
-    int npair;
-    int8_t pa[4], pb[4];
-};
+// (DiagTab itself is declared in gv_internal.hpp.)
 
 enum { IN_LOAD = 0, IN_LOAD_DIAG = 1, IN_GENERATE = 2 };
 
@@ -78,6 +71,7 @@ struct FusedArgs {
     double *part;            // P x grid gradient partials
     double *epart;           // turnaround: 2 x grid energy partials
     int grid;
+    u64 qmask;               // qubits whose gradient rows are written (others get 0)
 };
 
 template <int K, int LOGR>
@@ -104,6 +98,15 @@ struct Tile {
         return (t & ((1 << l) - 1)) | (r << l) | ((t >> l) << (l + LOGR));
     }
     __device__ static __forceinline__ int pad(int u) { return u + (u >> 4); }
+    // pad(u_of(t, r, l)) = lds_base(t, l) + r * lds_stride(l) whenever the
+    // register bits do not straddle the 16-entry padding groups (l = 0 or
+    // l >= 4), which lets register r's LDS access use an immediate offset
+    static constexpr bool lds_linear(int l) { return l == 0 || l >= 4; }
+    static constexpr int lds_stride(int l) { return l == 0 ? 1 : (1 << l) + (1 << (l - 4)); }
+    __device__ static __forceinline__ int lds_index(int t, int r, int l)
+    {
+        return lds_linear(l) ? pad(u_of(t, 0, l)) + r * lds_stride(l) : pad(u_of(t, r, l));
+    }
 };
 
 __device__ __forceinline__ u64 tile_base(u64 tile, const FusedArgs &a)
@@ -238,13 +241,13 @@ __device__ __forceinline__ cx<R> cmul_conj(cx<R> a, cx<R> d)  // a * conj(d)
 
 // RY on the pair (x, y): (c x - s y, s x + c y)
 template <typename R>
-__device__ __forceinline__ void rot_pair(cx<R> &x, cx<R> &y, R c, R s)
+__device__ __forceinline__ void rot_pair(cx<R> &x, cx<R> &y, R c, R sn)
 {
     const cx<R> a = x, b = y;
-    x.re = c * a.re - s * b.re;
-    x.im = c * a.im - s * b.im;
-    y.re = s * a.re + c * b.re;
-    y.im = s * a.im + c * b.im;
+    x.re = c * a.re - sn * b.re;
+    x.im = c * a.im - sn * b.im;
+    y.re = sn * a.re + c * b.re;
+    y.im = sn * a.im + c * b.im;
 }
 
 // forward rotations of the tile bits that are new in assignment AI
@@ -259,10 +262,10 @@ __device__ __forceinline__ void fwd_assign(cx<R> (&v)[1 << LOGR], const FusedArg
         const int j = LO + k;
         if (!((NEW >> j) & 1) || !((a.active >> j) & 1)) continue;
         const double *e = a.ry + 2 * ((int64_t)a.layer * a.nparam_layer + a.pos[j]);
-        const R c = (R)e[0], s = (R)e[1];
+        const R c = (R)e[0], sn = (R)e[1];
 #pragma unroll
         for (int r = 0; r < T::NR; ++r)
-            if (!(r & (1 << k))) rot_pair(v[r], v[r | (1 << k)], c, s);
+            if (!(r & (1 << k))) rot_pair(v[r], v[r | (1 << k)], c, sn);
     }
 }
 
@@ -281,30 +284,38 @@ __device__ __forceinline__ void bwd_assign(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 <
         const int j = LO + k;
         if (!((NEW >> j) & 1) || !((a.active >> j) & 1)) continue;
         const double *e = a.ry + 2 * ((int64_t)a.layer * a.nparam_layer + a.pos[j]);
-        const R c = (R)e[0], s = -(R)e[1];
+        const R c = (R)e[0], sn = -(R)e[1];
         R g = 0;
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
             if (r & (1 << k)) continue;
             const int r1 = r | (1 << k);
             g += (l[r1].re * f[r].re + l[r1].im * f[r].im) - (l[r].re * f[r1].re + l[r].im * f[r1].im);
-            rot_pair(f[r], f[r1], c, s);
-            rot_pair(l[r], l[r1], c, s);
+            rot_pair(f[r], f[r1], c, sn);
+            rot_pair(l[r], l[r1], c, sn);
         }
         accY[j] += (double)g;
     }
 }
 
-template <typename R, int K, int LOGR>
-__device__ __forceinline__ void exchange(cx<R> (&v)[1 << LOGR], cx<R> *lds, int t, int lfrom, int lto)
+template <typename R, int K, int LOGR, int LFROM, int LTO>
+__device__ __forceinline__ void exchange(cx<R> (&v)[1 << LOGR], cx<R> *lds, int t)
 {
     using T = Tile<K, LOGR>;
     __syncthreads();
+    cx<R> *wr = lds + (T::lds_linear(LFROM) ? T::lds_index(t, 0, LFROM) : 0);
 #pragma unroll
-    for (int r = 0; r < T::NR; ++r) lds[T::pad(T::u_of(t, r, lfrom))] = v[r];
+    for (int r = 0; r < T::NR; ++r) {
+        if constexpr (T::lds_linear(LFROM)) wr[r * T::lds_stride(LFROM)] = v[r];
+        else lds[T::lds_index(t, r, LFROM)] = v[r];
+    }
     __syncthreads();
+    const cx<R> *rd = lds + (T::lds_linear(LTO) ? T::lds_index(t, 0, LTO) : 0);
 #pragma unroll
-    for (int r = 0; r < T::NR; ++r) v[r] = lds[T::pad(T::u_of(t, r, lto))];
+    for (int r = 0; r < T::NR; ++r) {
+        if constexpr (T::lds_linear(LTO)) v[r] = rd[r * T::lds_stride(LTO)];
+        else v[r] = lds[T::lds_index(t, r, LTO)];
+    }
 }
 
 template <typename R, int K, int LOGR, int AI>
@@ -313,7 +324,7 @@ struct FwdChain {
                                                const FusedArgs &a)
     {
         using T = Tile<K, LOGR>;
-        exchange<R, K, LOGR>(v, lds, t, T::lo(AI - 1), T::lo(AI));
+        exchange<R, K, LOGR, T::lo(AI - 1), T::lo(AI)>(v, lds, t);
         fwd_assign<R, K, LOGR, AI>(v, a);
         if constexpr (AI + 1 < T::NA) FwdChain<R, K, LOGR, AI + 1>::run(v, lds, t, a);
     }
@@ -327,8 +338,8 @@ struct BwdChain {
                                                const FusedArgs &a)
     {
         using T = Tile<K, LOGR>;
-        exchange<R, K, LOGR>(f, lds, t, T::lo(AI - 1), T::lo(AI));
-        exchange<R, K, LOGR>(l, lds, t, T::lo(AI - 1), T::lo(AI));
+        exchange<R, K, LOGR, T::lo(AI - 1), T::lo(AI)>(f, lds, t);
+        exchange<R, K, LOGR, T::lo(AI - 1), T::lo(AI)>(l, lds, t);
         bwd_assign<R, K, LOGR, AI>(f, l, accY, a);
         if constexpr (AI + 1 < T::NA) BwdChain<R, K, LOGR, AI + 1>::run(f, l, accY, lds, t, a);
     }
@@ -344,8 +355,8 @@ struct BwdChainRev {
                                                const FusedArgs &a)
     {
         using T = Tile<K, LOGR>;
-        exchange<R, K, LOGR>(f, lds, t, T::lo(AI + 1), T::lo(AI));
-        exchange<R, K, LOGR>(l, lds, t, T::lo(AI + 1), T::lo(AI));
+        exchange<R, K, LOGR, T::lo(AI + 1), T::lo(AI)>(f, lds, t);
+        exchange<R, K, LOGR, T::lo(AI + 1), T::lo(AI)>(l, lds, t);
         bwd_assign<R, K, LOGR, AI>(f, l, accY, a);
         if constexpr (AI > 0) BwdChainRev<R, K, LOGR, AI - 1>::run(f, l, accY, lds, t, a);
     }
@@ -374,12 +385,15 @@ __device__ __forceinline__ void load_tile(cx<R> (&v)[1 << LOGR], const cx<R> *sr
     }
 }
 
+// The pass bodies below take the tiles t0, t0 + tstep, ... so that a grid
+// of blocks (t0 = blockIdx.x, tstep = gridDim.x) or a single block that owns
+// a whole batch instance (t0 = 0, tstep = 1) can run them; col is the
+// partial-sum column the block writes.
 template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_pass(void *psi_, FusedArgs a)
+__device__ __forceinline__ void fwd_body(cx<R> *psi, const FusedArgs &a, u64 t0, u64 tstep,
+                                         cx<R> *lds)
 {
     using T = Tile<K, LOGR>;
-    cx<R> *psi = (cx<R> *)psi_;
-    __shared__ cx<R> lds[T::LDS];
     const int t = threadIdx.x;
     constexpr int LD = T::lo(0), ST = T::lo(T::NA - 1);
     const u64 toff_ld = thread_off<K, LOGR>(t, LD, a), toff_st = thread_off<K, LOGR>(t, ST, a);
@@ -388,7 +402,7 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_pass(void *psi_, FusedA
     mst.init(a.pos + ST);
     P0Diag<R, K, LOGR> pd;
     if (a.in_mode != IN_LOAD) pd.init(a.dt, t);
-    for (u64 tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> v[T::NR];
         load_tile<R, K, LOGR, CONTIG>(v, psi, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
@@ -399,30 +413,44 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_pass(void *psi_, FusedA
     }
 }
 
-template <typename R, int K>
-__device__ __forceinline__ void write_partials(const double (&accY)[K], const double (&accZ)[K],
-                                               bool zeroZ, double *sh, const FusedArgs &a)
+template <typename R, int K, int LOGR, bool CONTIG>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_pass(void *psi_, FusedArgs a)
 {
+    __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
+    fwd_body<R, K, LOGR, CONTIG>((cx<R> *)psi_, a, blockIdx.x, gridDim.x, lds);
+}
+
+// Block sums of the gradient partials of the pass's active tile qubits.
+// The RZ partials come as one accumulator per register bit of the load
+// assignment (accZr) and one per-thread total (ztot) whose sign for thread
+// bit j is that bit of the thread id; HAVEZ = false writes zeros.
+template <typename R, int K, int LOGR, bool HAVEZ>
+__device__ __forceinline__ void write_partials(const double (&accY)[K], const double (&accZr)[LOGR],
+                                               double ztot, double *sh, const FusedArgs &a,
+                                               int col)
+{
+    constexpr int LD = K - LOGR;
+    const int t = threadIdx.x;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         if (!((a.active >> j) & 1)) continue;
+        const bool keep = (a.qmask >> a.pos[j]) & 1;
         const int64_t row = (int64_t)a.layer * a.nparam_layer + a.pos[j];
         const double y = block_sum(accY[j], sh);
-        if (threadIdx.x == 0) a.part[row * a.grid + blockIdx.x] = y;
-        const double z = zeroZ ? 0.0 : block_sum(accZ[j], sh);
-        if (threadIdx.x == 0) a.part[(row + a.n) * a.grid + blockIdx.x] = z;
+        if (t == 0) a.part[row * a.grid + col] = keep ? y : 0.0;
+        double z = 0.0;
+        if constexpr (HAVEZ)
+            z = block_sum(j >= LD ? accZr[j - LD] : (((t >> j) & 1) ? -ztot : ztot), sh);
+        if (t == 0) a.part[(row + a.n) * a.grid + col] = keep ? z : 0.0;
     }
 }
 
 template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const void *phi_in_, void *phi_,
-                                                              void *lam_, FusedArgs a)
+__device__ __forceinline__ void bwd_body(const cx<R> *phi_in, cx<R> *phi, cx<R> *lam,
+                                         const FusedArgs &a, u64 t0, u64 tstep, int col,
+                                         cx<R> *lds, double *sh)
 {
     using T = Tile<K, LOGR>;
-    const cx<R> *phi_in = (const cx<R> *)phi_in_;
-    cx<R> *phi = (cx<R> *)phi_, *lam = (cx<R> *)lam_;
-    __shared__ cx<R> lds[T::LDS];
-    __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
     const int t = threadIdx.x;
     constexpr int LD = T::lo(0), ST = T::lo(T::NA - 1);
     const u64 toff_ld = thread_off<K, LOGR>(t, LD, a), toff_st = thread_off<K, LOGR>(t, ST, a);
@@ -433,11 +461,13 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const void *phi_in
     const bool any_diag = a.diag_phi || a.diag_lam;
     if (any_diag) pd.init(a.dt, t);
     if (a.phi_gen) pg.init(a.gt, t);
-    double accY[K], accZ[K];
+    double accY[K], accZr[LOGR], ztot = 0.0;
 #pragma unroll
-    for (int j = 0; j < K; ++j) accY[j] = accZ[j] = 0.0;
+    for (int j = 0; j < K; ++j) accY[j] = 0.0;
+#pragma unroll
+    for (int k = 0; k < LOGR; ++k) accZr[k] = 0.0;
 
-    for (u64 tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> f[T::NR], l[T::NR];
         if (a.phi_gen) {
@@ -468,18 +498,14 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const void *phi_in
                 tt[r] = l[r].re * f[r].im - l[r].im * f[r].re;
                 tsum += tt[r];
             }
+            ztot += (double)tsum;   // thread bits: the sign is applied at the block sum
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                if (!((a.active >> j) & 1)) continue;
-                if (j >= LD) {  // register bit of the load assignment
-                    const int k = j - LD;
-                    R s = 0;
+            for (int k = 0; k < LOGR; ++k) {    // register bits of the load assignment
+                if (!((a.active >> (LD + k)) & 1)) continue;
+                R s = 0;
 #pragma unroll
-                    for (int r = 0; r < T::NR; ++r) s += ((r >> k) & 1) ? -tt[r] : tt[r];
-                    accZ[j] += (double)s;
-                } else {        // thread bit j of the load assignment
-                    accZ[j] += ((t >> j) & 1) ? -(double)tsum : (double)tsum;
-                }
+                for (int r = 0; r < T::NR; ++r) s += ((r >> k) & 1) ? -tt[r] : tt[r];
+                accZr[k] += (double)s;
             }
         }
         bwd_assign<R, K, LOGR, 0>(f, l, accY, a);
@@ -491,7 +517,17 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const void *phi_in
             if (a.store_lam) lam[i] = l[r];
         }
     }
-    write_partials<R, K>(accY, accZ, false, sh, a);
+    write_partials<R, K, LOGR, true>(accY, accZr, ztot, sh, a, col);
+}
+
+template <typename R, int K, int LOGR, bool CONTIG>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const void *phi_in_, void *phi_,
+                                                              void *lam_, FusedArgs a)
+{
+    __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
+    __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
+    bwd_body<R, K, LOGR, CONTIG>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_, a,
+                                 blockIdx.x, gridDim.x, blockIdx.x, lds, sh);
 }
 
 // Last forward pass of the last layer + energy + first reverse pass, for a
@@ -503,14 +539,10 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const void *phi_in
 // the layer's only pass, the load applies the previous layer's diagonal (or
 // generates the first layer's state).
 template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_pass(const void *psi_, void *lam_,
-                                                               FusedArgs a)
+__device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const FusedArgs &a,
+                                          u64 t0, u64 tstep, int col, cx<R> *lds, double *sh)
 {
     using T = Tile<K, LOGR>;
-    const cx<R> *psi = (const cx<R> *)psi_;
-    cx<R> *lam = (cx<R> *)lam_;
-    __shared__ cx<R> lds[T::LDS];
-    __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
     const int t = threadIdx.x;
     constexpr int LD = T::lo(0), ST = T::lo(T::NA - 1);
     const u64 toff_ld = thread_off<K, LOGR>(t, LD, a), toff_st = thread_off<K, LOGR>(t, ST, a);
@@ -519,12 +551,12 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_pass(const void *psi_,
     mst.init(a.pos + ST);
     P0Diag<R, K, LOGR> pd;
     if (a.in_mode != IN_LOAD) pd.init(a.dt, t);
-    double accY[K], accZ[K];
+    double accY[K], accZr[LOGR];
 #pragma unroll
-    for (int j = 0; j < K; ++j) accY[j] = accZ[j] = 0.0;
+    for (int j = 0; j < K; ++j) accY[j] = 0.0;
     double eacc = 0.0;
 
-    for (u64 tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> f[T::NR], l[T::NR];
         load_tile<R, K, LOGR, CONTIG>(f, psi, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
@@ -539,18 +571,195 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_pass(const void *psi_,
             l[r].im = (R)d * f[r].im;
         }
         bwd_assign<R, K, LOGR, T::NA - 1>(f, l, accY, a);
-        if constexpr (T::NA > 1) BwdChainRev<R, K, LOGR, T::NA - 2>::run(f, l, accY, lds, t, a);
+        if constexpr (T::NA > 1)
+            BwdChainRev<R, K, LOGR, T::NA - 2>::run(f, l, accY, lds, t, a);
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) lam[base | toff_ld | mld.off(r)] = l[r];
     }
-    write_partials<R, K>(accY, accZ, true, sh, a);
+    write_partials<R, K, LOGR, false>(accY, accZr, 0.0, sh, a, col);
     const double e = block_sum(eacc, sh);
     if (t == 0) {
-        a.epart[blockIdx.x] = e;
-        a.epart[a.grid + blockIdx.x] = 0.0;
+        a.epart[col] = e;
+        a.epart[a.grid + col] = 0.0;
     }
 }
 
+template <typename R, int K, int LOGR, bool CONTIG>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_pass(const void *psi_, void *lam_,
+                                                               FusedArgs a)
+{
+    __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
+    __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
+    turn_body<R, K, LOGR, CONTIG>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x, gridDim.x,
+                                  blockIdx.x, lds, sh);
+}
+
+
+// ------------------------------------------------ first-layer gradients
+
+// Arguments of the first-layer gradient kernel.  The state after the first
+// layer's RY gates is the product state G = R_0|0...0>, held as chunk tables
+// in gt (no CZ pairs); dt is the first layer's diagonal when lam still sits
+// after it.
+struct Layer0Args {
+    int n;
+    u64 ntiles;
+    int diag_lam;
+    DiagTab dt;
+    DiagTab gt;
+    double *part;
+    int grid;
+    u64 qmask;
+};
+
+// sum over the block of a complex double, returned to every thread
+__device__ __forceinline__ void block_sum2_all(double &x, double &y, double *sh)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        if (o >= (int)blockDim.x) continue;
+        x += __shfl_down(x, o, 64);
+        y += __shfl_down(y, o, 64);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        sh[2 * w] = x;
+        sh[2 * w + 1] = y;
+    }
+    __syncthreads();
+    x = y = 0.0;
+    for (int i = 0; i < nw; ++i) {
+        x += sh[2 * i];
+        y += sh[2 * i + 1];
+    }
+}
+
+// Gradients of the first rotation layer (Eq. 11) from lam alone.  With phi
+// the product state G after the layer's RY gates, every RY and RZ gradient
+// of the layer is Im<lam'|P_q|G> (P = Y or Z, lam' = lam before the layer's
+// diagonal), because P_q commutes with the RY gates of the other qubits and
+// with the diagonal gates.  G factorises over the index bits, G_i = T0(t)
+// T1(r) B(tile) in the coalesced layout (thread bits = index bits 0..K-LOGR-1,
+// register bits = the next LOGR bits, tile id = the rest), and
+// (Y_q G)_i = (+i if bit q of i is set, else -i) G_{i ^ 2^q}, so per tile a
+// thread needs U = sum_r conj(lam'_r) T1(r), the signed sums of the same
+// products for the register bits, and the flipped-partner sums W_k; the
+// thread and tile factors multiply in afterwards.  One read of lam replaces
+// the layer's reverse passes.
+template <typename R, int K, int LOGR>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_layer0_grad(const void *lam_, Layer0Args a)
+{
+    constexpr int NR = 1 << LOGR, LD = K - LOGR;
+    __shared__ double sh[2 * ((1 << (K - LOGR)) / 64 + 1)];
+    const cx<R> *lam = (const cx<R> *)lam_;
+    const int t = threadIdx.x;
+    const cx<R> *G = (const cx<R> *)a.gt.tab;
+    P0Diag<R, K, LOGR> pd;
+    if (a.diag_lam) pd.init(a.dt, t);
+    const int nb = a.n - K;            // tile-id qubits K .. n-1
+    double Vre = 0, Vim = 0;
+    double Wre[LOGR], Wim[LOGR], Zre[LOGR], Zim[LOGR];
+#pragma unroll
+    for (int k = 0; k < LOGR; ++k) Wre[k] = Wim[k] = Zre[k] = Zim[k] = 0.0;
+    double bY = 0, bZ = 0;             // thread t < nb: qubit K + t
+    const cx<R> g0 = G[t];
+
+    for (u64 tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const u64 base = tile << K;
+        cx<R> c[NR];                   // conj(lam'_r)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) c[r] = lam[base | ((u64)r << LD) | (u64)t];
+        if (a.diag_lam) {
+            pd.tile(a.dt, base, t);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) c[r] = cmul_conj(c[r], pd.at(a.dt, r));
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) c[r].im = -c[r].im;
+        R ure = 0, uim = 0;
+        R zr[LOGR], zi[LOGR], wr[LOGR], wi[LOGR];
+#pragma unroll
+        for (int k = 0; k < LOGR; ++k) zr[k] = zi[k] = wr[k] = wi[k] = 0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const cx<R> p = cmul(c[r], G[a.gt.off1 + r]);
+            ure += p.re;
+            uim += p.im;
+#pragma unroll
+            for (int k = 0; k < LOGR; ++k) {
+                const bool b = (r >> k) & 1;
+                zr[k] += b ? -p.re : p.re;
+                zi[k] += b ? -p.im : p.im;
+                const cx<R> q = cmul(c[r], G[a.gt.off1 + (r ^ (1 << k))]);
+                // (+-i) q: +i q = (-q.im, q.re), -i q = (q.im, -q.re)
+                wr[k] += b ? -q.im : q.im;
+                wi[k] += b ? q.re : -q.re;
+            }
+        }
+        const cx<R> b2 = G[a.gt.off2 + ((base >> a.gt.b2) & a.gt.m2)];
+        const cx<R> b3 = G[a.gt.off3 + (base >> a.gt.b3)];
+        const double Bre = (double)b2.re * b3.re - (double)b2.im * b3.im;
+        const double Bim = (double)b2.re * b3.im + (double)b2.im * b3.re;
+        Vre += Bre * ure - Bim * uim;
+        Vim += Bre * uim + Bim * ure;
+#pragma unroll
+        for (int k = 0; k < LOGR; ++k) {
+            Wre[k] += Bre * wr[k] - Bim * wi[k];
+            Wim[k] += Bre * wi[k] + Bim * wr[k];
+            Zre[k] += Bre * zr[k] - Bim * zi[k];
+            Zim[k] += Bre * zi[k] + Bim * zr[k];
+        }
+        // tile-id qubits: S = sum over the tile of conj(lam'_i) T0(t) T1(r)
+        if (nb > 0) {
+            double Sre = (double)g0.re * ure - (double)g0.im * uim;
+            double Sim = (double)g0.re * uim + (double)g0.im * ure;
+            block_sum2_all(Sre, Sim, sh);
+            if (t < nb) {
+                const int q = K + t;
+                const bool bit = (base >> q) & 1;
+                // Z: sign * Im(B S)
+                const double im_bs = Bre * Sim + Bim * Sre;
+                bZ += bit ? -im_bs : im_bs;
+                // Y: Im((+-i) B' S) with B' the factor of the partner tile
+                const u64 fb = base ^ (1ull << q);
+                const cx<R> f2 = G[a.gt.off2 + ((fb >> a.gt.b2) & a.gt.m2)];
+                const cx<R> f3 = G[a.gt.off3 + (fb >> a.gt.b3)];
+                const double Fre = (double)f2.re * f3.re - (double)f2.im * f3.im;
+                const double Fim = (double)f2.re * f3.im + (double)f2.im * f3.re;
+                const double re_fs = Fre * Sre - Fim * Sim;
+                bY += bit ? re_fs : -re_fs;
+            }
+        }
+    }
+
+    const int col = blockIdx.x;
+    auto put = [&](int q, double y, double z, bool lane0) {
+        if (!lane0) return;
+        const bool keep = (a.qmask >> q) & 1;
+        a.part[(int64_t)q * a.grid + col] = keep ? y : 0.0;
+        a.part[(int64_t)(a.n + q) * a.grid + col] = keep ? z : 0.0;
+    };
+    // thread bits j: Z = sum_t sign_j(t) Im(T0(t) V), Y = sum_t Im((+-i) T0(t^2^j) V)
+    for (int j = 0; j < LD; ++j) {
+        const bool bit = (t >> j) & 1;
+        const double im_tv = (double)g0.re * Vim + (double)g0.im * Vre;
+        const cx<R> gf = G[t ^ (1 << j)];
+        const double re_fv = (double)gf.re * Vre - (double)gf.im * Vim;
+        const double z = block_sum(bit ? -im_tv : im_tv, sh);
+        const double y = block_sum(bit ? re_fv : -re_fv, sh);
+        put(j, y, z, t == 0);
+    }
+    // register bits k: Y = sum_t Im(T0(t) W_k), Z = sum_t Im(T0(t) Z_k)
+#pragma unroll
+    for (int k = 0; k < LOGR; ++k) {
+        const double y = block_sum((double)g0.re * Wim[k] + (double)g0.im * Wre[k], sh);
+        const double z = block_sum((double)g0.re * Zim[k] + (double)g0.im * Zre[k], sh);
+        put(LD + k, y, z, t == 0);
+    }
+    // tile-id qubits: accumulated whole by thread t
+    if (t < nb) put(K + t, bY, bZ, true);
+}
 
 // ------------------------------------------------------- off-diagonal terms
 
@@ -573,14 +782,10 @@ struct OffArgs {
 // terms in the amplitude precision.  The pass's share of <psi|H|psi> goes to
 // FP64 partials.
 template <typename R, int K, int LOGR>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_offdiag_pass(const void *psi_, void *lam_,
-                                                                  OffArgs a)
+__device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const OffArgs &a, u64 t0,
+                                         u64 tstep, int col, cx<R> *lds, double *sh)
 {
     using T = Tile<K, LOGR>;
-    const cx<R> *psi = (const cx<R> *)psi_;
-    cx<R> *lam = (cx<R> *)lam_;
-    __shared__ cx<R> lds[T::LDS];
-    __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
     const int t = threadIdx.x;
     constexpr int LD = T::lo(0);
     FusedArgs fa;  // only the tile geometry is used
@@ -595,7 +800,7 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_offdiag_pass(const void *ps
     RegMap<LOGR, false> m;
     m.init(a.pos + LD);
     double er = 0.0, ei = 0.0;
-    for (u64 tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, fa);
         cx<R> v[T::NR], acc[T::NR];
         __syncthreads();
@@ -645,34 +850,36 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_offdiag_pass(const void *ps
     const double tr = block_sum(er, sh);
     const double ti = block_sum(ei, sh);
     if (t == 0) {
-        a.epart[blockIdx.x] += tr;
-        a.epart[a.estride + blockIdx.x] += ti;
+        a.epart[col] += tr;
+        a.epart[a.estride + col] += ti;
     }
+    __syncthreads();
+}
+
+template <typename R, int K, int LOGR>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_offdiag_pass(const void *psi_, void *lam_,
+                                                                  OffArgs a)
+{
+    __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
+    __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
+    off_body<R, K, LOGR>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x, gridDim.x, blockIdx.x,
+                         lds, sh);
 }
 
 // ------------------------------------------------------------ table kernels
-
 // ry[p] = (cos(theta_p / 2), sin(theta_p / 2))
+__device__ __forceinline__ void ry_entry(double theta, double *e)
+{
+    sincos(0.5 * theta, &e[1], &e[0]);
+}
+
 __global__ void k_ry_table(const double *theta, int64_t np, double *ry)
 {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        double s, c;
-        sincos(0.5 * theta[p], &s, &c);
-        ry[2 * p] = c;
-        ry[2 * p + 1] = s;
-    }
+         p += (int64_t)gridDim.x * blockDim.x)
+        ry_entry(theta[p], ry + 2 * p);
 }
 
-struct TabArgs {
-    int n;
-    int rot_layers;
-    int cz_layers;          // layers that carry the CZ ladder
-    int cz;                 // 1 linear CZ, 2 circular CZ, 0 none
-    int b[5];               // chunk bounds 0, b1, b2, b3, n
-    int off[5];             // entry offsets of the chunks within a table set
-    size_t stride;          // bytes per layer
-};
 
 __device__ __forceinline__ int chunk_of(const TabArgs &ta, int w)
 {
@@ -835,6 +1042,281 @@ void fill_runs(FusedArgs &a, const PassPlan &pp, int K, int n)
     }
 }
 
+DiagTab layer_tab(const gv_ansatz &an, const Chunks &ch, const FusedTables &t, int layer)
+{
+    return make_diagtab(an, ch, (const char *)t.dtab + (size_t)layer * t.dtab_stride,
+                        layer < an.layers);
+}
+
+FusedArgs base_args(const gv_ansatz &an, const TilePlan &plan, int pass, int layer,
+                    const FusedTables &t)
+{
+    FusedArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n = an.n;
+    a.layer = layer;
+    a.nparam_layer = 2 * an.n;
+    for (int j = 0; j < plan.K; ++j) a.pos[j] = plan.pass[pass].pos[j];
+    a.active = plan.pass[pass].active;
+    fill_runs(a, plan.pass[pass], plan.K, an.n);
+    a.ntiles = 1ull << (an.n - plan.K);
+    a.ry = t.ry;
+    a.store_phi = a.store_lam = 1;
+    a.qmask = ~0ull;
+    return a;
+}
+
+inline int elem_grid(u64 dim)
+{
+    const u64 b = (dim + 255) / 256;
+    return (int)(b < 8192 ? b : 8192);
+}
+
+#define GV_LAUNCH_K(KERNEL, PREC, GRID, K, ...)                                                   \
+    do {                                                                                          \
+        switch (K) {                                                                              \
+        case 12:                                                                                  \
+            if (PREC == GV_C64)                                                                   \
+                hipLaunchKernelGGL((KERNEL<float, 12, 4, true>), dim3(GRID), dim3(256), 0, s,     \
+                                   __VA_ARGS__);                                                  \
+            else                                                                                  \
+                hipLaunchKernelGGL((KERNEL<double, 12, 4, true>), dim3(GRID), dim3(256), 0, s,    \
+                                   __VA_ARGS__);                                                  \
+            break;                                                                                \
+        case 10:                                                                                  \
+            if (PREC == GV_C64)                                                                   \
+                hipLaunchKernelGGL((KERNEL<float, 10, 4, true>), dim3(GRID), dim3(64), 0, s,  \
+                                   __VA_ARGS__);                                                  \
+            else                                                                                  \
+                hipLaunchKernelGGL((KERNEL<double, 10, 4, true>), dim3(GRID), dim3(64), 0, s, \
+                                   __VA_ARGS__);                                                  \
+            break;                                                                                \
+        case 8:                                                                                   \
+            if (PREC == GV_C64)                                                                   \
+                hipLaunchKernelGGL((KERNEL<float, 8, 3, false>), dim3(GRID), dim3(32), 0, s,  \
+                                   __VA_ARGS__);                                                  \
+            else                                                                                  \
+                hipLaunchKernelGGL((KERNEL<double, 8, 3, false>), dim3(GRID), dim3(32), 0, s, \
+                                   __VA_ARGS__);                                                  \
+            break;                                                                                \
+        default: return hipErrorInvalidValue;                                                     \
+        }                                                                                         \
+    } while (0)
+
+
+// ---------------------------------------------------------------- batching
+//
+// Many independent instances (their own n, layers, angles, Hamiltonian and
+// qubit block) in one persistent kernel: each block takes the next instance
+// from an atomic queue (in the order the host gives, largest first by
+// default) and runs that instance's whole evaluation -- the same tile passes
+// as the single-instance engine, over all of the instance's tiles, with block
+// barriers between passes.  One block owns an instance, so its energy and
+// gradient block sums are the final, fixed-order FP64 results.
+
+// tables of every instance: blockIdx.y is the instance
+template <typename R>
+__global__ void k_batch_tables(const BatchInst *insts)
+{
+    const BatchInst &I = insts[blockIdx.y];
+    const TabArgs &ta = I.ta;
+    const int per = ta.off[4];
+    const int64_t np = 2ll * I.n * I.rot;
+    const int64_t nd = (int64_t)per * I.rot;
+    const int64_t total = np + nd + per;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        if (e < np) {
+            ry_entry(I.theta[e], I.ry + 2 * e);
+            continue;
+        }
+        const int64_t f = e - np;
+        const bool init = f >= nd;
+        const int l = init ? 0 : (int)(f / per);
+        const int w = init ? (int)(f - nd) : (int)(f % per);
+        const int c = chunk_of(ta, w);
+        const u64 v = (u64)(w - ta.off[c]);
+        double ang;
+        int par;
+        chunk_phase(I.theta, ta, l, c, v, ang, par);
+        double sn, cs;
+        sincos(ang, &sn, &cs);
+        if (!init) {
+            if (par) {
+                sn = -sn;
+                cs = -cs;
+            }
+            cx<R> out;
+            out.re = (R)cs;
+            out.im = (R)sn;
+            ((cx<R> *)(I.dtab + (size_t)l * I.dtab_stride))[w] = out;
+        } else {
+            double mag = 1.0;
+            for (int q = ta.b[c]; q < ta.b[c + 1]; ++q) {
+                double s2, c2;
+                sincos(0.5 * I.theta[q], &s2, &c2);
+                mag *= ((v >> (q - ta.b[c])) & 1) ? s2 : c2;
+            }
+            cx<R> g0;
+            g0.re = (R)mag;
+            g0.im = (R)0;
+            ((cx<R> *)I.g0tab)[w] = g0;
+            if (par) mag = -mag;
+            cx<R> g;
+            g.re = (R)(mag * cs);
+            g.im = (R)(mag * sn);
+            ((cx<R> *)I.gtab)[w] = g;
+        }
+    }
+}
+
+__global__ void k_zero_u32(unsigned *p)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
+}
+
+__device__ __forceinline__ void batch_fill_pass(FusedArgs &a, const BatchInst &I, int p, int layer)
+{
+    a.n = I.n;
+    a.layer = layer;
+    a.nparam_layer = 2 * I.n;
+    for (int j = 0; j < kMaxTileBits; ++j) a.pos[j] = I.pass[p].pos[j];
+    a.active = I.pass[p].active;
+    a.nruns = I.pass[p].nruns;
+    for (int k = 0; k <= kMaxTileBits; ++k) {
+        a.run_src[k] = I.pass[p].run_src[k];
+        a.run_w[k] = I.pass[p].run_w[k];
+        a.run_dst[k] = I.pass[p].run_dst[k];
+    }
+    a.ntiles = I.ntiles;
+    a.ry = I.ry;
+    a.in_mode = IN_LOAD;
+    a.diag_phi = a.diag_lam = a.phi_gen = 0;
+    a.store_phi = a.store_lam = 1;
+    a.part = I.grad;
+    a.grid = 1;
+    a.qmask = I.qmask;
+}
+
+__device__ __forceinline__ DiagTab batch_layer_tab(const BatchInst &I, int layer)
+{
+    DiagTab d = (I.cz && layer < I.layers) ? I.dt_cz : I.dt_plain;
+    d.tab = I.dtab + (size_t)layer * I.dtab_stride;
+    return d;
+}
+
+template <typename R>
+__device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh)
+{
+    constexpr int K = 12, LOGR = 4;
+    const int t = threadIdx.x, nt = blockDim.x;
+    cx<R> *psi = (cx<R> *)I.psi, *lam = (cx<R> *)I.lam;
+    const u64 dim = 1ull << I.n;
+    const int R_ = I.rot, np = I.np;
+    FusedArgs a;
+    // forward: R_0|0..0> (generated inside layer 1's first pass), then the layers
+    if (R_ == 1) {
+        for (u64 i = t; i < dim; i += nt) psi[i] = diag_entry<R>(i, I.g0);
+        __syncthreads();
+    }
+    for (int l = 1; l < R_; ++l) {
+        for (int p = 0; p < np; ++p) {
+            batch_fill_pass(a, I, p, l);
+            if (p == 0) {
+                a.in_mode = l == 1 ? IN_GENERATE : IN_LOAD_DIAG;
+                a.dt = l == 1 ? I.gt : batch_layer_tab(I, l - 1);
+            }
+            fwd_body<R, K, LOGR, true>(psi, a, 0, 1, lds);
+            __syncthreads();
+        }
+    }
+    // psi = D psi~ of the last layer unless H is diagonal (then they commute)
+    if (!I.zonly) {
+        const DiagTab d = batch_layer_tab(I, R_ - 1);
+        for (u64 i = t; i < dim; i += nt) psi[i] = cmul(psi[i], diag_entry<R>(i, d));
+        __syncthreads();
+    }
+    // energy: diagonal part with lam = D psi, then the off-diagonal cover passes
+    {
+        double e = 0.0;
+        for (u64 i = t; i < dim; i += nt) {
+            const cx<R> v = psi[i];
+            const double d = I.hdiag[i];
+            e += d * ((double)v.re * v.re + (double)v.im * v.im);
+            cx<R> o;
+            o.re = (R)d * v.re;
+            o.im = (R)d * v.im;
+            lam[i] = o;
+        }
+        const double tot = block_sum(e, sh);
+        if (t == 0) {
+            I.energy[0] = tot;
+            I.energy[1] = 0.0;
+        }
+        __syncthreads();
+    }
+    for (int k = 0; k < I.noff; ++k) {
+        OffArgs o;
+        const BatchOffPass &op = I.offp[k];
+        o.n = I.n;
+        for (int j = 0; j < kMaxTileBits; ++j) o.pos[j] = op.tile.pos[j];
+        o.nruns = op.tile.nruns;
+        for (int q = 0; q <= kMaxTileBits; ++q) {
+            o.run_src[q] = op.tile.run_src[q];
+            o.run_w[q] = op.tile.run_w[q];
+            o.run_dst[q] = op.tile.run_dst[q];
+        }
+        o.ntiles = I.ntiles;
+        o.cls = I.cls;
+        o.c0 = op.c0;
+        o.c1 = op.c1;
+        o.terms = I.terms;
+        o.epart = I.energy;
+        o.estride = 1;
+        off_body<R, K, LOGR>(psi, lam, o, 0, 1, 0, lds, sh);
+        __syncthreads();
+    }
+    // reverse sweep
+    bool post = !I.zonly;
+    for (int l = R_ - 1; l >= 0; --l) {
+        for (int p = 0; p < np; ++p) {
+            const bool last = p == np - 1;
+            batch_fill_pass(a, I, p, l);
+            if (p == 0) {
+                a.phi_gen = l == 0;
+                if (a.phi_gen) a.gt = I.g0;
+                a.diag_phi = post && l > 0;
+                a.diag_lam = post;
+                if (a.diag_phi || a.diag_lam) a.dt = batch_layer_tab(I, l);
+            }
+            a.store_phi = !last || l - 1 >= 1;
+            a.store_lam = !(l == 0 && last);
+            bwd_body<R, K, LOGR, true>(psi, psi, lam, a, 0, 1, 0, lds, sh);
+            __syncthreads();
+        }
+        post = true;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_batch(const BatchInst *insts, const int *order, int count,
+                                               unsigned *counter)
+{
+    __shared__ cx<R> lds[Tile<12, 4>::LDS];
+    __shared__ double sh[8];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int idx = next;
+        __syncthreads();
+        if (idx >= count) break;   // every block leaves once the queue is empty
+        batch_instance<R>(insts[order[idx]], lds, sh);
+    }
+}
+
+}  // namespace
+
 // table set at `tab` for a layer (cz_layer: whether it carries the CZ ladder)
 DiagTab make_diagtab(const gv_ansatz &an, const Chunks &ch, const void *tab, bool cz_layer)
 {
@@ -872,12 +1354,6 @@ DiagTab make_diagtab(const gv_ansatz &an, const Chunks &ch, const void *tab, boo
     return d;
 }
 
-DiagTab layer_tab(const gv_ansatz &an, const Chunks &ch, const FusedTables &t, int layer)
-{
-    return make_diagtab(an, ch, (const char *)t.dtab + (size_t)layer * t.dtab_stride,
-                        layer < an.layers);
-}
-
 TabArgs make_tab_args(const gv_ansatz &an, const Chunks &ch, size_t stride)
 {
     TabArgs ta;
@@ -893,61 +1369,23 @@ TabArgs make_tab_args(const gv_ansatz &an, const Chunks &ch, size_t stride)
     return ta;
 }
 
-FusedArgs base_args(const gv_ansatz &an, const TilePlan &plan, int pass, int layer,
-                    const FusedTables &t)
+void pass_runs(const int8_t *pos, int K, int n, BatchPass *out)
 {
-    FusedArgs a;
-    memset(&a, 0, sizeof(a));
-    a.n = an.n;
-    a.layer = layer;
-    a.nparam_layer = 2 * an.n;
-    for (int j = 0; j < plan.K; ++j) a.pos[j] = plan.pass[pass].pos[j];
-    a.active = plan.pass[pass].active;
-    fill_runs(a, plan.pass[pass], plan.K, an.n);
-    a.ntiles = 1ull << (an.n - plan.K);
-    a.ry = t.ry;
-    a.store_phi = a.store_lam = 1;
-    return a;
+    PassPlan pp;
+    for (int j = 0; j < K; ++j) pp.pos[j] = pos[j];
+    pp.active = 0;
+    FusedArgs fa;
+    memset(&fa, 0, sizeof(fa));
+    fill_runs(fa, pp, K, n);
+    for (int j = 0; j < K; ++j) out->pos[j] = pos[j];
+    out->nruns = fa.nruns;
+    for (int k = 0; k < fa.nruns; ++k) {
+        out->run_src[k] = fa.run_src[k];
+        out->run_w[k] = fa.run_w[k];
+        out->run_dst[k] = fa.run_dst[k];
+    }
 }
 
-inline int elem_grid(u64 dim)
-{
-    const u64 b = (dim + 255) / 256;
-    return (int)(b < 8192 ? b : 8192);
-}
-
-#define GV_LAUNCH_K(KERNEL, PREC, GRID, K, ...)                                                   \
-    do {                                                                                          \
-        switch (K) {                                                                              \
-        case 12:                                                                                  \
-            if (PREC == GV_C64)                                                                   \
-                hipLaunchKernelGGL((KERNEL<float, 12, 4, true>), dim3(GRID), dim3(256), 0, s,     \
-                                   __VA_ARGS__);                                                  \
-            else                                                                                  \
-                hipLaunchKernelGGL((KERNEL<double, 12, 4, true>), dim3(GRID), dim3(256), 0, s,    \
-                                   __VA_ARGS__);                                                  \
-            break;                                                                                \
-        case 10:                                                                                  \
-            if (PREC == GV_C64)                                                                   \
-                hipLaunchKernelGGL((KERNEL<float, 10, 4, true>), dim3(GRID), dim3(64), 0, s,      \
-                                   __VA_ARGS__);                                                  \
-            else                                                                                  \
-                hipLaunchKernelGGL((KERNEL<double, 10, 4, true>), dim3(GRID), dim3(64), 0, s,     \
-                                   __VA_ARGS__);                                                  \
-            break;                                                                                \
-        case 8:                                                                                   \
-            if (PREC == GV_C64)                                                                   \
-                hipLaunchKernelGGL((KERNEL<float, 8, 3, false>), dim3(GRID), dim3(32), 0, s,      \
-                                   __VA_ARGS__);                                                  \
-            else                                                                                  \
-                hipLaunchKernelGGL((KERNEL<double, 8, 3, false>), dim3(GRID), dim3(32), 0, s,     \
-                                   __VA_ARGS__);                                                  \
-            break;                                                                                \
-        default: return hipErrorInvalidValue;                                                     \
-        }                                                                                         \
-    } while (0)
-
-}  // namespace
 
 int fused_grid(int prec, const TilePlan &plan, int n)
 {
@@ -1029,6 +1467,44 @@ hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *la
     a.part = part;
     a.grid = grid;
     GV_LAUNCH_K(k_bwd_pass, prec, grid, plan.K, phi_in, phi, lam, a);
+    return hipGetLastError();
+}
+
+hipError_t fused_layer0_grad(int prec, const void *lam, const gv_ansatz &an, const TilePlan &plan,
+                             int diag_lam, const Chunks &ch, const FusedTables &t, double *part,
+                             int grid, hipStream_t s)
+{
+    Layer0Args a;
+    memset(&a, 0, sizeof(a));
+    a.n = an.n;
+    a.ntiles = 1ull << (an.n - plan.K);
+    a.diag_lam = diag_lam;
+    if (diag_lam) a.dt = layer_tab(an, ch, t, 0);
+    a.gt = make_diagtab(an, ch, t.g0tab, false);
+    a.part = part;
+    a.grid = grid;
+    a.qmask = ~0ull;
+    switch (plan.K) {
+    case 12:
+        if (prec == GV_C64)
+            hipLaunchKernelGGL((k_layer0_grad<float, 12, 4>), dim3(grid), dim3(256), 0, s, lam, a);
+        else
+            hipLaunchKernelGGL((k_layer0_grad<double, 12, 4>), dim3(grid), dim3(256), 0, s, lam, a);
+        break;
+    case 10:
+        if (prec == GV_C64)
+            hipLaunchKernelGGL((k_layer0_grad<float, 10, 4>), dim3(grid), dim3(64), 0, s, lam, a);
+        else
+            hipLaunchKernelGGL((k_layer0_grad<double, 10, 4>), dim3(grid), dim3(64), 0, s, lam, a);
+        break;
+    case 8:
+        if (prec == GV_C64)
+            hipLaunchKernelGGL((k_layer0_grad<float, 8, 3>), dim3(grid), dim3(32), 0, s, lam, a);
+        else
+            hipLaunchKernelGGL((k_layer0_grad<double, 8, 3>), dim3(grid), dim3(32), 0, s, lam, a);
+        break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -1137,6 +1613,32 @@ hipError_t offdiag_pass(int prec, const void *psi, void *lam, int n, int K, cons
         break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t batch_tables(int prec, const BatchInst *dev_insts, int count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    const dim3 grid(64, (unsigned)count);
+    if (prec == GV_C64)
+        hipLaunchKernelGGL(k_batch_tables<float>, grid, dim3(256), 0, s, dev_insts);
+    else
+        hipLaunchKernelGGL(k_batch_tables<double>, grid, dim3(256), 0, s, dev_insts);
+    return hipGetLastError();
+}
+
+hipError_t batch_run(int prec, const BatchInst *dev_insts, const int *order, int count,
+                     unsigned *counter, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || count <= 0) return e;
+    if (prec == GV_C64)
+        hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(256), 0, s, dev_insts, order, count,
+                           counter);
+    else
+        hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(256), 0, s, dev_insts, order, count,
+                           counter);
     return hipGetLastError();
 }
 

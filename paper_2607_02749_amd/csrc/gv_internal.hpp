@@ -133,6 +133,28 @@ struct TilePlan {
 
 bool make_tile_plan(int n, int K, int C, TilePlan *out);
 
+// Diagonal tables of one layer over four chunks of the amplitude index (see
+// gv_fused.hip): T0 | T1 | T2 | T3 and the CZ pairs that straddle chunks.
+struct DiagTab {
+    const void *tab;
+    int b1, b2, b3;
+    int off1, off2, off3;
+    u64 m0, m1, m2;
+    int npair;
+    int8_t pa[4], pb[4];
+};
+
+// What the table kernels need to fill one ansatz's tables.
+struct TabArgs {
+    int n;
+    int rot_layers;
+    int cz_layers;          // layers that carry the CZ ladder
+    int cz;                 // 1 linear CZ, 2 circular CZ, 0 none
+    int b[5];               // chunk bounds 0, b1, b2, b3, n
+    int off[5];             // entry offsets of the chunks within a table set
+    size_t stride;          // bytes per layer
+};
+
 // Diagonal-table chunks: chunk c covers index bits [b[c], b[c+1]); its
 // entries start at off[c] (off[4] = entries per layer)
 struct Chunks {
@@ -232,6 +254,11 @@ hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *la
                                const gv_ansatz &a, const TilePlan &plan, int pass, int layer,
                                const BwdFlags &fl, const Chunks &ch, const FusedTables &t,
                                double *part, int grid, hipStream_t s);
+// Gradients of rotation layer 0 from lam alone (one read), lam before
+// (diag_lam = 0) or after (1) the layer's diagonal; qubits of layer 0 only.
+hipError_t fused_layer0_grad(int prec, const void *lam, const gv_ansatz &an, const TilePlan &plan,
+                             int diag_lam, const Chunks &ch, const FusedTables &t, double *part,
+                             int grid, hipStream_t s);
 hipError_t fused_turnaround(int prec, const void *psi, void *lam, const double *hdiag,
                             const gv_ansatz &a, const TilePlan &plan, int pass, int layer,
                             int in_mode, const Chunks &ch, const FusedTables &t, double *part,
@@ -243,5 +270,49 @@ hipError_t cnot_ladder_gather(int prec, const void *src, void *dst, const gv_ans
                               const Chunks &ch, const FusedTables *t, int layer, int inverse,
                               hipStream_t s);
 int fused_grid(int prec, const TilePlan &plan, int n);
+
+// ---------------------------------------------------------------- batching
+// One tile pass of a batch instance (pass 0 of the plan, or a later one).
+struct BatchPass {
+    int8_t pos[kMaxTileBits];
+    uint32_t active;
+    int nruns;
+    int8_t run_src[kMaxTileBits + 1], run_w[kMaxTileBits + 1], run_dst[kMaxTileBits + 1];
+};
+struct BatchOffPass {
+    BatchPass tile;
+    int c0, c1;
+};
+// Everything the persistent batch kernel needs about one instance.
+struct BatchInst {
+    int n, layers, rot, np, noff, zonly;
+    int cz;                   // 1 linear CZ, 2 circular CZ, 0 no entangler
+    u64 ntiles;
+    u64 qmask;                // gradient written for these qubits' parameters
+    const double *theta;
+    double *energy, *grad;
+    const double *hdiag;
+    const OffClass *cls;
+    const OffTerm *terms;
+    const BatchOffPass *offp;
+    void *psi, *lam;
+    double *ry;
+    char *dtab;
+    size_t dtab_stride;
+    void *gtab, *g0tab;
+    DiagTab dt_cz, dt_plain;  // layer tables (tab = layer 0's; layer l adds l * stride)
+    DiagTab gt, g0;           // D_0 R_0|0..0> and R_0|0..0>
+    TabArgs ta;
+    BatchPass pass[kMaxPasses];
+};
+// tables of every instance (one launch), then the queue counter reset and the
+// persistent kernel; grid = persistent blocks
+hipError_t batch_tables(int prec, const BatchInst *dev_insts, int count, hipStream_t s);
+hipError_t batch_run(int prec, const BatchInst *dev_insts, const int *order, int count,
+                     unsigned *counter, int grid, hipStream_t s);
+// host helpers shared with gv_batch.cpp
+DiagTab make_diagtab(const gv_ansatz &an, const Chunks &ch, const void *tab, bool cz_layer);
+TabArgs make_tab_args(const gv_ansatz &an, const Chunks &ch, size_t stride);
+void pass_runs(const int8_t *pos, int K, int n, BatchPass *out);
 
 }  // namespace gv

@@ -42,6 +42,16 @@ class _Ansatz(ctypes.Structure):
                 ("final_rotation", ctypes.c_int32)]
 
 
+class _Instance(ctypes.Structure):
+    _fields_ = [("ansatz", _Ansatz), ("params_dev", ctypes.c_void_p), ("h", ctypes.c_void_p),
+                ("qubit_mask", ctypes.c_uint64), ("energy_dev", ctypes.c_void_p),
+                ("grad_dev", ctypes.c_void_p)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("order", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -72,14 +82,24 @@ def lib():
     L.gv_pauli_sum_prepare.argtypes = [vp, vp, vp, sz]
     L.gv_energy.argtypes = [vp, vp, vp]
     L.gv_energy_grad.argtypes = [vp, vp, vp, AP, vp, i32, vp, vp]
+    L.gv_pauli_sum_prepare_for.argtypes = [vp, i32, i32, vp, vp, sz]
+    IP = ctypes.POINTER(_Instance)
+    L.gv_batch_query.argtypes = [i32, IP, i32, ctypes.POINTER(sz)]
+    L.gv_batch_create.argtypes = [i32, IP, i32, ctypes.POINTER(_Tuning), vp, sz, vp, i32,
+                                  ctypes.POINTER(vp)]
+    L.gv_batch_run.argtypes = [vp]
+    L.gv_batch_destroy.argtypes = [vp]
+    L.gv_batch_energy_grad.argtypes = [i32, IP, i32, vp, sz, vp]
     L.gv_profile_enable.argtypes = [vp, i32]
     L.gv_profile_reset.argtypes = [vp]
     L.gv_profile_read.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)]
-    for name in ("gv_profile_enable", "gv_profile_reset", "gv_profile_read","gv_query_sizes", "gv_state_create", "gv_state_destroy", "gv_state_set_stream",
+    for name in ("gv_profile_enable", "gv_profile_reset", "gv_profile_read", "gv_query_sizes",
+                 "gv_state_create", "gv_state_destroy", "gv_state_set_stream",
                  "gv_apply_ansatz", "gv_pauli_sum_create", "gv_pauli_sum_destroy",
                  "gv_pauli_sum_info", "gv_pauli_sum_device_bytes", "gv_pauli_sum_prepare",
-                 "gv_energy", "gv_energy_grad"):
+                 "gv_pauli_sum_prepare_for", "gv_energy", "gv_energy_grad", "gv_batch_query",
+                 "gv_batch_create", "gv_batch_run", "gv_batch_destroy", "gv_batch_energy_grad"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -174,7 +194,7 @@ class State:
 
     # per-kernel-class timing (HIP events on the state's stream)
     PROF_KINDS = {"forward_pass": 0, "backward_pass": 1, "energy": 2, "init": 3,
-                  "plain_gate": 4, "other": 5, "offdiag": 6}
+                  "plain_gate": 4, "other": 5, "offdiag": 6, "first_layer": 7}
 
     def profile(self, enable: bool = True):
         _check(lib().gv_profile_enable(self.handle, int(enable)), "gv_profile_enable")
@@ -226,6 +246,19 @@ class PauliSum:
         state._sync_stream()
         _check(lib().gv_pauli_sum_prepare(self.handle, state.handle, _ptr(self.device_buffer),
                                           nb.value), "gv_pauli_sum_prepare")
+        return self
+
+    def prepare_for(self, precision="c64", engine="fused", device="cuda"):
+        """Device form for states of `precision` on `engine` (and for batches)."""
+        nb = ctypes.c_size_t()
+        _check(lib().gv_pauli_sum_device_bytes(self.handle, ctypes.byref(nb)), "device_bytes")
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self._owner, self.device_buffer = _aligned_bytes(nb.value, dev)
+        _check(lib().gv_pauli_sum_prepare_for(self.handle, _PREC[precision], _ENGINE[engine],
+                                              _stream_ptr(dev), _ptr(self.device_buffer), nb.value),
+               "gv_pauli_sum_prepare_for")
         return self
 
     def diagonal(self) -> torch.Tensor:
@@ -296,3 +329,69 @@ def param_mask(n: int, layers: int, qubit_mask: int, final_rotation: int = 0,
                 if (qubit_mask >> q) & 1:
                     m[l * 2 * n + g * n + q] = 1
     return m.to(device)
+
+
+class Batch:
+    """Many independent energy + restricted-gradient evaluations in one
+    persistent kernel (optionally replayed from a HIP graph).
+
+    items: sequence of (Ansatz, theta tensor (float64, device), PauliSum,
+    qubit_mask).  Each PauliSum is prepared here for the batch precision.
+    After run(), energies[i] holds (re, im) and grads[i] the gradient of
+    item i (0 outside its qubit block).  Rewriting the theta tensors in place
+    and calling run() again evaluates the new angles."""
+
+    def __init__(self, items, precision="c64", blocks_per_cu=None, order=None, graph=True,
+                 device="cuda"):
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.precision = _PREC[precision]
+        self.items = list(items)
+        count = len(self.items)
+        total_p = sum(an.num_params for an, _, _, _ in self.items)
+        self.energy_buf = torch.zeros(count, 2, dtype=torch.float64, device=dev)
+        self.grad_buf = torch.zeros(max(total_p, 1), dtype=torch.float64, device=dev)
+        arr = (_Instance * max(count, 1))()
+        self.grads = []
+        off = 0
+        for i, (an, th, h, qmask) in enumerate(self.items):
+            assert th.dtype == torch.float64 and th.is_contiguous() and th.device == dev
+            if h.device_buffer is None:
+                h.prepare_for(precision, "fused", dev)
+            g = self.grad_buf[off:off + an.num_params]
+            off += an.num_params
+            self.grads.append(g)
+            arr[i].ansatz = an.c()
+            arr[i].params_dev = th.data_ptr()
+            arr[i].h = h.handle
+            arr[i].qubit_mask = int(qmask)
+            arr[i].energy_dev = self.energy_buf[i].data_ptr()
+            arr[i].grad_dev = g.data_ptr()
+        self._arr = arr
+        wb = ctypes.c_size_t()
+        _check(lib().gv_batch_query(count, arr, self.precision, ctypes.byref(wb)), "gv_batch_query")
+        self._work_owner, self.work = _aligned_bytes(wb.value, dev)
+        tu = None
+        if blocks_per_cu is not None or order is not None:
+            tu = _Tuning(2 if blocks_per_cu is None else blocks_per_cu, 0 if order is None else order)
+        b = ctypes.c_void_p()
+        _check(lib().gv_batch_create(count, arr, self.precision,
+                                     None if tu is None else ctypes.byref(tu), _ptr(self.work),
+                                     wb.value, _stream_ptr(dev), int(graph), ctypes.byref(b)),
+               "gv_batch_create")
+        self.handle = b
+
+    @property
+    def energies(self) -> torch.Tensor:
+        return self.energy_buf
+
+    def run(self):
+        _check(lib().gv_batch_run(self.handle), "gv_batch_run")
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.gv_batch_destroy(h)
+            self.handle = None
