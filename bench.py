@@ -60,47 +60,39 @@ def time_steps(step, k, torch):
 
 
 def cpu_baseline(inst):
-    """The oracle on host cores, on a bounded sample of one evaluation: a few
-    forward gates and reverse-sweep steps of the n=28 circuit plus the
-    lambda = D psi product, each timed and scaled by how many of them one
-    evaluation runs (the theta-independent diagonal excluded, as on the GPU)."""
+    """The oracle on host cores, on a bounded sample of one evaluation: one
+    whole layer of the n=28 circuit forward (every RY, RZ and CZ gate), the
+    reverse-sweep steps of the same layer, and the lambda = D psi product,
+    each timed once; one evaluation runs L such layers each way (the
+    theta-independent diagonal excluded, as on the GPU)."""
     import oracle
     n, L, ent = inst.n, inst.layers, inst.ent
     ng = oracle.num_gates(n, L, ent)
-    per_layer = 3 * n - 1           # n RY, n RZ, n-1 CZ
+    per_layer = ng // L
     assert ng == L * per_layer
     dim = 1 << n
     phi = np.zeros(dim, np.complex128)
     phi[0] = 1.0
-    lam = np.full(dim, 1e-3 + 0j)
     grad = np.zeros(inst.num_params)
-    # sample gate indices in layer 0: RY q=0, 13, 27; RZ q=0, 27; CZ (0,1), (26,27)
-    fwd = [0, 13, n - 1, n, 2 * n - 1, 2 * n, 3 * n - 2]
-    kinds = ["ry", "ry", "ry", "rz", "rz", "cz", "cz"]
-    t_f = {"ry": [], "rz": [], "cz": []}
-    t_b = {"ry": [], "rz": [], "cz": []}
-    for g, k in zip(fwd, kinds):
-        t0 = time.perf_counter()
-        oracle.apply_gates(n, L, ent, inst.theta, phi, g, 1)
-        t_f[k].append(time.perf_counter() - t0)
-    for g, k in zip([n - 1, 2 * n - 1, 3 * n - 2], ["ry", "rz", "cz"]):
-        t0 = time.perf_counter()
-        oracle.adjoint_gates(n, L, ent, inst.theta, phi, lam, grad, g, 1)
-        t_b[k].append(time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    oracle.apply_gates(n, L, ent, inst.theta, phi, 0, per_layer)
+    t_f = time.perf_counter() - t0
     d = np.random.default_rng(0).normal(size=dim)
     t0 = time.perf_counter()
-    hpsi = oracle.apply_h(n, np.zeros(0, np.uint64), np.zeros(0, np.uint64), np.zeros(0), phi, d)
-    oracle.inner(n, phi, hpsi)
+    lam = oracle.apply_h(n, np.zeros(0, np.uint64), np.zeros(0, np.uint64), np.zeros(0), phi, d)
+    oracle.inner(n, phi, lam)
     t_h = time.perf_counter() - t0
-    counts = {"ry": n * L, "rz": n * L, "cz": (n - 1) * L}
-    est = t_h + sum(counts[k] * (np.mean(t_f[k]) + np.mean(t_b[k])) for k in counts)
-    sample_s = sum(map(sum, t_f.values())) + sum(map(sum, t_b.values())) + t_h
+    t0 = time.perf_counter()
+    oracle.adjoint_gates(n, L, ent, inst.theta, phi, lam, grad, 0, per_layer)
+    t_b = time.perf_counter() - t0
+    est = L * (t_f + t_b) + t_h
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
         "value": 1.0 / est, "unit": "evals/s", "cores": threads, "kind": "oracle",
-        "sample": (f"complex128 oracle at n={n}: 7 forward gates, 3 reverse-sweep steps and one "
-                   f"lambda=D*psi product timed ({sample_s:.1f} s), scaled by the "
-                   f"{ng} gates of one evaluation; est. {est:.1f} s/eval; diagonal build excluded"),
+        "sample": (f"complex128 oracle at n={n}: one full layer forward ({per_layer} gates, "
+                   f"{t_f:.1f} s), its {per_layer} reverse-sweep steps ({t_b:.1f} s) and one "
+                   f"lambda=D*psi product ({t_h:.1f} s), scaled to the {L} layers of one "
+                   f"evaluation: est. {est:.1f} s/eval; diagonal build excluded"),
     }
 
 

@@ -160,6 +160,9 @@ gv_status work_layout(const gv_ansatz &a, gv_precision prec, gv_engine eng, gv_g
         off += w.dtab_stride;
         w.g0tab = off;
         off += w.dtab_stride;
+        w.ldtab_stride = align_up((size_t)ldiag_entries(a.n, K, choose_logr(K)) * s);
+        w.ldtab = off;
+        off += w.ldtab_stride * (size_t)(R > 0 ? 2 * R : 1);
     } else {
         w.grid = kPlainGrid;
     }
@@ -248,11 +251,22 @@ static gv_status plain_forward(gv_state st, const gv_ansatz &an, const double *t
     return GV_OK;
 }
 
+// One tile pass of the forward sweep in snake order: group g (a pass of the
+// tile plan) for rotation layer la, and, when lb >= 0, also for layer
+// lb = la + 1 (a two-layer pass).  slot >= 0: the state after the pass is a
+// checkpoint slot.
+struct FwdOp {
+    int g, la, lb, in_mode, slot;
+};
+
 struct FusedCtx {
     TilePlan plan;
     Chunks ch;
     FusedTables tabs;
     WorkLayout w;
+    std::vector<FwdOp> ops;          // snake order (diagonal entanglers)
+    std::vector<LDiagTab> ld;        // per rotation layer: its diagonal in the last assignment
+    std::vector<LDiagTab> ld0;       // ... and in the load assignment of the same pass
 };
 
 static bool is_cnot(const gv_ansatz &a)
@@ -271,11 +285,13 @@ static gv_status fused_setup(gv_state st, const gv_ansatz &an, const double *the
     make_tile_plan(an.n, K, choose_C(st->prec, K), &c->plan);
     c->ch = make_chunks(an.n, K, choose_logr(K));
     char *w = (char *)st->work;
-    c->tabs.ry = (const double *)(w + c->w.ry_tab);
+    c->tabs.ry = w + c->w.ry_tab;
     c->tabs.dtab = w + c->w.dtab;
     c->tabs.dtab_stride = c->w.dtab_stride;
     c->tabs.gtab = w + c->w.gtab;
     c->tabs.g0tab = w + c->w.g0tab;
+    c->tabs.ldtab = w + c->w.ldtab;
+    c->tabs.ldtab_stride = c->w.ldtab_stride;
     ProfScope ps(st, GV_PROF_OTHER, 0.0);
     return check_hip(fused_build_tables(st->prec, an, c->ch, theta, c->tabs, st->stream), "tables");
 }
@@ -352,6 +368,90 @@ static gv_status last_layer_transform(gv_state st, const gv_ansatz &an, const Fu
     ProfScope ps(st, GV_PROF_OTHER, (lam ? 4.0 : 2.0) * vb);
     return check_hip(fused_diag_apply(st->prec, psi, lam, an, c.ch, c.tabs, l, inverse, st->stream),
                      "diagonal");
+}
+
+// Snake order for diagonal entanglers: layer l runs the plan's passes
+// forward when l is odd and backward when l is even, so the last pass of a
+// layer and the first of the next act on the same tile qubits and fuse into
+// one two-layer pass (the layer diagonal between them is applied in
+// registers).  Layer 0 (the product state) is generated inside layer 1's
+// first pass.  keep_last_single keeps the last layer's pass out of a
+// two-layer pass (the turnaround takes it).  Checkpoint slots go to the
+// states after two-layer passes (every pass when the plan has one pass).
+static std::vector<FwdOp> snake_ops(int np, int upto, bool keep_last_single, bool ckpt)
+{
+    std::vector<FwdOp> ops;
+    for (int l = 1; l <= upto; ++l)
+        for (int i = 0; i < np; ++i) {
+            const int g = (l & 1) ? i : np - 1 - i;
+            if (i == 0 && l >= 2) {
+                FwdOp &pv = ops.back();
+                const bool hold = keep_last_single && l == upto && np == 1;
+                if (pv.lb < 0 && pv.g == g && !hold) {
+                    pv.lb = l;
+                    continue;
+                }
+                ops.push_back({g, l, -1, FWD_LOAD_DIAG, -1});  // np == 1: g == 0
+                continue;
+            }
+            ops.push_back({g, l, -1, (l == 1 && i == 0) ? FWD_GENERATE : FWD_LOAD, -1});
+        }
+    if (ckpt) {
+        int slot = 0;
+        const int last = (int)ops.size() - (keep_last_single ? 2 : 1);
+        for (int k = 0; k < last; ++k)
+            if (ops[k].lb >= 0 || np == 1) ops[k].slot = slot++;
+    }
+    return ops;
+}
+
+static bool use_snake(const gv_ansatz &an) { return !is_cnot(an) && rot_layers(an) >= 2; }
+
+// op list and the two-layer passes' diagonal tables
+static gv_status snake_setup(gv_state st, const gv_ansatz &an, const double *theta,
+                             bool keep_last_single, bool ckpt, FusedCtx *c)
+{
+    const int R = rot_layers(an);
+    c->ops = snake_ops(c->plan.npass, R - 1, keep_last_single, ckpt);
+    c->ld.assign(R, LDiagTab{});
+    c->ld0.assign(R, LDiagTab{});
+    ProfScope ps(st, GV_PROF_OTHER, 0.0);
+    for (const FwdOp &op : c->ops) {
+        if (op.lb < 0) continue;
+        for (int last = 0; last < 2; ++last) {
+            void *tab = (char *)c->tabs.ldtab + (size_t)(2 * op.la + last) * c->tabs.ldtab_stride;
+            LDiagTab *out = last ? &c->ld[op.la] : &c->ld0[op.la];
+            if (gv_status r = check_hip(make_ldiag(st->prec, an, c->plan, op.g, last, op.la, theta,
+                                                   tab, out, st->stream),
+                                        "layout diagonal tables"))
+                return r;
+        }
+    }
+    return GV_OK;
+}
+
+// the first `count` passes of the snake order, from |0...0>
+static gv_status snake_forward(gv_state st, const gv_ansatz &an, const FusedCtx &c, size_t count,
+                               void *psi, char *ckpt, size_t vb)
+{
+    hipStream_t s = st->stream;
+    for (size_t k = 0; k < count; ++k) {
+        const FwdOp &op = c.ops[k];
+        ProfScope ps(st, GV_PROF_FORWARD_PASS, op.in_mode == FWD_GENERATE ? (double)vb : 2.0 * vb);
+        hipError_t e = op.lb >= 0
+                           ? fused_forward2_pass(st->prec, psi, an, c.plan, op.g, op.la, op.in_mode,
+                                                 c.ch, c.tabs, c.ld[op.la], s)
+                           : fused_forward_pass(st->prec, psi, an, c.plan, op.g, op.la, op.in_mode,
+                                                c.ch, c.tabs, s);
+        if (gv_status r = check_hip(e, "forward pass")) return r;
+        if (ckpt && op.slot >= 0) {
+            ProfScope pc(st, GV_PROF_OTHER, 2.0 * vb);
+            if (gv_status r = check_hip(copy_vector(ckpt + (size_t)op.slot * vb, psi, vb, s),
+                                        "checkpoint"))
+                return r;
+        }
+    }
+    return GV_OK;
 }
 
 static gv_status energy_chain(gv_state st, gv_pauli_sum h, void *lam, double *epart,
@@ -488,8 +588,14 @@ gv_status gv_apply_ansatz(gv_state st, const double *theta, const gv_ansatz *a)
         FusedCtx c;
         if (gv_status r = fused_setup(st, *a, theta, GV_GRAD_UNCOMPUTE, &c)) return r;
         const size_t vb = ((size_t)1 << a->n) * amp_bytes(st->prec);
-        if (gv_status r = fused_forward(st, *a, c, rot_layers(*a) - 1, false, st->amps, nullptr, vb))
+        if (use_snake(*a)) {
+            if (gv_status r = snake_setup(st, *a, theta, false, false, &c)) return r;
+            if (gv_status r = snake_forward(st, *a, c, c.ops.size(), st->amps, nullptr, vb))
+                return r;
+        } else if (gv_status r = fused_forward(st, *a, c, rot_layers(*a) - 1, false, st->amps,
+                                               nullptr, vb)) {
             return r;
+        }
         if (gv_status r = last_layer_transform(st, *a, c, st->amps, nullptr, 0)) return r;
     } else {
         if (gv_status r = plain_forward(st, *a, theta)) return r;
@@ -831,6 +937,91 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
     // the turnaround fuses the last forward pass, the energy and the first
     // reverse pass; it needs a diagonal H that commutes with the last layer
     const bool turn = zonly && !cnot && R >= 2;
+
+    if (use_snake(*a)) {
+        if (gv_status r = snake_setup(st, *a, theta, turn, mode == GV_GRAD_CHECKPOINT, &c)) return r;
+        const std::vector<FwdOp> &ops = c.ops;
+        const int nops = (int)ops.size();
+        for (const FwdOp &op : ops)
+            if (op.slot >= R - 2) return set_error(GV_EUNSUPPORTED, "checkpoint slot %d", op.slot);
+        char *ck = mode == GV_GRAD_CHECKPOINT ? w + c.w.ckpt : nullptr;
+        int kstart;
+        if (turn) {
+            if (gv_status r = snake_forward(st, *a, c, nops - 1, psi, ck, vb)) return r;
+            const FwdOp &op = ops[nops - 1];
+            ProfScope ps(st, GV_PROF_ENERGY, 2.0 * vb + 8.0 * (double)((size_t)1 << n));
+            if (gv_status r = check_hip(fused_turnaround(st->prec, psi, lam, h->diag, *a, c.plan,
+                                                         op.g, op.la, op.in_mode, c.ch, c.tabs,
+                                                         part, epart, c.w.grid, s),
+                                        "turnaround"))
+                return r;
+            if (gv_status r = check_hip(reduce_energy(epart, c.w.grid, energy, s), "energy reduce"))
+                return r;
+            kstart = nops - 2;
+        } else {
+            // psi~ -> psi (the last layer's diagonal), E and lam = H psi, then
+            // both vectors back to the point before that diagonal
+            if (gv_status r = snake_forward(st, *a, c, nops, psi, ck, vb)) return r;
+            if (gv_status r = last_layer_transform(st, *a, c, psi, nullptr, 0)) return r;
+            if (gv_status r = energy_chain(st, h, lam, epart, energy)) return r;
+            if (gv_status r = last_layer_transform(st, *a, c, psi, lam, 1)) return r;
+            kstart = nops - 1;
+        }
+        for (int k = kstart; k >= 0; --k) {
+            const FwdOp &op = ops[k];
+            // phi comes from the previous reverse pass (uncompute), from the
+            // turnaround's untouched input, from a checkpoint or recomputed;
+            // the last three have not been through the next pass's load diagonal
+            const void *phi_src = psi;
+            bool fresh = turn && k == kstart;
+            if (k != kstart && op.slot >= 0) {
+                if (mode == GV_GRAD_CHECKPOINT) {
+                    phi_src = ck + (size_t)op.slot * vb;
+                    fresh = true;
+                } else if (mode == GV_GRAD_RECOMPUTE) {
+                    if (gv_status r = snake_forward(st, *a, c, k + 1, psi, nullptr, vb)) return r;
+                    fresh = true;
+                }
+            }
+            const bool next_diag = k + 1 < nops && ops[k + 1].in_mode == FWD_LOAD_DIAG;
+            const bool prev_fresh = k >= 1 && ops[k - 1].slot >= 0 && mode != GV_GRAD_UNCOMPUTE;
+            BwdFlags fl;
+            fl.diag_lam = next_diag;
+            fl.diag_phi = next_diag && !fresh;
+            fl.store_phi = k >= 1 && !prev_fresh;
+            fl.store_lam = 1;
+            // a two-layer pass is undone by two reverse passes: layer lb's RY
+            // gates, then layer la's diagonal (on load) and RY gates
+            if (op.lb >= 0) {
+                BwdFlags fa = fl;
+                fa.store_phi = 1;
+                ProfScope ps(st, GV_PROF_BACKWARD_PASS, 4.0 * vb);
+                if (gv_status r = check_hip(
+                        fused_backward_pass(st->prec, phi_src, psi, lam, *a, c.plan, op.g, op.lb,
+                                            fa, c.ch, c.tabs, part, c.w.grid, s),
+                        "backward pass"))
+                    return r;
+                phi_src = psi;
+                fl.diag_phi = fl.diag_lam = 0;
+            }
+            const double bytes = (3.0 + (fl.store_phi ? 1.0 : 0.0)) * vb;
+            ProfScope ps(st, GV_PROF_BACKWARD_PASS, bytes);
+            hipError_t e = fused_backward_pass(st->prec, phi_src, psi, lam, *a, c.plan, op.g, op.la,
+                                               fl, c.ch, c.tabs, part, c.w.grid, s,
+                                               op.lb >= 0 ? &c.ld0[op.la] : nullptr);
+            if (gv_status r = check_hip(e, "backward pass")) return r;
+        }
+        {   // layer 0: lam now sits after the first layer's diagonal
+            ProfScope ps(st, GV_PROF_FIRST_LAYER, (double)vb);
+            if (gv_status r = check_hip(fused_layer0_grad(st->prec, lam, *a, c.plan, 1, c.ch,
+                                                          c.tabs, part, c.w.grid, s),
+                                        "first-layer gradients"))
+                return r;
+        }
+        st->has_psi = false;
+        ProfScope ps(st, GV_PROF_OTHER, 0.0);
+        return check_hip(reduce_rows(part, P, c.w.grid, mask, grad, s), "grad reduce");
+    }
 
     // What the state and lam buffers hold at the start of a layer's reverse
     // sweep: the point before the layer's diagonal (PRE) or after it (POST).

@@ -171,7 +171,7 @@ gv_status gv_batch_create(int32_t count, const gv_instance *inst, gv_precision p
         b.offp = (const BatchOffPass *)(w + L.offp[i]);
         b.psi = w + L.psi[i];
         b.lam = w + L.lam[i];
-        b.ry = (double *)(w + L.ry[i]);
+        b.ry = w + L.ry[i];
         b.dtab = w + L.dtab[i];
         b.dtab_stride = L.stride[i];
         b.gtab = w + L.gtab[i];

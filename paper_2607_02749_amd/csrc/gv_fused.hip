@@ -64,7 +64,7 @@ struct FusedArgs {
     int nruns;               // tile id -> outside bits, as runs of contiguous bits
     int8_t run_src[kMaxTileBits + 1], run_w[kMaxTileBits + 1], run_dst[kMaxTileBits + 1];
     u64 ntiles;
-    const double *ry;        // [P][2] cos, sin of half angles
+    const void *ry;          // [P] (cos, sin) of half angles, amplitude precision
     DiagTab dt;              // layer diagonal (or the first layer's generator in forward)
     DiagTab gt;              // reverse: generator of R_0|0...0>
     const double *hdiag;     // turnaround: diagonal of the Hamiltonian
@@ -72,6 +72,8 @@ struct FusedArgs {
     double *epart;           // turnaround: 2 x grid energy partials
     int grid;
     u64 qmask;               // qubits whose gradient rows are written (others get 0)
+    int layer2;              // two-layer passes: the second rotation layer
+    LDiagTab ld;             // two-layer passes: diagonal of `layer` in the last assignment
 };
 
 template <int K, int LOGR>
@@ -230,6 +232,43 @@ struct P0Diag {
     }
 };
 
+// A layer diagonal in an arbitrary pass layout (LDiagTab): per thread and
+// tile the product of the thread and tile-id factors with the signs of the
+// straddling CZ pairs, then per register its factor and sign.
+template <typename R, int K, int LOGR>
+struct LDiag {
+    static constexpr int NR = 1 << LOGR;
+    cx<R> w;
+    uint32_t neg;
+    __device__ static __forceinline__ uint32_t reg_pattern(int k)
+    {
+        constexpr uint32_t P[5] = {0xaaaaaaaau, 0xccccccccu, 0xf0f0f0f0u, 0xff00ff00u, 0xffff0000u};
+        constexpr uint32_t ALL = (NR >= 32) ? 0xffffffffu : ((1u << NR) - 1u);
+        return P[k] & ALL;
+    }
+    // idx: the thread's index bits outside the registers (tile base | thread offset)
+    __device__ __forceinline__ void tile(const LDiagTab &d, u64 tile_id, u64 idx, int t)
+    {
+        const cx<R> *T = (const cx<R> *)d.tab;
+        w = cmul(T[t], cmul(T[d.offB1 + (tile_id & ((1ull << d.h1) - 1))],
+                            T[d.offB2 + (tile_id >> d.h1)]));
+        neg = 0;
+        int par = 0;
+        for (int k = 0; k < d.npair; ++k) {
+            const int ka = d.ka[k], kb = d.kb[k];
+            if (ka < 0 && kb < 0) par ^= (int)((idx >> d.pa[k]) & (idx >> d.pb[k]) & 1);
+            else if (ka >= 0) neg ^= ((idx >> d.pb[k]) & 1) ? reg_pattern(ka) : 0u;
+            else neg ^= ((idx >> d.pa[k]) & 1) ? reg_pattern(kb) : 0u;
+        }
+        if (par) w = cneg(w);
+    }
+    __device__ __forceinline__ cx<R> at(const LDiagTab &d, int r) const
+    {
+        const cx<R> v = cmul(w, ((const cx<R> *)d.tab)[d.offR + r]);
+        return ((neg >> r) & 1) ? cneg(v) : v;
+    }
+};
+
 template <typename R>
 __device__ __forceinline__ cx<R> cmul_conj(cx<R> a, cx<R> d)  // a * conj(d)
 {
@@ -252,7 +291,7 @@ __device__ __forceinline__ void rot_pair(cx<R> &x, cx<R> &y, R c, R sn)
 
 // forward rotations of the tile bits that are new in assignment AI
 template <typename R, int K, int LOGR, int AI>
-__device__ __forceinline__ void fwd_assign(cx<R> (&v)[1 << LOGR], const FusedArgs &a)
+__device__ __forceinline__ void fwd_assign(cx<R> (&v)[1 << LOGR], const FusedArgs &a, int layer)
 {
     using T = Tile<K, LOGR>;
     constexpr int LO = T::lo(AI);
@@ -261,8 +300,8 @@ __device__ __forceinline__ void fwd_assign(cx<R> (&v)[1 << LOGR], const FusedArg
     for (int k = 0; k < LOGR; ++k) {
         const int j = LO + k;
         if (!((NEW >> j) & 1) || !((a.active >> j) & 1)) continue;
-        const double *e = a.ry + 2 * ((int64_t)a.layer * a.nparam_layer + a.pos[j]);
-        const R c = (R)e[0], sn = (R)e[1];
+        const cx<R> e = ((const cx<R> *)a.ry)[(int64_t)layer * a.nparam_layer + a.pos[j]];
+        const R c = e.re, sn = e.im;
 #pragma unroll
         for (int r = 0; r < T::NR; ++r)
             if (!(r & (1 << k))) rot_pair(v[r], v[r | (1 << k)], c, sn);
@@ -274,7 +313,7 @@ __device__ __forceinline__ void fwd_assign(cx<R> (&v)[1 << LOGR], const FusedArg
 // then RY(-theta) on both vectors
 template <typename R, int K, int LOGR, int AI>
 __device__ __forceinline__ void bwd_assign(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
-                                           double (&accY)[K], const FusedArgs &a)
+                                           double (&accY)[K], const FusedArgs &a, int layer)
 {
     using T = Tile<K, LOGR>;
     constexpr int LO = T::lo(AI);
@@ -283,8 +322,8 @@ __device__ __forceinline__ void bwd_assign(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 <
     for (int k = 0; k < LOGR; ++k) {
         const int j = LO + k;
         if (!((NEW >> j) & 1) || !((a.active >> j) & 1)) continue;
-        const double *e = a.ry + 2 * ((int64_t)a.layer * a.nparam_layer + a.pos[j]);
-        const R c = (R)e[0], sn = -(R)e[1];
+        const cx<R> e = ((const cx<R> *)a.ry)[(int64_t)layer * a.nparam_layer + a.pos[j]];
+        const R c = e.re, sn = -e.im;
         R g = 0;
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
@@ -321,12 +360,26 @@ __device__ __forceinline__ void exchange(cx<R> (&v)[1 << LOGR], cx<R> *lds, int 
 template <typename R, int K, int LOGR, int AI>
 struct FwdChain {
     __device__ static __forceinline__ void run(cx<R> (&v)[1 << LOGR], cx<R> *lds, int t,
-                                               const FusedArgs &a)
+                                               const FusedArgs &a, int layer)
     {
         using T = Tile<K, LOGR>;
         exchange<R, K, LOGR, T::lo(AI - 1), T::lo(AI)>(v, lds, t);
-        fwd_assign<R, K, LOGR, AI>(v, a);
-        if constexpr (AI + 1 < T::NA) FwdChain<R, K, LOGR, AI + 1>::run(v, lds, t, a);
+        fwd_assign<R, K, LOGR, AI>(v, a, layer);
+        if constexpr (AI + 1 < T::NA) FwdChain<R, K, LOGR, AI + 1>::run(v, lds, t, a, layer);
+    }
+};
+
+// forward assignments in the order AI, AI-1, ..., 0 (each after an exchange
+// from AI+1): the second layer of a two-layer pass
+template <typename R, int K, int LOGR, int AI>
+struct FwdChainRev {
+    __device__ static __forceinline__ void run(cx<R> (&v)[1 << LOGR], cx<R> *lds, int t,
+                                               const FusedArgs &a, int layer)
+    {
+        using T = Tile<K, LOGR>;
+        exchange<R, K, LOGR, T::lo(AI + 1), T::lo(AI)>(v, lds, t);
+        fwd_assign<R, K, LOGR, AI>(v, a, layer);
+        if constexpr (AI > 0) FwdChainRev<R, K, LOGR, AI - 1>::run(v, lds, t, a, layer);
     }
 };
 
@@ -335,30 +388,31 @@ template <typename R, int K, int LOGR, int AI>
 struct BwdChain {
     __device__ static __forceinline__ void run(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
                                                double (&accY)[K], cx<R> *lds, int t,
-                                               const FusedArgs &a)
+                                               const FusedArgs &a, int layer)
     {
         using T = Tile<K, LOGR>;
         exchange<R, K, LOGR, T::lo(AI - 1), T::lo(AI)>(f, lds, t);
         exchange<R, K, LOGR, T::lo(AI - 1), T::lo(AI)>(l, lds, t);
-        bwd_assign<R, K, LOGR, AI>(f, l, accY, a);
-        if constexpr (AI + 1 < T::NA) BwdChain<R, K, LOGR, AI + 1>::run(f, l, accY, lds, t, a);
+        bwd_assign<R, K, LOGR, AI>(f, l, accY, a, layer);
+        if constexpr (AI + 1 < T::NA)
+            BwdChain<R, K, LOGR, AI + 1>::run(f, l, accY, lds, t, a, layer);
     }
 };
 
 // reverse assignments in the order AI, AI-1, ..., 0 (each after an exchange
-// from AI+1), used by the turnaround whose data ends the forward part in the
-// last assignment
+// from AI+1), used where the data ends a forward or reverse part in the last
+// assignment
 template <typename R, int K, int LOGR, int AI>
 struct BwdChainRev {
     __device__ static __forceinline__ void run(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
                                                double (&accY)[K], cx<R> *lds, int t,
-                                               const FusedArgs &a)
+                                               const FusedArgs &a, int layer)
     {
         using T = Tile<K, LOGR>;
         exchange<R, K, LOGR, T::lo(AI + 1), T::lo(AI)>(f, lds, t);
         exchange<R, K, LOGR, T::lo(AI + 1), T::lo(AI)>(l, lds, t);
-        bwd_assign<R, K, LOGR, AI>(f, l, accY, a);
-        if constexpr (AI > 0) BwdChainRev<R, K, LOGR, AI - 1>::run(f, l, accY, lds, t, a);
+        bwd_assign<R, K, LOGR, AI>(f, l, accY, a, layer);
+        if constexpr (AI > 0) BwdChainRev<R, K, LOGR, AI - 1>::run(f, l, accY, lds, t, a, layer);
     }
 };
 
@@ -406,8 +460,8 @@ __device__ __forceinline__ void fwd_body(cx<R> *psi, const FusedArgs &a, u64 t0,
         const u64 base = tile_base(tile, a);
         cx<R> v[T::NR];
         load_tile<R, K, LOGR, CONTIG>(v, psi, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
-        fwd_assign<R, K, LOGR, 0>(v, a);
-        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(v, lds, t, a);
+        fwd_assign<R, K, LOGR, 0>(v, a, a.layer);
+        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(v, lds, t, a, a.layer);
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) psi[base | toff_st | mst.off(r)] = v[r];
     }
@@ -420,32 +474,64 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_pass(void *psi_, FusedA
     fwd_body<R, K, LOGR, CONTIG>((cx<R> *)psi_, a, blockIdx.x, gridDim.x, lds);
 }
 
-// Block sums of the gradient partials of the pass's active tile qubits.
-// The RZ partials come as one accumulator per register bit of the load
-// assignment (accZr) and one per-thread total (ztot) whose sign for thread
-// bit j is that bit of the thread id; HAVEZ = false writes zeros.
-template <typename R, int K, int LOGR, bool HAVEZ>
+// Block sums of the gradient partials of the pass's active tile qubits for
+// rotation layer `layer`.  The RZ partials come as one accumulator per
+// register bit of assignment AZ (accZr) and one per-thread total (ztot)
+// whose sign for a thread bit is that bit of the thread id; HAVEZ = false
+// writes zeros.
+template <typename R, int K, int LOGR, int AZ, bool HAVEZ>
 __device__ __forceinline__ void write_partials(const double (&accY)[K], const double (&accZr)[LOGR],
                                                double ztot, double *sh, const FusedArgs &a,
-                                               int col)
+                                               int layer, int col)
 {
-    constexpr int LD = K - LOGR;
+    constexpr int LZ = Tile<K, LOGR>::lo(AZ);
     const int t = threadIdx.x;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         if (!((a.active >> j) & 1)) continue;
         const bool keep = (a.qmask >> a.pos[j]) & 1;
-        const int64_t row = (int64_t)a.layer * a.nparam_layer + a.pos[j];
+        const int64_t row = (int64_t)layer * a.nparam_layer + a.pos[j];
         const double y = block_sum(accY[j], sh);
         if (t == 0) a.part[row * a.grid + col] = keep ? y : 0.0;
         double z = 0.0;
-        if constexpr (HAVEZ)
-            z = block_sum(j >= LD ? accZr[j - LD] : (((t >> j) & 1) ? -ztot : ztot), sh);
+        if constexpr (HAVEZ) {
+            const int tb = j < LZ ? j : j - LOGR;   // thread-id bit of tile bit j
+            const bool reg = j >= LZ && j < LZ + LOGR;
+            z = block_sum(reg ? accZr[j - LZ] : (((t >> tb) & 1) ? -ztot : ztot), sh);
+        }
         if (t == 0) a.part[(row + a.n) * a.grid + col] = keep ? z : 0.0;
     }
 }
 
-template <typename R, int K, int LOGR, bool CONTIG>
+// RZ partials of the active tile qubits in assignment AI: per register bit
+// the signed sum of Im(conj(lam_i) phi_i), and the thread's total (its sign
+// per thread bit is applied at the block sum)
+template <typename R, int K, int LOGR, int AI>
+__device__ __forceinline__ void z_partials(const cx<R> (&f)[1 << LOGR], const cx<R> (&l)[1 << LOGR],
+                                           double (&accZr)[LOGR], double &ztot, const FusedArgs &a)
+{
+    constexpr int NR = 1 << LOGR, LZ = Tile<K, LOGR>::lo(AI);
+    R tt[NR];
+    R tsum = 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        tt[r] = l[r].re * f[r].im - l[r].im * f[r].re;
+        tsum += tt[r];
+    }
+    ztot += (double)tsum;
+#pragma unroll
+    for (int k = 0; k < LOGR; ++k) {
+        if (!((a.active >> (LZ + k)) & 1)) continue;
+        R s = 0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) s += ((r >> k) & 1) ? -tt[r] : tt[r];
+        accZr[k] += (double)s;
+    }
+}
+
+// LDG: both vectors first lose the diagonal of `layer` in the load layout
+// (a.ld), for the reverse of a two-layer pass.
+template <typename R, int K, int LOGR, bool CONTIG, bool LDG>
 __device__ __forceinline__ void bwd_body(const cx<R> *phi_in, cx<R> *phi, cx<R> *lam,
                                          const FusedArgs &a, u64 t0, u64 tstep, int col,
                                          cx<R> *lds, double *sh)
@@ -461,6 +547,7 @@ __device__ __forceinline__ void bwd_body(const cx<R> *phi_in, cx<R> *phi, cx<R> 
     const bool any_diag = a.diag_phi || a.diag_lam;
     if (any_diag) pd.init(a.dt, t);
     if (a.phi_gen) pg.init(a.gt, t);
+    LDiag<R, K, LOGR> dg;
     double accY[K], accZr[LOGR], ztot = 0.0;
 #pragma unroll
     for (int j = 0; j < K; ++j) accY[j] = 0.0;
@@ -489,27 +576,19 @@ __device__ __forceinline__ void bwd_body(const cx<R> *phi_in, cx<R> *phi, cx<R> 
                 if (a.diag_lam) l[r] = cmul_conj(l[r], d);
             }
         }
-        // RZ gradients of the active tile qubits: sum_i z_q(i) Im(conj(lam_i) phi_i)
-        {
-            R tt[T::NR];
-            R tsum = 0;
+        if constexpr (LDG) {
+            dg.tile(a.ld, tile, base | toff_ld, t);
 #pragma unroll
             for (int r = 0; r < T::NR; ++r) {
-                tt[r] = l[r].re * f[r].im - l[r].im * f[r].re;
-                tsum += tt[r];
-            }
-            ztot += (double)tsum;   // thread bits: the sign is applied at the block sum
-#pragma unroll
-            for (int k = 0; k < LOGR; ++k) {    // register bits of the load assignment
-                if (!((a.active >> (LD + k)) & 1)) continue;
-                R s = 0;
-#pragma unroll
-                for (int r = 0; r < T::NR; ++r) s += ((r >> k) & 1) ? -tt[r] : tt[r];
-                accZr[k] += (double)s;
+                const cx<R> d = dg.at(a.ld, r);
+                f[r] = cmul_conj(f[r], d);
+                l[r] = cmul_conj(l[r], d);
             }
         }
-        bwd_assign<R, K, LOGR, 0>(f, l, accY, a);
-        if constexpr (T::NA > 1) BwdChain<R, K, LOGR, 1>::run(f, l, accY, lds, t, a);
+        // RZ gradients of the active tile qubits: sum_i z_q(i) Im(conj(lam_i) phi_i)
+        z_partials<R, K, LOGR, 0>(f, l, accZr, ztot, a);
+        bwd_assign<R, K, LOGR, 0>(f, l, accY, a, a.layer);
+        if constexpr (T::NA > 1) BwdChain<R, K, LOGR, 1>::run(f, l, accY, lds, t, a, a.layer);
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
             const u64 i = base | toff_st | mst.off(r);
@@ -517,7 +596,7 @@ __device__ __forceinline__ void bwd_body(const cx<R> *phi_in, cx<R> *phi, cx<R> 
             if (a.store_lam) lam[i] = l[r];
         }
     }
-    write_partials<R, K, LOGR, true>(accY, accZr, ztot, sh, a, col);
+    write_partials<R, K, LOGR, 0, true>(accY, accZr, ztot, sh, a, a.layer, col);
 }
 
 template <typename R, int K, int LOGR, bool CONTIG>
@@ -526,8 +605,19 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const void *phi_in
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
-    bwd_body<R, K, LOGR, CONTIG>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_, a,
-                                 blockIdx.x, gridDim.x, blockIdx.x, lds, sh);
+    bwd_body<R, K, LOGR, CONTIG, false>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_, a,
+                                        blockIdx.x, gridDim.x, blockIdx.x, lds, sh);
+}
+
+// the reverse pass that first undoes the layer diagonal given in a.ld
+template <typename R, int K, int LOGR, bool CONTIG>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_ld_pass(const void *phi_in_, void *phi_,
+                                                                 void *lam_, FusedArgs a)
+{
+    __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
+    __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
+    bwd_body<R, K, LOGR, CONTIG, true>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_, a,
+                                       blockIdx.x, gridDim.x, blockIdx.x, lds, sh);
 }
 
 // Last forward pass of the last layer + energy + first reverse pass, for a
@@ -560,8 +650,8 @@ __device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const Fu
         const u64 base = tile_base(tile, a);
         cx<R> f[T::NR], l[T::NR];
         load_tile<R, K, LOGR, CONTIG>(f, psi, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
-        fwd_assign<R, K, LOGR, 0>(f, a);
-        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(f, lds, t, a);
+        fwd_assign<R, K, LOGR, 0>(f, a, a.layer);
+        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(f, lds, t, a, a.layer);
         // energy and lam in the last assignment's layout
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
@@ -570,13 +660,13 @@ __device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const Fu
             l[r].re = (R)d * f[r].re;
             l[r].im = (R)d * f[r].im;
         }
-        bwd_assign<R, K, LOGR, T::NA - 1>(f, l, accY, a);
+        bwd_assign<R, K, LOGR, T::NA - 1>(f, l, accY, a, a.layer);
         if constexpr (T::NA > 1)
-            BwdChainRev<R, K, LOGR, T::NA - 2>::run(f, l, accY, lds, t, a);
+            BwdChainRev<R, K, LOGR, T::NA - 2>::run(f, l, accY, lds, t, a, a.layer);
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) lam[base | toff_ld | mld.off(r)] = l[r];
     }
-    write_partials<R, K, LOGR, false>(accY, accZr, 0.0, sh, a, col);
+    write_partials<R, K, LOGR, 0, false>(accY, accZr, 0.0, sh, a, a.layer, col);
     const double e = block_sum(eacc, sh);
     if (t == 0) {
         a.epart[col] = e;
@@ -584,8 +674,10 @@ __device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const Fu
     }
 }
 
+// Capped at 256 registers (two waves per SIMD): the few spilled values cost
+// less than running one wave per SIMD.
 template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_pass(const void *psi_, void *lam_,
+__global__ __launch_bounds__(1 << (K - LOGR)) __attribute__((amdgpu_waves_per_eu(2))) void k_turn_pass(const void *psi_, void *lam_,
                                                                FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
@@ -594,6 +686,49 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_pass(const void *psi_,
                                   blockIdx.x, lds, sh);
 }
 
+
+// ------------------------------------------------------ two-layer passes
+
+// The last pass of rotation layer `layer` and the first of layer2 = layer + 1
+// act on the same tile qubits, so one pass does both: the first layer's RY
+// gates through the assignments 0 .. NA-1, the first layer's diagonal in
+// the last assignment, then the second layer's RY gates back through
+// NA-1 .. 0, and the tile is stored in the load layout.
+template <typename R, int K, int LOGR, bool CONTIG>
+__device__ __forceinline__ void fwd2_body(cx<R> *psi, const FusedArgs &a, u64 t0, u64 tstep,
+                                          cx<R> *lds)
+{
+    using T = Tile<K, LOGR>;
+    const int t = threadIdx.x;
+    constexpr int LD = T::lo(0), ST = T::lo(T::NA - 1);
+    const u64 toff_ld = thread_off<K, LOGR>(t, LD, a), toff_st = thread_off<K, LOGR>(t, ST, a);
+    RegMap<LOGR, CONTIG> mld;
+    mld.init(a.pos + LD);
+    P0Diag<R, K, LOGR> pd;
+    if (a.in_mode != IN_LOAD) pd.init(a.dt, t);
+    LDiag<R, K, LOGR> dg;
+    for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
+        const u64 base = tile_base(tile, a);
+        cx<R> v[T::NR];
+        load_tile<R, K, LOGR, CONTIG>(v, psi, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
+        fwd_assign<R, K, LOGR, 0>(v, a, a.layer);
+        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(v, lds, t, a, a.layer);
+        dg.tile(a.ld, tile, base | toff_st, t);
+#pragma unroll
+        for (int r = 0; r < T::NR; ++r) v[r] = cmul(v[r], dg.at(a.ld, r));
+        fwd_assign<R, K, LOGR, T::NA - 1>(v, a, a.layer2);
+        if constexpr (T::NA > 1) FwdChainRev<R, K, LOGR, T::NA - 2>::run(v, lds, t, a, a.layer2);
+#pragma unroll
+        for (int r = 0; r < T::NR; ++r) psi[base | toff_ld | mld.off(r)] = v[r];
+    }
+}
+
+template <typename R, int K, int LOGR, bool CONTIG>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd2_pass(void *psi_, FusedArgs a)
+{
+    __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
+    fwd2_body<R, K, LOGR, CONTIG>((cx<R> *)psi_, a, blockIdx.x, gridDim.x, lds);
+}
 
 // ------------------------------------------------ first-layer gradients
 
@@ -867,17 +1002,23 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_offdiag_pass(const void *ps
 }
 
 // ------------------------------------------------------------ table kernels
-// ry[p] = (cos(theta_p / 2), sin(theta_p / 2))
-__device__ __forceinline__ void ry_entry(double theta, double *e)
+// ry[p] = (cos(theta_p / 2), sin(theta_p / 2)), computed in FP64 and
+// rounded once to the amplitude precision (so the passes read them as
+// scalar operands)
+template <typename R>
+__device__ __forceinline__ void ry_entry(double theta, cx<R> *e)
 {
-    sincos(0.5 * theta, &e[1], &e[0]);
+    double sn, cs;
+    sincos(0.5 * theta, &sn, &cs);
+    *e = cx<R>{(R)cs, (R)sn};
 }
 
-__global__ void k_ry_table(const double *theta, int64_t np, double *ry)
+template <typename R>
+__global__ void k_ry_table(const double *theta, int64_t np, cx<R> *ry)
 {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
          p += (int64_t)gridDim.x * blockDim.x)
-        ry_entry(theta[p], ry + 2 * p);
+        ry_entry<R>(theta[p], ry + p);
 }
 
 
@@ -1018,6 +1159,44 @@ __global__ void k_cnot_gather(const cx<R> *src, cx<R> *dst, int n, int circular,
     }
 }
 
+// Entries of one LDiagTab: entry m of a group is the product over the
+// group's qubits of the RZ factor e^{-i phi_q/2} (bit clear) or e^{+i phi_q/2}
+// (bit set), times -1 per CZ pair inside the group with both bits set.  The
+// phase is summed in FP64 and rounded once.
+template <typename R>
+__global__ void k_ldiag_table(const double *theta, LDiagBuild b, cx<R> *out)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= b.total) return;
+    int first, count, m;
+    if (e < b.offR) { first = 0; count = b.nt; m = e; }
+    else if (e < b.offB1) { first = b.nt; count = b.nr; m = e - b.offR; }
+    else if (e < b.offB2) { first = b.nt + b.nr; count = b.h1; m = e - b.offB1; }
+    else { first = b.nt + b.nr + b.h1; count = b.h2; m = e - b.offB2; }
+    const double *phi = theta + (int64_t)b.layer * 2 * b.n + b.n;
+    double ph = 0.0;
+    int par = 0;
+    for (int j = 0; j < count; ++j) {
+        const int q = b.q[first + j];
+        const bool set = (m >> j) & 1;
+        ph += set ? 0.5 * phi[q] : -0.5 * phi[q];
+        if (!set || b.cz == 0) continue;
+        // partner of q in the ladder: q + 1, and n-1 -> 0 when circular
+        int p = q + 1;
+        if (p == b.n) p = (b.cz == 2 && b.n > 2) ? 0 : -1;
+        if (p < 0) continue;
+        for (int i = 0; i < count; ++i)
+            if (b.q[first + i] == p && ((m >> i) & 1)) par ^= 1;
+    }
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    if (par) {
+        sn = -sn;
+        cs = -cs;
+    }
+    out[e] = cx<R>{(R)cs, (R)sn};
+}
+
 // ------------------------------------------------------------ host helpers
 
 void fill_runs(FusedArgs &a, const PassPlan &pp, int K, int n)
@@ -1127,7 +1306,7 @@ __global__ void k_batch_tables(const BatchInst *insts)
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         if (e < np) {
-            ry_entry(I.theta[e], I.ry + 2 * e);
+            ry_entry<R>(I.theta[e], (cx<R> *)I.ry + e);
             continue;
         }
         const int64_t f = e - np;
@@ -1291,7 +1470,7 @@ __device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh)
             }
             a.store_phi = !last || l - 1 >= 1;
             a.store_lam = !(l == 0 && last);
-            bwd_body<R, K, LOGR, true>(psi, psi, lam, a, 0, 1, 0, lds, sh);
+            bwd_body<R, K, LOGR, true, false>(psi, psi, lam, a, 0, 1, 0, lds, sh);
             __syncthreads();
         }
         post = true;
@@ -1399,8 +1578,12 @@ hipError_t fused_build_tables(int prec, const gv_ansatz &an, const Chunks &ch,
                               const double *theta, const FusedTables &t, hipStream_t s)
 {
     const int64_t np = nparams(an);
-    hipLaunchKernelGGL(k_ry_table, dim3((int)((np + 255) / 256)), dim3(256), 0, s, theta, np,
-                       (double *)t.ry);
+    if (prec == GV_C64)
+        hipLaunchKernelGGL(k_ry_table<float>, dim3((int)((np + 255) / 256)), dim3(256), 0, s,
+                           theta, np, (cx<float> *)t.ry);
+    else
+        hipLaunchKernelGGL(k_ry_table<double>, dim3((int)((np + 255) / 256)), dim3(256), 0, s,
+                           theta, np, (cx<double> *)t.ry);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     TabArgs ta = make_tab_args(an, ch, t.dtab_stride);
@@ -1453,9 +1636,10 @@ hipError_t fused_forward_pass(int prec, void *psi, const gv_ansatz &an, const Ti
 hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *lam,
                                const gv_ansatz &an, const TilePlan &plan, int pass, int layer,
                                const BwdFlags &fl, const Chunks &ch, const FusedTables &t,
-                               double *part, int grid, hipStream_t s)
+                               double *part, int grid, hipStream_t s, const LDiagTab *ld_load)
 {
     if ((fl.phi_generate || fl.diag_phi || fl.diag_lam) && pass != 0) return hipErrorInvalidValue;
+    if (ld_load && (fl.phi_generate || fl.diag_phi || fl.diag_lam)) return hipErrorInvalidValue;
     FusedArgs a = base_args(an, plan, pass, layer, t);
     a.phi_gen = fl.phi_generate;
     if (fl.phi_generate) a.gt = make_diagtab(an, ch, t.g0tab, false);
@@ -1466,7 +1650,12 @@ hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *la
     a.store_lam = fl.store_lam;
     a.part = part;
     a.grid = grid;
-    GV_LAUNCH_K(k_bwd_pass, prec, grid, plan.K, phi_in, phi, lam, a);
+    if (ld_load) {
+        a.ld = *ld_load;
+        GV_LAUNCH_K(k_bwd_ld_pass, prec, grid, plan.K, phi_in, phi, lam, a);
+    } else {
+        GV_LAUNCH_K(k_bwd_pass, prec, grid, plan.K, phi_in, phi, lam, a);
+    }
     return hipGetLastError();
 }
 
@@ -1505,6 +1694,114 @@ hipError_t fused_layer0_grad(int prec, const void *lam, const gv_ansatz &an, con
         break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+int ldiag_entries(int n, int K, int LOGR)
+{
+    const int nb = n - K, h1 = nb - nb / 2, h2 = nb / 2;
+    return (1 << (K - LOGR)) + (1 << LOGR) + (1 << h1) + (1 << h2);
+}
+
+static int assign_lo(int K, int LOGR, int a)
+{
+    return a == 0 ? K - LOGR : std::min((a - 1) * LOGR, K - LOGR);
+}
+
+hipError_t make_ldiag(int prec, const gv_ansatz &an, const TilePlan &plan, int pass, int last,
+                      int layer, const double *theta, void *tab, LDiagTab *out, hipStream_t s)
+{
+    const int n = an.n, K = plan.K, LOGR = K == 8 ? 3 : 4;
+    const int NA = 1 + (K - LOGR + LOGR - 1) / LOGR;
+    const int lo = assign_lo(K, LOGR, last ? NA - 1 : 0);
+    const PassPlan &pp = plan.pass[pass];
+    LDiagBuild b;
+    memset(&b, 0, sizeof(b));
+    b.n = n;
+    b.layer = layer;
+    b.nt = K - LOGR;
+    b.nr = LOGR;
+    const int nb = n - K;
+    b.h1 = nb - nb / 2;
+    b.h2 = nb / 2;
+    int group[64];   // 0 thread, 1 register, 2 B1, 3 B2
+    int regbit[64];
+    int c = 0;
+    bool in_tile[64] = {false};
+    for (int j = 0; j < K; ++j) in_tile[pp.pos[j]] = true;
+    for (int j = 0; j < K; ++j)
+        if (j < lo || j >= lo + LOGR) {
+            b.q[c++] = pp.pos[j];
+            group[pp.pos[j]] = 0;
+            regbit[pp.pos[j]] = -1;
+        }
+    for (int k = 0; k < LOGR; ++k) {
+        b.q[c++] = pp.pos[lo + k];
+        group[pp.pos[lo + k]] = 1;
+        regbit[pp.pos[lo + k]] = k;
+    }
+    int m = 0;
+    for (int q = 0; q < n; ++q) {
+        if (in_tile[q]) continue;
+        b.q[c++] = (int8_t)q;
+        group[q] = m < b.h1 ? 2 : 3;
+        regbit[q] = -1;
+        ++m;
+    }
+    const bool cz_layer = layer < an.layers;
+    b.cz = !cz_layer ? 0 : (an.ent == GV_ENT_CZ_LINEAR ? 1 : (an.ent == GV_ENT_CZ_CIRCULAR ? 2 : 0));
+    b.offR = 1 << b.nt;
+    b.offB1 = b.offR + (1 << b.nr);
+    b.offB2 = b.offB1 + (1 << b.h1);
+    b.total = b.offB2 + (1 << b.h2);
+
+    LDiagTab d;
+    memset(&d, 0, sizeof(d));
+    d.tab = tab;
+    d.offR = b.offR;
+    d.offB1 = b.offB1;
+    d.offB2 = b.offB2;
+    d.h1 = b.h1;
+    auto add = [&](int qa, int qb) {
+        if (group[qa] == group[qb]) return true;
+        if (d.npair >= kMaxLPairs) return false;
+        d.pa[d.npair] = (int8_t)qa;
+        d.pb[d.npair] = (int8_t)qb;
+        d.ka[d.npair] = (int8_t)regbit[qa];
+        d.kb[d.npair] = (int8_t)regbit[qb];
+        ++d.npair;
+        return true;
+    };
+    if (b.cz != 0) {
+        for (int q = 0; q + 1 < n; ++q)
+            if (!add(q, q + 1)) return hipErrorInvalidValue;
+        if (b.cz == 2 && n > 2 && !add(n - 1, 0)) return hipErrorInvalidValue;
+    }
+    *out = d;
+    const int grid = (b.total + 255) / 256;
+    if (prec == GV_C64)
+        hipLaunchKernelGGL(k_ldiag_table<float>, dim3(grid), dim3(256), 0, s, theta, b,
+                           (cx<float> *)tab);
+    else
+        hipLaunchKernelGGL(k_ldiag_table<double>, dim3(grid), dim3(256), 0, s, theta, b,
+                           (cx<double> *)tab);
+    return hipGetLastError();
+}
+
+hipError_t fused_forward2_pass(int prec, void *psi, const gv_ansatz &an, const TilePlan &plan,
+                               int pass, int layer, int in_mode, const Chunks &ch,
+                               const FusedTables &t, const LDiagTab &ld, hipStream_t s)
+{
+    if (in_mode != IN_LOAD && pass != 0) return hipErrorInvalidValue;
+    if (layer + 1 >= an.layers + an.final_rotation) return hipErrorInvalidValue;
+    FusedArgs a = base_args(an, plan, pass, layer, t);
+    a.layer2 = layer + 1;
+    a.ld = ld;
+    a.in_mode = in_mode;
+    if (in_mode == IN_LOAD_DIAG) a.dt = layer_tab(an, ch, t, layer - 1);
+    if (in_mode == IN_GENERATE) a.dt = make_diagtab(an, ch, t.gtab, 0 < an.layers);
+    const int grid = fused_grid(prec, plan, an.n);
+    GV_LAUNCH_K(k_fwd2_pass, prec, grid, plan.K, psi, a);
     return hipGetLastError();
 }
 

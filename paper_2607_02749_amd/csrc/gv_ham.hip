@@ -84,6 +84,69 @@ __global__ __launch_bounds__(kBlock) void k_wht_pass(double *d, WhtPass w)
     }
 }
 
+// The same pass for 12-bit tiles whose tile bits 4..7 and 8..11 sit at
+// consecutive index positions: 256 threads hold 16 values each, and the
+// butterflies of a tile bit run in registers while it is one of the
+// thread's four register bits.  The register bits go 8..11 (load), 0..3,
+// 4..7 (store), switched through LDS (padded one slot per 16 against bank
+// conflicts).
+__device__ __forceinline__ int wht_slot(int t, int r, int l)
+{
+    const int u = (t & ((1 << l) - 1)) | (r << l) | ((t >> l) << (l + 4));
+    return u + (u >> 4);
+}
+
+__device__ __forceinline__ void wht_bfly(double (&v)[16], uint32_t m)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (!((m >> k) & 1)) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if (r & (1 << k)) continue;
+            const double a = v[r], b = v[r | (1 << k)];
+            v[r] = a + b;
+            v[r | (1 << k)] = a - b;
+        }
+    }
+}
+
+template <int LF, int LT>
+__device__ __forceinline__ void wht_exchange(double (&v)[16], double *lds, int t)
+{
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) lds[wht_slot(t, r, LF)] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = lds[wht_slot(t, r, LT)];
+}
+
+__global__ __launch_bounds__(256) void k_wht_reg(double *d, WhtPass w)
+{
+    __shared__ double lds[4096 + 256];
+    const int t = threadIdx.x;
+    u64 toff0 = 0, toff2 = 0;
+    for (int j = 0, tb = 0; j < 12; ++j)
+        if (j < 8) toff0 |= (u64)((t >> tb++) & 1) << w.pos[j];
+    for (int j = 0, tb = 0; j < 12; ++j)
+        if (j < 4 || j >= 8) toff2 |= (u64)((t >> tb++) & 1) << w.pos[j];
+    const int sh0 = w.pos[8], sh2 = w.pos[4];
+    for (u64 tile = blockIdx.x; tile < w.ntiles; tile += gridDim.x) {
+        const u64 base = deposit(tile, w.outside);
+        double v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = d[base | toff0 | ((u64)r << sh0)];
+        wht_bfly(v, w.active >> 8);
+        wht_exchange<8, 0>(v, lds, t);
+        wht_bfly(v, w.active & 0xf);
+        wht_exchange<0, 4>(v, lds, t);
+        wht_bfly(v, (w.active >> 4) & 0xf);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) d[base | toff2 | ((u64)r << sh2)] = v[r];
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_energy_diag(const cx<R> *psi, const double *diag,
                                                          cx<R> *lam, u64 dim, double *epart,
@@ -218,8 +281,16 @@ hipError_t fwht_inplace(double *d, int n, hipStream_t s)
         w.active = plan.pass[p].active;
         w.outside = ((n >= 64) ? ~0ull : ((1ull << n) - 1)) & ~inside;
         w.ntiles = 1ull << (n - K);
-        const int grid = (int)(w.ntiles < 8192 ? w.ntiles : 8192);
-        hipLaunchKernelGGL(k_wht_pass, dim3(grid), dim3(kBlock), 0, s, d, w);
+        bool reg = K == 12;
+        for (int k = 1; k < 4; ++k)
+            reg = reg && w.pos[4 + k] == w.pos[4] + k && w.pos[8 + k] == w.pos[8] + k;
+        if (reg) {
+            const int grid = (int)(w.ntiles < 2048 ? w.ntiles : 2048);
+            hipLaunchKernelGGL(k_wht_reg, dim3(grid), dim3(256), 0, s, d, w);
+        } else {
+            const int grid = (int)(w.ntiles < 8192 ? w.ntiles : 8192);
+            hipLaunchKernelGGL(k_wht_pass, dim3(grid), dim3(kBlock), 0, s, d, w);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

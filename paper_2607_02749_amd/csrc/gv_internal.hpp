@@ -144,6 +144,33 @@ struct DiagTab {
     int8_t pa[4], pb[4];
 };
 
+// Diagonal of one rotation layer (its RZ gates and CZ ladder) in the register
+// layout of one assignment of a tile pass: the entry of index i is
+// T[thread id] R[register] B1[tile id & (2^h1 - 1)] B2[tile id >> h1], times
+// -1 for every CZ pair whose two qubits sit in different groups and are
+// both set.  ka / kb give the register bit of such a pair's qubits (-1 when
+// the qubit is a thread or tile-id bit).
+constexpr int kMaxLPairs = 36;
+struct LDiagTab {
+    const void *tab;
+    int offR, offB1, offB2;
+    int h1;
+    int npair;
+    int8_t pa[kMaxLPairs], pb[kMaxLPairs];
+    int8_t ka[kMaxLPairs], kb[kMaxLPairs];
+};
+
+// What the table kernel needs to fill one LDiagTab: the qubit of every
+// index bit of the four groups, in order (thread bits, register bits, B1
+// bits, B2 bits).
+struct LDiagBuild {
+    int n, layer;
+    int nt, nr, h1, h2;
+    int8_t q[40];
+    int cz;                 // 0 none, 1 linear, 2 circular
+    int offR, offB1, offB2, total;
+};
+
 // What the table kernels need to fill one ansatz's tables.
 struct TabArgs {
     int n;
@@ -177,6 +204,8 @@ struct WorkLayout {
     size_t total = 0;
     int grid = 0;            // columns of the partial arrays
     size_t dtab_stride = 0;  // bytes per layer of diagonal tables (fwd + bwd)
+    size_t ldtab = 0;        // per rotation layer: layout diagonal of a two-layer pass
+    size_t ldtab_stride = 0;
 };
 gv_status work_layout(const gv_ansatz &a, gv_precision prec, gv_engine eng, gv_grad_mode mode,
                       WorkLayout *out);
@@ -229,11 +258,13 @@ hipError_t offdiag_pass(int prec, const void *psi, void *lam, int n, int K, cons
 
 // fused engine
 struct FusedTables {
-    const double *ry;    // [P][2]: cos, sin of half angles
+    const void *ry;      // [P]: (cos, sin) of half angles in the amplitude precision
     void *dtab;          // per rotation layer diagonal tables (RZ phases, CZ signs)
     size_t dtab_stride;
     void *gtab;          // D_0 R_0|0...0> tables
     void *g0tab;         // R_0|0...0> tables
+    void *ldtab;         // per rotation layer: its diagonal in a two-layer pass's layout
+    size_t ldtab_stride;
 };
 struct BwdFlags {
     int phi_generate = 0;   // phi = R_0|0...0> from tables instead of a load (pass 0)
@@ -250,15 +281,29 @@ hipError_t fused_init_state(int prec, void *psi, const gv_ansatz &a, const Chunk
 hipError_t fused_forward_pass(int prec, void *psi, const gv_ansatz &a, const TilePlan &plan,
                               int pass, int layer, int in_mode, const Chunks &ch,
                               const FusedTables &t, hipStream_t s);
+// ld_load (may be NULL): both vectors first lose `layer`'s diagonal in the
+// pass's load layout (the second half of a two-layer pass's reverse)
 hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *lam,
                                const gv_ansatz &a, const TilePlan &plan, int pass, int layer,
                                const BwdFlags &fl, const Chunks &ch, const FusedTables &t,
-                               double *part, int grid, hipStream_t s);
+                               double *part, int grid, hipStream_t s,
+                               const LDiagTab *ld_load = nullptr);
 // Gradients of rotation layer 0 from lam alone (one read), lam before
 // (diag_lam = 0) or after (1) the layer's diagonal; qubits of layer 0 only.
 hipError_t fused_layer0_grad(int prec, const void *lam, const gv_ansatz &an, const TilePlan &plan,
                              int diag_lam, const Chunks &ch, const FusedTables &t, double *part,
                              int grid, hipStream_t s);
+// Two-layer passes (the last pass of `layer` and the first of layer + 1 on
+// the same tile qubits).  make_ldiag fills `tab` (device, ldiag_entries
+// entries of the precision's complex type) for layer's diagonal in the last
+// (last = 1) or the load (last = 0) assignment of plan pass `pass`; the
+// table kernel runs on `s`.
+int ldiag_entries(int n, int K, int LOGR);
+hipError_t make_ldiag(int prec, const gv_ansatz &an, const TilePlan &plan, int pass, int last,
+                      int layer, const double *theta, void *tab, LDiagTab *out, hipStream_t s);
+hipError_t fused_forward2_pass(int prec, void *psi, const gv_ansatz &an, const TilePlan &plan,
+                               int pass, int layer, int in_mode, const Chunks &ch,
+                               const FusedTables &t, const LDiagTab &ld, hipStream_t s);
 hipError_t fused_turnaround(int prec, const void *psi, void *lam, const double *hdiag,
                             const gv_ansatz &a, const TilePlan &plan, int pass, int layer,
                             int in_mode, const Chunks &ch, const FusedTables &t, double *part,
@@ -296,7 +341,7 @@ struct BatchInst {
     const OffTerm *terms;
     const BatchOffPass *offp;
     void *psi, *lam;
-    double *ry;
+    void *ry;            // [P] (cos, sin) of half angles, amplitude precision
     char *dtab;
     size_t dtab_stride;
     void *gtab, *g0tab;

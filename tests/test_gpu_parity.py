@@ -229,3 +229,24 @@ def test_random_pauli_strings(precision):
                           theta=th)
     e, g, _, _ = run_gpu(inst, precision)
     check(e, g, *oracle_eg(inst), precision, "random strings")
+
+
+@pytest.mark.parametrize("n,layers,ent,zonly", [
+    (9, 6, synth.ENT_CZ_LINEAR, True),
+    (12, 5, synth.ENT_CZ_CIRCULAR, True),
+    (12, 6, synth.ENT_CZ_LINEAR, False),
+    (14, 7, synth.ENT_CZ_LINEAR, True),
+    (17, 6, synth.ENT_CZ_CIRCULAR, False),
+    (20, 6, synth.ENT_NONE, True),
+    (22, 5, synth.ENT_CZ_LINEAR, True),
+])
+@pytest.mark.parametrize("mode", ["uncompute", "checkpoint", "recompute"])
+def test_snake_order_many_layers(n, layers, ent, zonly, mode):
+    # deep circuits: every layer boundary becomes a two-layer tile pass
+    inst = synth.make_instance(n, layers, 10 * n, 4, 3, seed=900 + n + layers, ent=ent,
+                               m_off=0 if zonly else n, off_types=("XX", "YY", "XZ"),
+                               final_rotation=int(n % 2 == 0))
+    e_ref, g_ref = oracle_eg(inst)
+    for precision in ("c128", "c64"):
+        e, g, _, _ = run_gpu(inst, precision, mode=mode)
+        check(e, g, e_ref, g_ref, precision, f"snake n={n} L={layers} ent={ent} {mode}")
