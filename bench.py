@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--mode", default="uncompute", choices=["uncompute", "checkpoint", "recompute"])
+    ap.add_argument("--mode", default="store", choices=["uncompute", "checkpoint", "recompute", "store"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a 2 GiB device-to-device copy (the practical HBM ceiling, and "
                          "the reference kernel for scaling byte counters)")

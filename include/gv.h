@@ -76,7 +76,12 @@ typedef enum {
 typedef enum {
     GV_GRAD_UNCOMPUTE = 0,    /* undo gates on the final state; no extra memory */
     GV_GRAD_CHECKPOINT = 1,   /* store the state at the layers-1 inner layer boundaries */
-    GV_GRAD_RECOMPUTE = 2     /* re-run the forward from |0> to each layer boundary */
+    GV_GRAD_RECOMPUTE = 2,    /* re-run the forward from |0> to each layer boundary */
+    GV_GRAD_STORE = 3         /* keep the state after every fused tile pass (each pass
+                                 writes its own buffer); the reverse sweep reads them back
+                                 and writes only lambda.  Most memory, least traffic.
+                                 Ansatze with a CNOT ladder store the layer boundaries
+                                 only, as CHECKPOINT does. */
 } gv_grad_mode;
 
 /* Kernel family.  FUSED: tile passes that apply many gates per HBM sweep.

@@ -133,6 +133,60 @@ static int choose_logr(int K) { return K == 8 ? 3 : 4; }
 static int choose_C(gv_precision p, int K) { return std::min(K - 1, p == GV_C64 ? 4 : 3); }
 static bool fused_ok(gv_engine e, int n) { return e == GV_ENGINE_FUSED && n >= 8; }
 
+// One tile pass of the forward sweep in snake order: group g (a pass of the
+// tile plan) for rotation layer la, and, when lb >= 0, also for layer
+// lb = la + 1 (a two-layer pass).  slot >= 0: the state after the pass is a
+// checkpoint slot.
+struct FwdOp {
+    int g, la, lb, in_mode, slot;
+};
+
+// Snake order for diagonal entanglers: layer l runs the plan's passes
+// forward when l is odd and backward when l is even, so the last pass of a
+// layer and the first of the next act on the same tile qubits and fuse into
+// one two-layer pass (the layer diagonal between them is applied in
+// registers).  Layer 0 (the product state) is generated inside layer 1's
+// first pass.  keep_last_single keeps the last layer's pass out of a
+// two-layer pass (the turnaround takes it).  Checkpoint slots go to the
+// states after two-layer passes (every pass when the plan has one pass).
+static std::vector<FwdOp> snake_ops(int np, int upto, bool keep_last_single, bool ckpt)
+{
+    std::vector<FwdOp> ops;
+    for (int l = 1; l <= upto; ++l)
+        for (int i = 0; i < np; ++i) {
+            const int g = (l & 1) ? i : np - 1 - i;
+            if (i == 0 && l >= 2) {
+                FwdOp &pv = ops.back();
+                const bool hold = keep_last_single && l == upto && np == 1;
+                if (pv.lb < 0 && pv.g == g && !hold) {
+                    pv.lb = l;
+                    continue;
+                }
+                ops.push_back({g, l, -1, FWD_LOAD_DIAG, -1});  // np == 1: g == 0
+                continue;
+            }
+            ops.push_back({g, l, -1, (l == 1 && i == 0) ? FWD_GENERATE : FWD_LOAD, -1});
+        }
+    if (ckpt) {
+        int slot = 0;
+        const int last = (int)ops.size() - (keep_last_single ? 2 : 1);
+        for (int k = 0; k < last; ++k)
+            if (ops[k].lb >= 0 || np == 1) ops[k].slot = slot++;
+    }
+    return ops;
+}
+
+// buffers the STORE mode needs: one per pass output except the last
+static int store_slots(const gv_ansatz &a, int np)
+{
+    const bool cnot = a.ent == GV_ENT_CNOT_LINEAR || a.ent == GV_ENT_CNOT_CIRCULAR;
+    const int R = rot_layers(a);
+    if (cnot || R < 2) return std::max(0, R - 2);
+    const size_t m = std::max(snake_ops(np, R - 1, false, false).size(),
+                              snake_ops(np, R - 1, true, false).size());
+    return (int)m - 1;
+}
+
 gv_status work_layout(const gv_ansatz &a, gv_precision prec, gv_engine eng, gv_grad_mode mode,
                       WorkLayout *out)
 {
@@ -176,8 +230,14 @@ gv_status work_layout(const gv_ansatz &a, gv_precision prec, gv_engine eng, gv_g
         off += align_up(A * s);
     }
     if (mode == GV_GRAD_CHECKPOINT && fused_ok(eng, a.n) && R > 2) {
-        w.ckpt = off;  // states after the RY gates of layers 1 .. R-2
+        w.ckpt = off;  // states at the inner layer boundaries
         off += align_up(A * s) * (size_t)(R - 2);
+    }
+    if (mode == GV_GRAD_STORE && fused_ok(eng, a.n)) {
+        TilePlan plan;
+        make_tile_plan(a.n, choose_K(a.n), choose_C(prec, choose_K(a.n)), &plan);
+        w.ckpt = off;  // the output of every pass but the last
+        off += align_up(A * s) * (size_t)store_slots(a, plan.npass);
     }
     w.total = off;
     *out = w;
@@ -250,14 +310,6 @@ static gv_status plain_forward(gv_state st, const gv_ansatz &an, const double *t
     }
     return GV_OK;
 }
-
-// One tile pass of the forward sweep in snake order: group g (a pass of the
-// tile plan) for rotation layer la, and, when lb >= 0, also for layer
-// lb = la + 1 (a two-layer pass).  slot >= 0: the state after the pass is a
-// checkpoint slot.
-struct FwdOp {
-    int g, la, lb, in_mode, slot;
-};
 
 struct FusedCtx {
     TilePlan plan;
@@ -370,41 +422,6 @@ static gv_status last_layer_transform(gv_state st, const gv_ansatz &an, const Fu
                      "diagonal");
 }
 
-// Snake order for diagonal entanglers: layer l runs the plan's passes
-// forward when l is odd and backward when l is even, so the last pass of a
-// layer and the first of the next act on the same tile qubits and fuse into
-// one two-layer pass (the layer diagonal between them is applied in
-// registers).  Layer 0 (the product state) is generated inside layer 1's
-// first pass.  keep_last_single keeps the last layer's pass out of a
-// two-layer pass (the turnaround takes it).  Checkpoint slots go to the
-// states after two-layer passes (every pass when the plan has one pass).
-static std::vector<FwdOp> snake_ops(int np, int upto, bool keep_last_single, bool ckpt)
-{
-    std::vector<FwdOp> ops;
-    for (int l = 1; l <= upto; ++l)
-        for (int i = 0; i < np; ++i) {
-            const int g = (l & 1) ? i : np - 1 - i;
-            if (i == 0 && l >= 2) {
-                FwdOp &pv = ops.back();
-                const bool hold = keep_last_single && l == upto && np == 1;
-                if (pv.lb < 0 && pv.g == g && !hold) {
-                    pv.lb = l;
-                    continue;
-                }
-                ops.push_back({g, l, -1, FWD_LOAD_DIAG, -1});  // np == 1: g == 0
-                continue;
-            }
-            ops.push_back({g, l, -1, (l == 1 && i == 0) ? FWD_GENERATE : FWD_LOAD, -1});
-        }
-    if (ckpt) {
-        int slot = 0;
-        const int last = (int)ops.size() - (keep_last_single ? 2 : 1);
-        for (int k = 0; k < last; ++k)
-            if (ops[k].lb >= 0 || np == 1) ops[k].slot = slot++;
-    }
-    return ops;
-}
-
 static bool use_snake(const gv_ansatz &an) { return !is_cnot(an) && rot_layers(an) >= 2; }
 
 // op list and the two-layer passes' diagonal tables
@@ -430,21 +447,32 @@ static gv_status snake_setup(gv_state st, const gv_ansatz &an, const double *the
     return GV_OK;
 }
 
-// the first `count` passes of the snake order, from |0...0>
+// Where the STORE mode keeps the output of pass k: its own buffer, except
+// the last pass, which writes the state buffer.
+static void *store_out(const FusedCtx &c, int k, void *psi, char *bufs, size_t vb)
+{
+    return k == (int)c.ops.size() - 1 ? psi : bufs + (size_t)k * vb;
+}
+
+// The first `count` passes of the snake order, from |0...0>: in place on
+// psi (copying checkpoint slots out of it when ckpt is set), or with
+// store = true from each pass's buffer to the next.
 static gv_status snake_forward(gv_state st, const gv_ansatz &an, const FusedCtx &c, size_t count,
-                               void *psi, char *ckpt, size_t vb)
+                               void *psi, char *ckpt, size_t vb, bool store = false)
 {
     hipStream_t s = st->stream;
     for (size_t k = 0; k < count; ++k) {
         const FwdOp &op = c.ops[k];
+        void *dst = store ? store_out(c, (int)k, psi, ckpt, vb) : psi;
+        const void *src = (store && k > 0) ? store_out(c, (int)k - 1, psi, ckpt, vb) : dst;
         ProfScope ps(st, GV_PROF_FORWARD_PASS, op.in_mode == FWD_GENERATE ? (double)vb : 2.0 * vb);
         hipError_t e = op.lb >= 0
-                           ? fused_forward2_pass(st->prec, psi, an, c.plan, op.g, op.la, op.in_mode,
-                                                 c.ch, c.tabs, c.ld[op.la], s)
-                           : fused_forward_pass(st->prec, psi, an, c.plan, op.g, op.la, op.in_mode,
-                                                c.ch, c.tabs, s);
+                           ? fused_forward2_pass(st->prec, dst, an, c.plan, op.g, op.la, op.in_mode,
+                                                 c.ch, c.tabs, c.ld[op.la], s, src)
+                           : fused_forward_pass(st->prec, dst, an, c.plan, op.g, op.la, op.in_mode,
+                                                c.ch, c.tabs, s, src);
         if (gv_status r = check_hip(e, "forward pass")) return r;
-        if (ckpt && op.slot >= 0) {
+        if (!store && ckpt && op.slot >= 0) {
             ProfScope pc(st, GV_PROF_OTHER, 2.0 * vb);
             if (gv_status r = check_hip(copy_vector(ckpt + (size_t)op.slot * vb, psi, vb, s),
                                         "checkpoint"))
@@ -520,7 +548,7 @@ gv_status gv_query_sizes(const gv_ansatz *a, gv_precision prec, gv_engine engine
     if (gv_status r = check_ansatz(a)) return r;
     if (prec != GV_C64 && prec != GV_C128) return set_error(GV_EINVAL, "precision");
     if (engine != GV_ENGINE_FUSED && engine != GV_ENGINE_PLAIN) return set_error(GV_EINVAL, "engine");
-    if (mode < GV_GRAD_UNCOMPUTE || mode > GV_GRAD_RECOMPUTE) return set_error(GV_EINVAL, "mode");
+    if (mode < GV_GRAD_UNCOMPUTE || mode > GV_GRAD_STORE) return set_error(GV_EINVAL, "mode");
     WorkLayout w;
     if (gv_status r = work_layout(*a, prec, engine, mode, &w)) return r;
     if (state_bytes) *state_bytes = ((size_t)1 << a->n) * amp_bytes(prec);
@@ -867,7 +895,7 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
     if (a->n != st->n) return set_error(GV_ESTATE, "ansatz n=%d but state n=%d", a->n, st->n);
     if (!h->prepared) return set_error(GV_ESTATE, "pauli sum not prepared");
     if (h->n != st->n) return set_error(GV_ESTATE, "pauli sum n=%d but state n=%d", h->n, st->n);
-    if (mode < GV_GRAD_UNCOMPUTE || mode > GV_GRAD_RECOMPUTE) return set_error(GV_EINVAL, "mode");
+    if (mode < GV_GRAD_UNCOMPUTE || mode > GV_GRAD_STORE) return set_error(GV_EINVAL, "mode");
     const int64_t P = nparams(*a);
     const int n = a->n;
     const size_t vb = ((size_t)1 << n) * amp_bytes(st->prec);
@@ -928,7 +956,9 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
     if (gv_status r = fused_setup(st, *a, theta, mode, &c)) return r;
     void *psi = st->amps;
     void *lam = w + c.w.lam;
-    char *ckpt = (mode == GV_GRAD_CHECKPOINT && R > 2) ? w + c.w.ckpt : nullptr;
+    // the layer-by-layer path keeps layer boundaries for STORE as CHECKPOINT does
+    const gv_grad_mode lmode = mode == GV_GRAD_STORE ? GV_GRAD_CHECKPOINT : mode;
+    char *ckpt = (lmode == GV_GRAD_CHECKPOINT && R > 2) ? w + c.w.ckpt : nullptr;
     double *part = (double *)(w + c.w.part);
     double *epart = (double *)(w + c.w.epart);
     const bool cnot = is_cnot(*a);
@@ -939,18 +969,22 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
     const bool turn = zonly && !cnot && R >= 2;
 
     if (use_snake(*a)) {
+        const bool store = mode == GV_GRAD_STORE;
         if (gv_status r = snake_setup(st, *a, theta, turn, mode == GV_GRAD_CHECKPOINT, &c)) return r;
         const std::vector<FwdOp> &ops = c.ops;
         const int nops = (int)ops.size();
         for (const FwdOp &op : ops)
             if (op.slot >= R - 2) return set_error(GV_EUNSUPPORTED, "checkpoint slot %d", op.slot);
-        char *ck = mode == GV_GRAD_CHECKPOINT ? w + c.w.ckpt : nullptr;
+        if (store && nops - 1 > store_slots(*a, np))
+            return set_error(GV_EUNSUPPORTED, "%d passes need more buffers than reserved", nops);
+        char *ck = (mode == GV_GRAD_CHECKPOINT || store) ? w + c.w.ckpt : nullptr;
         int kstart;
         if (turn) {
-            if (gv_status r = snake_forward(st, *a, c, nops - 1, psi, ck, vb)) return r;
+            if (gv_status r = snake_forward(st, *a, c, nops - 1, psi, ck, vb, store)) return r;
             const FwdOp &op = ops[nops - 1];
+            const void *tin = (store && nops >= 2) ? store_out(c, nops - 2, psi, ck, vb) : psi;
             ProfScope ps(st, GV_PROF_ENERGY, 2.0 * vb + 8.0 * (double)((size_t)1 << n));
-            if (gv_status r = check_hip(fused_turnaround(st->prec, psi, lam, h->diag, *a, c.plan,
+            if (gv_status r = check_hip(fused_turnaround(st->prec, tin, lam, h->diag, *a, c.plan,
                                                          op.g, op.la, op.in_mode, c.ch, c.tabs,
                                                          part, epart, c.w.grid, s),
                                         "turnaround"))
@@ -961,7 +995,7 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
         } else {
             // psi~ -> psi (the last layer's diagonal), E and lam = H psi, then
             // both vectors back to the point before that diagonal
-            if (gv_status r = snake_forward(st, *a, c, nops, psi, ck, vb)) return r;
+            if (gv_status r = snake_forward(st, *a, c, nops, psi, ck, vb, store)) return r;
             if (gv_status r = last_layer_transform(st, *a, c, psi, nullptr, 0)) return r;
             if (gv_status r = energy_chain(st, h, lam, epart, energy)) return r;
             if (gv_status r = last_layer_transform(st, *a, c, psi, lam, 1)) return r;
@@ -972,9 +1006,9 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
             // phi comes from the previous reverse pass (uncompute), from the
             // turnaround's untouched input, from a checkpoint or recomputed;
             // the last three have not been through the next pass's load diagonal
-            const void *phi_src = psi;
-            bool fresh = turn && k == kstart;
-            if (k != kstart && op.slot >= 0) {
+            const void *phi_src = store ? store_out(c, k, psi, ck, vb) : psi;
+            bool fresh = store || (turn && k == kstart);
+            if (!store && k != kstart && op.slot >= 0) {
                 if (mode == GV_GRAD_CHECKPOINT) {
                     phi_src = ck + (size_t)op.slot * vb;
                     fresh = true;
@@ -984,17 +1018,20 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
                 }
             }
             const bool next_diag = k + 1 < nops && ops[k + 1].in_mode == FWD_LOAD_DIAG;
-            const bool prev_fresh = k >= 1 && ops[k - 1].slot >= 0 && mode != GV_GRAD_UNCOMPUTE;
+            const bool prev_fresh =
+                store || (k >= 1 && ops[k - 1].slot >= 0 && mode != GV_GRAD_UNCOMPUTE);
             BwdFlags fl;
             fl.diag_lam = next_diag;
             fl.diag_phi = next_diag && !fresh;
             fl.store_phi = k >= 1 && !prev_fresh;
             fl.store_lam = 1;
+            fl.grad_first = !fl.store_phi && !fl.diag_phi;
             // a two-layer pass is undone by two reverse passes: layer lb's RY
             // gates, then layer la's diagonal (on load) and RY gates
             if (op.lb >= 0) {
                 BwdFlags fa = fl;
                 fa.store_phi = 1;
+                fa.grad_first = 0;
                 ProfScope ps(st, GV_PROF_BACKWARD_PASS, 4.0 * vb);
                 if (gv_status r = check_hip(
                         fused_backward_pass(st->prec, phi_src, psi, lam, *a, c.plan, op.g, op.lb,
@@ -1056,10 +1093,10 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
         const bool phi_gen = l == 0;
         const void *phi_src = psi;
         if (!phi_gen && l <= R - 2 && npl > 0) {
-            if (mode == GV_GRAD_CHECKPOINT) {
+            if (lmode == GV_GRAD_CHECKPOINT) {
                 phi_src = ckpt + (size_t)(l - 1) * vb;
                 phi_post = false;
-            } else if (mode == GV_GRAD_RECOMPUTE) {
+            } else if (lmode == GV_GRAD_RECOMPUTE) {
                 if (gv_status r = fused_forward(st, *a, c, l, false, psi, nullptr, vb)) return r;
                 phi_post = false;
             }
@@ -1081,7 +1118,7 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
             break;
         }
         // does layer l-1 read phi from the state buffer?
-        const bool next_phi_needed = l - 1 >= 1 && mode == GV_GRAD_UNCOMPUTE;
+        const bool next_phi_needed = l - 1 >= 1 && lmode == GV_GRAD_UNCOMPUTE;
         for (int p = 0; p < npl; ++p) {
             const bool last = p == npl - 1;
             BwdFlags fl;

@@ -337,6 +337,49 @@ __device__ __forceinline__ void bwd_assign(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 <
     }
 }
 
+// RY partials of the tile bits new in assignment AI from (phi, lam) taken
+// at the same point, without rotating: Im<lam|Y_q|phi> over the pairs
+template <typename R, int K, int LOGR, int AI>
+__device__ __forceinline__ void ygrad_assign(const cx<R> (&f)[1 << LOGR], const cx<R> (&l)[1 << LOGR],
+                                             double (&accY)[K], const FusedArgs &a)
+{
+    using T = Tile<K, LOGR>;
+    constexpr int LO = T::lo(AI);
+    constexpr uint32_t NEW = T::newbits(AI);
+#pragma unroll
+    for (int k = 0; k < LOGR; ++k) {
+        const int j = LO + k;
+        if (!((NEW >> j) & 1) || !((a.active >> j) & 1)) continue;
+        R g = 0;
+#pragma unroll
+        for (int r = 0; r < T::NR; ++r) {
+            if (r & (1 << k)) continue;
+            const int r1 = r | (1 << k);
+            g += (l[r1].re * f[r].re + l[r1].im * f[r].im) - (l[r].re * f[r1].re + l[r].im * f[r1].im);
+        }
+        accY[j] += (double)g;
+    }
+}
+
+// RY(-theta) of the tile bits new in assignment AI on one vector
+template <typename R, int K, int LOGR, int AI>
+__device__ __forceinline__ void inv_assign(cx<R> (&v)[1 << LOGR], const FusedArgs &a, int layer)
+{
+    using T = Tile<K, LOGR>;
+    constexpr int LO = T::lo(AI);
+    constexpr uint32_t NEW = T::newbits(AI);
+#pragma unroll
+    for (int k = 0; k < LOGR; ++k) {
+        const int j = LO + k;
+        if (!((NEW >> j) & 1) || !((a.active >> j) & 1)) continue;
+        const cx<R> e = ((const cx<R> *)a.ry)[(int64_t)layer * a.nparam_layer + a.pos[j]];
+        const R c = e.re, sn = -e.im;
+#pragma unroll
+        for (int r = 0; r < T::NR; ++r)
+            if (!(r & (1 << k))) rot_pair(v[r], v[r | (1 << k)], c, sn);
+    }
+}
+
 template <typename R, int K, int LOGR, int LFROM, int LTO>
 __device__ __forceinline__ void exchange(cx<R> (&v)[1 << LOGR], cx<R> *lds, int t)
 {
@@ -416,6 +459,35 @@ struct BwdChainRev {
     }
 };
 
+// partials of assignments AI .. NA-1, each after an exchange of both vectors
+template <typename R, int K, int LOGR, int AI>
+struct GradChain {
+    __device__ static __forceinline__ void run(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
+                                               double (&accY)[K], cx<R> *lds, int t,
+                                               const FusedArgs &a)
+    {
+        using T = Tile<K, LOGR>;
+        exchange<R, K, LOGR, T::lo(AI - 1), T::lo(AI)>(f, lds, t);
+        exchange<R, K, LOGR, T::lo(AI - 1), T::lo(AI)>(l, lds, t);
+        ygrad_assign<R, K, LOGR, AI>(f, l, accY, a);
+        if constexpr (AI + 1 < T::NA) GradChain<R, K, LOGR, AI + 1>::run(f, l, accY, lds, t, a);
+    }
+};
+
+// RY(-theta) of assignments AI, AI-1, .., 0 on one vector, each after an
+// exchange from AI+1
+template <typename R, int K, int LOGR, int AI>
+struct InvChainRev {
+    __device__ static __forceinline__ void run(cx<R> (&v)[1 << LOGR], cx<R> *lds, int t,
+                                               const FusedArgs &a, int layer)
+    {
+        using T = Tile<K, LOGR>;
+        exchange<R, K, LOGR, T::lo(AI + 1), T::lo(AI)>(v, lds, t);
+        inv_assign<R, K, LOGR, AI>(v, a, layer);
+        if constexpr (AI > 0) InvChainRev<R, K, LOGR, AI - 1>::run(v, lds, t, a, layer);
+    }
+};
+
 // Load a pass's tile in the load assignment.  In pass 0 the loaded values
 // may be multiplied by the layer diagonal (IN_LOAD_DIAG) or replaced by the
 // generated first-layer state (IN_GENERATE).
@@ -444,8 +516,8 @@ __device__ __forceinline__ void load_tile(cx<R> (&v)[1 << LOGR], const cx<R> *sr
 // a whole batch instance (t0 = 0, tstep = 1) can run them; col is the
 // partial-sum column the block writes.
 template <typename R, int K, int LOGR, bool CONTIG>
-__device__ __forceinline__ void fwd_body(cx<R> *psi, const FusedArgs &a, u64 t0, u64 tstep,
-                                         cx<R> *lds)
+__device__ __forceinline__ void fwd_body(cx<R> *psi, const cx<R> *src, const FusedArgs &a,
+                                         u64 t0, u64 tstep, cx<R> *lds)
 {
     using T = Tile<K, LOGR>;
     const int t = threadIdx.x;
@@ -459,7 +531,7 @@ __device__ __forceinline__ void fwd_body(cx<R> *psi, const FusedArgs &a, u64 t0,
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> v[T::NR];
-        load_tile<R, K, LOGR, CONTIG>(v, psi, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
+        load_tile<R, K, LOGR, CONTIG>(v, src, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
         fwd_assign<R, K, LOGR, 0>(v, a, a.layer);
         if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(v, lds, t, a, a.layer);
 #pragma unroll
@@ -468,10 +540,11 @@ __device__ __forceinline__ void fwd_body(cx<R> *psi, const FusedArgs &a, u64 t0,
 }
 
 template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_pass(void *psi_, FusedArgs a)
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_pass(void *psi_, const void *src_,
+                                                              FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
-    fwd_body<R, K, LOGR, CONTIG>((cx<R> *)psi_, a, blockIdx.x, gridDim.x, lds);
+    fwd_body<R, K, LOGR, CONTIG>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x, gridDim.x, lds);
 }
 
 // Block sums of the gradient partials of the pass's active tile qubits for
@@ -620,6 +693,84 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_ld_pass(const void *phi
                                        blockIdx.x, gridDim.x, blockIdx.x, lds, sh);
 }
 
+// Reverse pass that does not write phi back: every RY and RZ partial of the
+// pass is taken from (phi, lam) at the pass's end point (the pass's RY gates
+// act on distinct qubits, so Y_q and Z_q commute with all of them but RY_q,
+// which commutes with Y_q), visiting the assignments 0 .. NA-1 with both
+// vectors; then lam alone is rotated back through NA-1 .. 0 and stored in
+// the load layout.  phi dies after the partials.
+template <typename R, int K, int LOGR, bool CONTIG, bool LDG>
+__device__ __forceinline__ void bwd_gf_body(const cx<R> *phi_in, cx<R> *lam, const FusedArgs &a,
+                                            u64 t0, u64 tstep, int col, cx<R> *lds, double *sh)
+{
+    using T = Tile<K, LOGR>;
+    const int t = threadIdx.x;
+    constexpr int LD = T::lo(0);
+    const u64 toff_ld = thread_off<K, LOGR>(t, LD, a);
+    RegMap<LOGR, CONTIG> mld;
+    mld.init(a.pos + LD);
+    P0Diag<R, K, LOGR> pd;
+    if (a.diag_lam) pd.init(a.dt, t);
+    LDiag<R, K, LOGR> dg;
+    double accY[K], accZr[LOGR], ztot = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) accY[j] = 0.0;
+#pragma unroll
+    for (int k = 0; k < LOGR; ++k) accZr[k] = 0.0;
+
+    for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
+        const u64 base = tile_base(tile, a);
+        cx<R> f[T::NR], l[T::NR];
+#pragma unroll
+        for (int r = 0; r < T::NR; ++r) {
+            f[r] = phi_in[base | toff_ld | mld.off(r)];
+            l[r] = lam[base | toff_ld | mld.off(r)];
+        }
+        if (a.diag_lam) {
+            pd.tile(a.dt, base, t);
+#pragma unroll
+            for (int r = 0; r < T::NR; ++r) l[r] = cmul_conj(l[r], pd.at(a.dt, r));
+        }
+        if constexpr (LDG) {
+            dg.tile(a.ld, tile, base | toff_ld, t);
+#pragma unroll
+            for (int r = 0; r < T::NR; ++r) {
+                const cx<R> d = dg.at(a.ld, r);
+                f[r] = cmul_conj(f[r], d);
+                l[r] = cmul_conj(l[r], d);
+            }
+        }
+        z_partials<R, K, LOGR, 0>(f, l, accZr, ztot, a);
+        ygrad_assign<R, K, LOGR, 0>(f, l, accY, a);
+        if constexpr (T::NA > 1) GradChain<R, K, LOGR, 1>::run(f, l, accY, lds, t, a);
+        inv_assign<R, K, LOGR, T::NA - 1>(l, a, a.layer);
+        if constexpr (T::NA > 1) InvChainRev<R, K, LOGR, T::NA - 2>::run(l, lds, t, a, a.layer);
+#pragma unroll
+        for (int r = 0; r < T::NR; ++r) lam[base | toff_ld | mld.off(r)] = l[r];
+    }
+    write_partials<R, K, LOGR, 0, true>(accY, accZr, ztot, sh, a, a.layer, col);
+}
+
+template <typename R, int K, int LOGR, bool CONTIG>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_gf_pass(const void *phi_in_, void *lam_,
+                                                                 FusedArgs a)
+{
+    __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
+    __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
+    bwd_gf_body<R, K, LOGR, CONTIG, false>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, blockIdx.x,
+                                           gridDim.x, blockIdx.x, lds, sh);
+}
+
+template <typename R, int K, int LOGR, bool CONTIG>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_gf_ld_pass(const void *phi_in_,
+                                                                    void *lam_, FusedArgs a)
+{
+    __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
+    __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
+    bwd_gf_body<R, K, LOGR, CONTIG, true>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, blockIdx.x,
+                                          gridDim.x, blockIdx.x, lds, sh);
+}
+
 // Last forward pass of the last layer + energy + first reverse pass, for a
 // Z-only Hamiltonian with diagonal D: in each tile psi gets the pass's RY
 // gates, E += sum D_i |psi_i|^2, lam = D psi, then the reverse step of the
@@ -695,8 +846,8 @@ __global__ __launch_bounds__(1 << (K - LOGR)) __attribute__((amdgpu_waves_per_eu
 // the last assignment, then the second layer's RY gates back through
 // NA-1 .. 0, and the tile is stored in the load layout.
 template <typename R, int K, int LOGR, bool CONTIG>
-__device__ __forceinline__ void fwd2_body(cx<R> *psi, const FusedArgs &a, u64 t0, u64 tstep,
-                                          cx<R> *lds)
+__device__ __forceinline__ void fwd2_body(cx<R> *psi, const cx<R> *src, const FusedArgs &a,
+                                          u64 t0, u64 tstep, cx<R> *lds)
 {
     using T = Tile<K, LOGR>;
     const int t = threadIdx.x;
@@ -710,7 +861,7 @@ __device__ __forceinline__ void fwd2_body(cx<R> *psi, const FusedArgs &a, u64 t0
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> v[T::NR];
-        load_tile<R, K, LOGR, CONTIG>(v, psi, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
+        load_tile<R, K, LOGR, CONTIG>(v, src, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
         fwd_assign<R, K, LOGR, 0>(v, a, a.layer);
         if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(v, lds, t, a, a.layer);
         dg.tile(a.ld, tile, base | toff_st, t);
@@ -724,10 +875,12 @@ __device__ __forceinline__ void fwd2_body(cx<R> *psi, const FusedArgs &a, u64 t0
 }
 
 template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd2_pass(void *psi_, FusedArgs a)
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd2_pass(void *psi_, const void *src_,
+                                                               FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
-    fwd2_body<R, K, LOGR, CONTIG>((cx<R> *)psi_, a, blockIdx.x, gridDim.x, lds);
+    fwd2_body<R, K, LOGR, CONTIG>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x, gridDim.x,
+                                  lds);
 }
 
 // ------------------------------------------------ first-layer gradients
@@ -1405,7 +1558,7 @@ __device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh)
                 a.in_mode = l == 1 ? IN_GENERATE : IN_LOAD_DIAG;
                 a.dt = l == 1 ? I.gt : batch_layer_tab(I, l - 1);
             }
-            fwd_body<R, K, LOGR, true>(psi, a, 0, 1, lds);
+            fwd_body<R, K, LOGR, true>(psi, psi, a, 0, 1, lds);
             __syncthreads();
         }
     }
@@ -1621,15 +1774,16 @@ hipError_t fused_init_state(int prec, void *psi, const gv_ansatz &an, const Chun
 
 hipError_t fused_forward_pass(int prec, void *psi, const gv_ansatz &an, const TilePlan &plan,
                               int pass, int layer, int in_mode, const Chunks &ch,
-                              const FusedTables &t, hipStream_t s)
+                              const FusedTables &t, hipStream_t s, const void *src)
 {
+    if (!src) src = psi;
     if (in_mode != IN_LOAD && pass != 0) return hipErrorInvalidValue;
     FusedArgs a = base_args(an, plan, pass, layer, t);
     a.in_mode = in_mode;
     if (in_mode == IN_LOAD_DIAG) a.dt = layer_tab(an, ch, t, layer - 1);
     if (in_mode == IN_GENERATE) a.dt = make_diagtab(an, ch, t.gtab, 0 < an.layers);
     const int grid = fused_grid(prec, plan, an.n);
-    GV_LAUNCH_K(k_fwd_pass, prec, grid, plan.K, psi, a);
+    GV_LAUNCH_K(k_fwd_pass, prec, grid, plan.K, psi, src, a);
     return hipGetLastError();
 }
 
@@ -1640,6 +1794,8 @@ hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *la
 {
     if ((fl.phi_generate || fl.diag_phi || fl.diag_lam) && pass != 0) return hipErrorInvalidValue;
     if (ld_load && (fl.phi_generate || fl.diag_phi || fl.diag_lam)) return hipErrorInvalidValue;
+    if (fl.grad_first && (fl.store_phi || !fl.store_lam || fl.phi_generate || fl.diag_phi))
+        return hipErrorInvalidValue;
     FusedArgs a = base_args(an, plan, pass, layer, t);
     a.phi_gen = fl.phi_generate;
     if (fl.phi_generate) a.gt = make_diagtab(an, ch, t.g0tab, false);
@@ -1650,8 +1806,11 @@ hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *la
     a.store_lam = fl.store_lam;
     a.part = part;
     a.grid = grid;
-    if (ld_load) {
-        a.ld = *ld_load;
+    if (ld_load) a.ld = *ld_load;
+    if (fl.grad_first) {
+        if (ld_load) GV_LAUNCH_K(k_bwd_gf_ld_pass, prec, grid, plan.K, phi_in, lam, a);
+        else GV_LAUNCH_K(k_bwd_gf_pass, prec, grid, plan.K, phi_in, lam, a);
+    } else if (ld_load) {
         GV_LAUNCH_K(k_bwd_ld_pass, prec, grid, plan.K, phi_in, phi, lam, a);
     } else {
         GV_LAUNCH_K(k_bwd_pass, prec, grid, plan.K, phi_in, phi, lam, a);
@@ -1790,8 +1949,10 @@ hipError_t make_ldiag(int prec, const gv_ansatz &an, const TilePlan &plan, int p
 
 hipError_t fused_forward2_pass(int prec, void *psi, const gv_ansatz &an, const TilePlan &plan,
                                int pass, int layer, int in_mode, const Chunks &ch,
-                               const FusedTables &t, const LDiagTab &ld, hipStream_t s)
+                               const FusedTables &t, const LDiagTab &ld, hipStream_t s,
+                               const void *src)
 {
+    if (!src) src = psi;
     if (in_mode != IN_LOAD && pass != 0) return hipErrorInvalidValue;
     if (layer + 1 >= an.layers + an.final_rotation) return hipErrorInvalidValue;
     FusedArgs a = base_args(an, plan, pass, layer, t);
@@ -1801,7 +1962,7 @@ hipError_t fused_forward2_pass(int prec, void *psi, const gv_ansatz &an, const T
     if (in_mode == IN_LOAD_DIAG) a.dt = layer_tab(an, ch, t, layer - 1);
     if (in_mode == IN_GENERATE) a.dt = make_diagtab(an, ch, t.gtab, 0 < an.layers);
     const int grid = fused_grid(prec, plan, an.n);
-    GV_LAUNCH_K(k_fwd2_pass, prec, grid, plan.K, psi, a);
+    GV_LAUNCH_K(k_fwd2_pass, prec, grid, plan.K, psi, src, a);
     return hipGetLastError();
 }
 

@@ -271,6 +271,9 @@ struct BwdFlags {
     int diag_phi = 0;       // undo the layer's diagonal on phi as it loads (pass 0)
     int diag_lam = 0;       // undo the layer's diagonal on lam as it loads (pass 0)
     int store_phi = 1, store_lam = 1;
+    // phi is not written back (store_phi = 0): take every partial at the pass's
+    // end point and rotate lam alone
+    int grad_first = 0;
 };
 // forward pass input modes
 enum { FWD_LOAD = 0, FWD_LOAD_DIAG = 1, FWD_GENERATE = 2 };
@@ -278,9 +281,11 @@ hipError_t fused_build_tables(int prec, const gv_ansatz &a, const Chunks &ch, co
                               const FusedTables &t, hipStream_t s);
 hipError_t fused_init_state(int prec, void *psi, const gv_ansatz &a, const Chunks &ch,
                             const FusedTables &t, hipStream_t s);
+// src (NULL: psi) is where the pass reads its input; it writes psi
 hipError_t fused_forward_pass(int prec, void *psi, const gv_ansatz &a, const TilePlan &plan,
                               int pass, int layer, int in_mode, const Chunks &ch,
-                              const FusedTables &t, hipStream_t s);
+                              const FusedTables &t, hipStream_t s,
+                              const void *src = nullptr);
 // ld_load (may be NULL): both vectors first lose `layer`'s diagonal in the
 // pass's load layout (the second half of a two-layer pass's reverse)
 hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *lam,
@@ -303,7 +308,8 @@ hipError_t make_ldiag(int prec, const gv_ansatz &an, const TilePlan &plan, int p
                       int layer, const double *theta, void *tab, LDiagTab *out, hipStream_t s);
 hipError_t fused_forward2_pass(int prec, void *psi, const gv_ansatz &an, const TilePlan &plan,
                                int pass, int layer, int in_mode, const Chunks &ch,
-                               const FusedTables &t, const LDiagTab &ld, hipStream_t s);
+                               const FusedTables &t, const LDiagTab &ld, hipStream_t s,
+                               const void *src = nullptr);
 hipError_t fused_turnaround(int prec, const void *psi, void *lam, const double *hdiag,
                             const gv_ansatz &a, const TilePlan &plan, int pass, int layer,
                             int in_mode, const Chunks &ch, const FusedTables &t, double *part,

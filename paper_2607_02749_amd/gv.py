@@ -20,15 +20,15 @@ LIB_PATH = os.path.join(HERE, "libgv.so")
 
 C64, C128 = 0, 1
 ENGINE_FUSED, ENGINE_PLAIN = 0, 1
-GRAD_UNCOMPUTE, GRAD_CHECKPOINT, GRAD_RECOMPUTE = 0, 1, 2
+GRAD_UNCOMPUTE, GRAD_CHECKPOINT, GRAD_RECOMPUTE, GRAD_STORE = 0, 1, 2, 3
 ENT_NONE, ENT_CZ_LINEAR, ENT_CZ_CIRCULAR, ENT_CNOT_LINEAR, ENT_CNOT_CIRCULAR = 0, 1, 2, 3, 4
 
 _PREC = {"c64": C64, "complex64": C64, C64: C64, "c128": C128, "complex128": C128, C128: C128}
 _ENGINE = {"fused": ENGINE_FUSED, "plain": ENGINE_PLAIN, ENGINE_FUSED: ENGINE_FUSED,
            ENGINE_PLAIN: ENGINE_PLAIN}
 _MODE = {"uncompute": GRAD_UNCOMPUTE, "checkpoint": GRAD_CHECKPOINT, "recompute": GRAD_RECOMPUTE,
-         GRAD_UNCOMPUTE: GRAD_UNCOMPUTE, GRAD_CHECKPOINT: GRAD_CHECKPOINT,
-         GRAD_RECOMPUTE: GRAD_RECOMPUTE}
+         "store": GRAD_STORE, GRAD_UNCOMPUTE: GRAD_UNCOMPUTE, GRAD_CHECKPOINT: GRAD_CHECKPOINT,
+         GRAD_RECOMPUTE: GRAD_RECOMPUTE, GRAD_STORE: GRAD_STORE}
 
 ALIGN = 256
 

@@ -48,6 +48,15 @@ def test_query_sizes():
     assert wb >= 8 << 28                       # holds the adjoint vector
     _, wck = gv.query_sizes(gv.Ansatz(28, 6), "c64", "fused", "checkpoint")
     assert wck >= wb + 4 * (8 << 28)           # states after layers 1..4 (layer 0 is regenerated)
+    # store: one buffer per tile pass but the last; at n = 28 the snake order
+    # runs 3 passes for layer 1 and 2 for each of layers 2..5 (two-layer
+    # passes at every boundary), so 11 passes -> 10 buffers
+    _, wst = gv.query_sizes(gv.Ansatz(28, 6), "c64", "fused", "store")
+    assert wst - wb == 10 * (8 << 28)
+    # CNOT ladders keep the layer boundaries only
+    _, wcn = gv.query_sizes(gv.Ansatz(20, 5, ent=3), "c64", "fused", "store")
+    _, wcn_ck = gv.query_sizes(gv.Ansatz(20, 5, ent=3), "c64", "fused", "checkpoint")
+    assert wcn == wcn_ck
     sb128, _ = gv.query_sizes(gv.Ansatz(10, 2), "c128", "plain")
     assert sb128 == 16 << 10
     with pytest.raises(gv.GVError):

@@ -108,7 +108,7 @@ def test_restricted_mask(precision):
     check(e, g, e_ref, g_ref, precision, "restricted")
 
 
-@pytest.mark.parametrize("mode", ["checkpoint", "recompute"])
+@pytest.mark.parametrize("mode", ["checkpoint", "recompute", "store"])
 @pytest.mark.parametrize("ent", [synth.ENT_CZ_LINEAR, synth.ENT_CNOT_LINEAR])
 def test_gradient_modes(mode, ent):
     inst = synth.make_instance(14, 4, 150, 4, 3, seed=33, ent=ent)
@@ -204,7 +204,7 @@ def test_workload_n22_both_precisions():
 
 @pytest.mark.parametrize("n", [10, 12, 13, 16])
 @pytest.mark.parametrize("layers", [1, 2, 3])
-@pytest.mark.parametrize("mode", ["uncompute", "checkpoint", "recompute"])
+@pytest.mark.parametrize("mode", ["uncompute", "checkpoint", "recompute", "store"])
 def test_z_only_turnaround(n, layers, mode):
     # Z-only Hamiltonians take the fused last-pass / energy / first-reverse-pass path
     inst = synth.make_instance(n, layers, 15 * n, 5, 3, seed=500 + 7 * n + layers,
@@ -240,7 +240,7 @@ def test_random_pauli_strings(precision):
     (20, 6, synth.ENT_NONE, True),
     (22, 5, synth.ENT_CZ_LINEAR, True),
 ])
-@pytest.mark.parametrize("mode", ["uncompute", "checkpoint", "recompute"])
+@pytest.mark.parametrize("mode", ["uncompute", "checkpoint", "recompute", "store"])
 def test_snake_order_many_layers(n, layers, ent, zonly, mode):
     # deep circuits: every layer boundary becomes a two-layer tile pass
     inst = synth.make_instance(n, layers, 10 * n, 4, 3, seed=900 + n + layers, ent=ent,
