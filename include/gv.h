@@ -236,15 +236,20 @@ gv_status gv_batch_energy_grad(int32_t count, const gv_instance *inst, gv_precis
  * device memory is allocated.  gv_profile_read waits for the recorded events.
  */
 typedef enum {
-    GV_PROF_FORWARD_PASS = 0,   /* fused ansatz tile pass */
-    GV_PROF_BACKWARD_PASS = 1,  /* fused reverse-sweep tile pass */
+    GV_PROF_FORWARD_PASS = 0,   /* fused ansatz tile pass (one layer) */
+    GV_PROF_BACKWARD_PASS = 1,  /* reverse tile pass rotating phi and lambda */
     GV_PROF_ENERGY = 2,         /* diagonal energy and lambda = H psi */
     GV_PROF_INIT = 3,           /* first-layer product state */
     GV_PROF_PLAIN_GATE = 4,     /* plain engine gate or reverse step */
     GV_PROF_OTHER = 5,          /* tables, reductions, copies, gathers */
     GV_PROF_OFFDIAG = 6,        /* off-diagonal terms: lambda += H_off psi */
     GV_PROF_FIRST_LAYER = 7,    /* first rotation layer's gradients from lambda */
-    GV_PROF_KINDS = 8
+    GV_PROF_FORWARD_PASS2 = 8,  /* two-layer forward tile pass */
+    GV_PROF_BACKWARD_LD = 9,    /* reverse pass undoing a layer diagonal on load */
+    GV_PROF_BACKWARD_GF = 10,   /* reverse pass rotating lambda alone (phi not kept) */
+    GV_PROF_BACKWARD_GF_LD = 11,/* the same, undoing a layer diagonal on load */
+    GV_PROF_TURNAROUND = 12,    /* last forward pass + energy + first reverse pass */
+    GV_PROF_KINDS = 13
 } gv_prof_kind;
 
 gv_status gv_profile_enable(gv_state st, int32_t enable);

@@ -465,7 +465,8 @@ static gv_status snake_forward(gv_state st, const gv_ansatz &an, const FusedCtx 
         const FwdOp &op = c.ops[k];
         void *dst = store ? store_out(c, (int)k, psi, ckpt, vb) : psi;
         const void *src = (store && k > 0) ? store_out(c, (int)k - 1, psi, ckpt, vb) : dst;
-        ProfScope ps(st, GV_PROF_FORWARD_PASS, op.in_mode == FWD_GENERATE ? (double)vb : 2.0 * vb);
+        ProfScope ps(st, op.lb >= 0 ? GV_PROF_FORWARD_PASS2 : GV_PROF_FORWARD_PASS,
+                     op.in_mode == FWD_GENERATE ? (double)vb : 2.0 * vb);
         hipError_t e = op.lb >= 0
                            ? fused_forward2_pass(st->prec, dst, an, c.plan, op.g, op.la, op.in_mode,
                                                  c.ch, c.tabs, c.ld[op.la], s, src)
@@ -983,7 +984,7 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
             if (gv_status r = snake_forward(st, *a, c, nops - 1, psi, ck, vb, store)) return r;
             const FwdOp &op = ops[nops - 1];
             const void *tin = (store && nops >= 2) ? store_out(c, nops - 2, psi, ck, vb) : psi;
-            ProfScope ps(st, GV_PROF_ENERGY, 2.0 * vb + 8.0 * (double)((size_t)1 << n));
+            ProfScope ps(st, GV_PROF_TURNAROUND, 2.0 * vb + 8.0 * (double)((size_t)1 << n));
             if (gv_status r = check_hip(fused_turnaround(st->prec, tin, lam, h->diag, *a, c.plan,
                                                          op.g, op.la, op.in_mode, c.ch, c.tabs,
                                                          part, epart, c.w.grid, s),
@@ -1042,7 +1043,11 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
                 fl.diag_phi = fl.diag_lam = 0;
             }
             const double bytes = (3.0 + (fl.store_phi ? 1.0 : 0.0)) * vb;
-            ProfScope ps(st, GV_PROF_BACKWARD_PASS, bytes);
+            const bool ldl = op.lb >= 0;
+            ProfScope ps(st,
+                         fl.grad_first ? (ldl ? GV_PROF_BACKWARD_GF_LD : GV_PROF_BACKWARD_GF)
+                                       : (ldl ? GV_PROF_BACKWARD_LD : GV_PROF_BACKWARD_PASS),
+                         bytes);
             hipError_t e = fused_backward_pass(st->prec, phi_src, psi, lam, *a, c.plan, op.g, op.la,
                                                fl, c.ch, c.tabs, part, c.w.grid, s,
                                                op.lb >= 0 ? &c.ld0[op.la] : nullptr);
@@ -1067,7 +1072,7 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
         if (gv_status r = fused_forward(st, *a, c, R - 1, true, psi, ckpt, vb)) return r;
         const int l = R - 1, p = np - 1;
         const int in_mode = np > 1 ? FWD_LOAD : (l == 1 ? FWD_GENERATE : FWD_LOAD_DIAG);
-        ProfScope ps(st, GV_PROF_ENERGY, 2.0 * vb + 8.0 * (double)((size_t)1 << n));
+        ProfScope ps(st, GV_PROF_TURNAROUND, 2.0 * vb + 8.0 * (double)((size_t)1 << n));
         if (gv_status r = check_hip(fused_turnaround(st->prec, psi, lam, h->diag, *a, c.plan, p, l,
                                                      in_mode, c.ch, c.tabs, part, epart,
                                                      c.w.grid, s),

@@ -488,15 +488,52 @@ struct InvChainRev {
     }
 };
 
+// partials of assignments AI, AI-1, .., 0, each after an exchange of both
+// vectors from AI+1
+template <typename R, int K, int LOGR, int AI>
+struct GradChainRev {
+    __device__ static __forceinline__ void run(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
+                                               double (&accY)[K], cx<R> *lds, int t,
+                                               const FusedArgs &a)
+    {
+        using T = Tile<K, LOGR>;
+        exchange<R, K, LOGR, T::lo(AI + 1), T::lo(AI)>(f, lds, t);
+        exchange<R, K, LOGR, T::lo(AI + 1), T::lo(AI)>(l, lds, t);
+        ygrad_assign<R, K, LOGR, AI>(f, l, accY, a);
+        if constexpr (AI > 0) GradChainRev<R, K, LOGR, AI - 1>::run(f, l, accY, lds, t, a);
+    }
+};
+
+// RY(-theta) of assignments AI .. NA-1 on one vector, each after an exchange
+// from AI-1
+template <typename R, int K, int LOGR, int AI>
+struct InvChain {
+    __device__ static __forceinline__ void run(cx<R> (&v)[1 << LOGR], cx<R> *lds, int t,
+                                               const FusedArgs &a, int layer)
+    {
+        using T = Tile<K, LOGR>;
+        exchange<R, K, LOGR, T::lo(AI - 1), T::lo(AI)>(v, lds, t);
+        inv_assign<R, K, LOGR, AI>(v, a, layer);
+        if constexpr (AI + 1 < T::NA) InvChain<R, K, LOGR, AI + 1>::run(v, lds, t, a, layer);
+    }
+};
+
 // Load a pass's tile in the load assignment.  In pass 0 the loaded values
 // may be multiplied by the layer diagonal (IN_LOAD_DIAG) or replaced by the
 // generated first-layer state (IN_GENERATE).
-template <typename R, int K, int LOGR, bool CONTIG>
+// PL: the caller guarantees mode == IN_LOAD (the common case, compiled
+// without the table code).
+template <typename R, int K, int LOGR, bool CONTIG, bool PL = false>
 __device__ __forceinline__ void load_tile(cx<R> (&v)[1 << LOGR], const cx<R> *src, u64 base,
                                           u64 toff, const RegMap<LOGR, CONTIG> &m, int mode,
                                           P0Diag<R, K, LOGR> &pd, const DiagTab &d, int t)
 {
     constexpr int NR = 1 << LOGR;
+    if constexpr (PL) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = src[base | toff | m.off(r)];
+        return;
+    }
     if (mode != IN_LOAD) pd.tile(d, base, t);
     if (mode == IN_GENERATE) {
 #pragma unroll
@@ -515,7 +552,7 @@ __device__ __forceinline__ void load_tile(cx<R> (&v)[1 << LOGR], const cx<R> *sr
 // of blocks (t0 = blockIdx.x, tstep = gridDim.x) or a single block that owns
 // a whole batch instance (t0 = 0, tstep = 1) can run them; col is the
 // partial-sum column the block writes.
-template <typename R, int K, int LOGR, bool CONTIG>
+template <typename R, int K, int LOGR, bool CONTIG, bool PL = false>
 __device__ __forceinline__ void fwd_body(cx<R> *psi, const cx<R> *src, const FusedArgs &a,
                                          u64 t0, u64 tstep, cx<R> *lds)
 {
@@ -531,7 +568,7 @@ __device__ __forceinline__ void fwd_body(cx<R> *psi, const cx<R> *src, const Fus
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> v[T::NR];
-        load_tile<R, K, LOGR, CONTIG>(v, src, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
+        load_tile<R, K, LOGR, CONTIG, PL>(v, src, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
         fwd_assign<R, K, LOGR, 0>(v, a, a.layer);
         if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(v, lds, t, a, a.layer);
 #pragma unroll
@@ -545,6 +582,16 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_pass(void *psi_, const 
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     fwd_body<R, K, LOGR, CONTIG>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x, gridDim.x, lds);
+}
+
+// the same for a plain load (no diagonal on load, no generated layer)
+template <typename R, int K, int LOGR, bool CONTIG>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_load_pass(void *psi_, const void *src_,
+                                                                   FusedArgs a)
+{
+    __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
+    fwd_body<R, K, LOGR, CONTIG, true>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
+                                       gridDim.x, lds);
 }
 
 // Block sums of the gradient partials of the pass's active tile qubits for
@@ -773,13 +820,15 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_gf_ld_pass(const void *
 
 // Last forward pass of the last layer + energy + first reverse pass, for a
 // Z-only Hamiltonian with diagonal D: in each tile psi gets the pass's RY
-// gates, E += sum D_i |psi_i|^2, lam = D psi, then the reverse step of the
-// same gates runs on (psi, lam) and only lam is stored (phi after the
-// reverse step equals the loaded tile, which stays in HBM).  RZ gradients of
-// the tile qubits are zero here: Im(conj(D_i psi_i) psi_i) = 0.  When this is
-// the layer's only pass, the load applies the previous layer's diagonal (or
-// generates the first layer's state).
-template <typename R, int K, int LOGR, bool CONTIG>
+// gates (assignments 0 .. NA-1), E += sum D_i |psi_i|^2 and lam = D psi;
+// the RY partials of the pass are taken right there, at the pass's end point
+// (assignments NA-1 .. 0 with both vectors), then lam alone is rotated back
+// (0 .. NA-1) and stored; psi is not written (it equals the loaded tile's
+// source, which stays in HBM).  RZ partials of the tile qubits are zero
+// here: Im(conj(D_i psi_i) psi_i) = 0.  When this is the layer's only pass,
+// the load applies the previous layer's diagonal (or generates the first
+// layer's state).
+template <typename R, int K, int LOGR, bool CONTIG, bool PL>
 __device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const FusedArgs &a,
                                           u64 t0, u64 tstep, int col, cx<R> *lds, double *sh)
 {
@@ -800,22 +849,26 @@ __device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const Fu
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> f[T::NR], l[T::NR];
-        load_tile<R, K, LOGR, CONTIG>(f, psi, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
+        load_tile<R, K, LOGR, CONTIG, PL>(f, psi, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
         fwd_assign<R, K, LOGR, 0>(f, a, a.layer);
         if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(f, lds, t, a, a.layer);
         // energy and lam in the last assignment's layout
+        R et = 0;
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
             const double d = a.hdiag[base | toff_st | mst.off(r)];
-            eacc += d * ((double)f[r].re * f[r].re + (double)f[r].im * f[r].im);
+            const R p = f[r].re * f[r].re + f[r].im * f[r].im;
+            et += (R)d * p;
             l[r].re = (R)d * f[r].re;
             l[r].im = (R)d * f[r].im;
         }
-        bwd_assign<R, K, LOGR, T::NA - 1>(f, l, accY, a, a.layer);
-        if constexpr (T::NA > 1)
-            BwdChainRev<R, K, LOGR, T::NA - 2>::run(f, l, accY, lds, t, a, a.layer);
+        eacc += (double)et;
+        ygrad_assign<R, K, LOGR, T::NA - 1>(f, l, accY, a);
+        if constexpr (T::NA > 1) GradChainRev<R, K, LOGR, T::NA - 2>::run(f, l, accY, lds, t, a);
+        inv_assign<R, K, LOGR, 0>(l, a, a.layer);
+        if constexpr (T::NA > 1) InvChain<R, K, LOGR, 1>::run(l, lds, t, a, a.layer);
 #pragma unroll
-        for (int r = 0; r < T::NR; ++r) lam[base | toff_ld | mld.off(r)] = l[r];
+        for (int r = 0; r < T::NR; ++r) lam[base | toff_st | mst.off(r)] = l[r];
     }
     write_partials<R, K, LOGR, 0, false>(accY, accZr, 0.0, sh, a, a.layer, col);
     const double e = block_sum(eacc, sh);
@@ -825,16 +878,26 @@ __device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const Fu
     }
 }
 
-// Capped at 256 registers (two waves per SIMD): the few spilled values cost
-// less than running one wave per SIMD.
 template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) __attribute__((amdgpu_waves_per_eu(2))) void k_turn_pass(const void *psi_, void *lam_,
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_pass(const void *psi_, void *lam_,
                                                                FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
-    turn_body<R, K, LOGR, CONTIG>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x, gridDim.x,
-                                  blockIdx.x, lds, sh);
+    turn_body<R, K, LOGR, CONTIG, false>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x,
+                                         gridDim.x, blockIdx.x, lds, sh);
+}
+
+// Plain-load turnaround for 12-bit tiles, run by 512 threads holding 8
+// amplitudes each (4 assignments): fewer registers per thread keeps two
+// waves per SIMD resident without spilling.
+template <typename R>
+__global__ __launch_bounds__(512) void k_turn_load_pass(const void *psi_, void *lam_, FusedArgs a)
+{
+    __shared__ cx<R> lds[Tile<12, 3>::LDS];
+    __shared__ double sh[512 / 64 + 1];
+    turn_body<R, 12, 3, true, true>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x,
+                                     gridDim.x, blockIdx.x, lds, sh);
 }
 
 
@@ -845,7 +908,7 @@ __global__ __launch_bounds__(1 << (K - LOGR)) __attribute__((amdgpu_waves_per_eu
 // gates through the assignments 0 .. NA-1, the first layer's diagonal in
 // the last assignment, then the second layer's RY gates back through
 // NA-1 .. 0, and the tile is stored in the load layout.
-template <typename R, int K, int LOGR, bool CONTIG>
+template <typename R, int K, int LOGR, bool CONTIG, bool PL>
 __device__ __forceinline__ void fwd2_body(cx<R> *psi, const cx<R> *src, const FusedArgs &a,
                                           u64 t0, u64 tstep, cx<R> *lds)
 {
@@ -861,7 +924,7 @@ __device__ __forceinline__ void fwd2_body(cx<R> *psi, const cx<R> *src, const Fu
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> v[T::NR];
-        load_tile<R, K, LOGR, CONTIG>(v, src, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
+        load_tile<R, K, LOGR, CONTIG, PL>(v, src, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
         fwd_assign<R, K, LOGR, 0>(v, a, a.layer);
         if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(v, lds, t, a, a.layer);
         dg.tile(a.ld, tile, base | toff_st, t);
@@ -879,8 +942,17 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd2_pass(void *psi_, const
                                                                FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
-    fwd2_body<R, K, LOGR, CONTIG>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x, gridDim.x,
-                                  lds);
+    fwd2_body<R, K, LOGR, CONTIG, false>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
+                                         gridDim.x, lds);
+}
+
+template <typename R, int K, int LOGR, bool CONTIG>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd2_load_pass(void *psi_, const void *src_,
+                                                                    FusedArgs a)
+{
+    __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
+    fwd2_body<R, K, LOGR, CONTIG, true>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
+                                        gridDim.x, lds);
 }
 
 // ------------------------------------------------ first-layer gradients
@@ -1783,7 +1855,8 @@ hipError_t fused_forward_pass(int prec, void *psi, const gv_ansatz &an, const Ti
     if (in_mode == IN_LOAD_DIAG) a.dt = layer_tab(an, ch, t, layer - 1);
     if (in_mode == IN_GENERATE) a.dt = make_diagtab(an, ch, t.gtab, 0 < an.layers);
     const int grid = fused_grid(prec, plan, an.n);
-    GV_LAUNCH_K(k_fwd_pass, prec, grid, plan.K, psi, src, a);
+    if (in_mode == IN_LOAD) GV_LAUNCH_K(k_fwd_load_pass, prec, grid, plan.K, psi, src, a);
+    else GV_LAUNCH_K(k_fwd_pass, prec, grid, plan.K, psi, src, a);
     return hipGetLastError();
 }
 
@@ -1962,7 +2035,8 @@ hipError_t fused_forward2_pass(int prec, void *psi, const gv_ansatz &an, const T
     if (in_mode == IN_LOAD_DIAG) a.dt = layer_tab(an, ch, t, layer - 1);
     if (in_mode == IN_GENERATE) a.dt = make_diagtab(an, ch, t.gtab, 0 < an.layers);
     const int grid = fused_grid(prec, plan, an.n);
-    GV_LAUNCH_K(k_fwd2_pass, prec, grid, plan.K, psi, src, a);
+    if (in_mode == IN_LOAD) GV_LAUNCH_K(k_fwd2_load_pass, prec, grid, plan.K, psi, src, a);
+    else GV_LAUNCH_K(k_fwd2_pass, prec, grid, plan.K, psi, src, a);
     return hipGetLastError();
 }
 
@@ -1980,7 +2054,14 @@ hipError_t fused_turnaround(int prec, const void *psi, void *lam, const double *
     a.part = part;
     a.epart = epart;
     a.grid = grid;
-    GV_LAUNCH_K(k_turn_pass, prec, grid, plan.K, psi, lam, a);
+    if (plan.K == 12 && in_mode == IN_LOAD) {
+        if (prec == GV_C64)
+            hipLaunchKernelGGL(k_turn_load_pass<float>, dim3(grid), dim3(512), 0, s, psi, lam, a);
+        else
+            hipLaunchKernelGGL(k_turn_load_pass<double>, dim3(grid), dim3(512), 0, s, psi, lam, a);
+    } else {
+        GV_LAUNCH_K(k_turn_pass, prec, grid, plan.K, psi, lam, a);
+    }
     return hipGetLastError();
 }
 

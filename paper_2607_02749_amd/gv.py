@@ -194,7 +194,9 @@ class State:
 
     # per-kernel-class timing (HIP events on the state's stream)
     PROF_KINDS = {"forward_pass": 0, "backward_pass": 1, "energy": 2, "init": 3,
-                  "plain_gate": 4, "other": 5, "offdiag": 6, "first_layer": 7}
+                  "plain_gate": 4, "other": 5, "offdiag": 6, "first_layer": 7,
+                  "forward_pass2": 8, "backward_ld": 9, "backward_gf": 10, "backward_gf_ld": 11,
+                  "turnaround": 12}
 
     def profile(self, enable: bool = True):
         _check(lib().gv_profile_enable(self.handle, int(enable)), "gv_profile_enable")
