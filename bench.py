@@ -1,17 +1,30 @@
 """Benchmark: energy + adjoint-gradient evaluations per second on one MI355X.
 
-Workload (default): n = 28 qubits, complex64 state (2 GiB) with FP64
-reductions, hardware-efficient ansatz with L = 6 layers of RY, RZ and a
-linear CZ ladder (336 parameters), Hamiltonian of 20,000 Z-strings of weight
-1-6 on a 16-community planted interaction graph (seed 0).  One step is one
-energy + full gradient through ``GVEnergy`` (forward and backward); the
-diagonal is built once before timing (it does not depend on the angles).
+Workload (default, ``--workload n28``): n = 28 qubits, complex64 state
+(2 GiB) with FP64 reductions, hardware-efficient ansatz with L = 6 layers of
+RY, RZ and a linear CZ ladder (336 parameters), Hamiltonian of 20,000
+Z-strings of weight 1-6 on a 16-community planted interaction graph (seed 0).
+One step is one energy + full gradient through ``GVEnergy`` (forward and
+backward); the diagonal is built once before timing (it does not depend on
+the angles).  The default gradient mode keeps every tile pass's output state
+(``store``); ``--mode`` picks another.
 
-The JSON line also carries: the plain complex128 GPU path on the same
-workload, the dominant kernel's achieved HBM bandwidth (algorithmic bytes per
-launch over its HIP-event-timed average duration, taken inside the timed
-region), the error against the stored oracle result, and the CPU oracle timed
-on a bounded sample of the same evaluation.
+The JSON line also carries: the dominant kernel's achieved HBM bandwidth
+(algorithmic bytes per launch over its HIP-event-timed average duration on
+the launch stream, inside the timed region) with the HBM bytes the hardware
+counters measured for it, every kernel class's time, the error against the
+stored oracle result, the plain complex128 GPU path on the same workload,
+and the CPU oracle timed on a bounded sample of the same evaluation.
+
+``--workload batch``: 256 uneven cluster instances (n in 12..20, L in 3..5,
+50 n Z-strings + 5 n XX/YY terms each, restricted to the instance's
+community) in one persistent kernel replayed from a HIP graph, with the
+launch shape from the autotuner; instance evaluations per second.
+
+``--workload n32``: n = 32 (32 GiB per complex64 state), L = 4, 50,000
+Z-strings + 2,000 XX/YY/XZ/ZY terms in 64 qubit-wise-commuting groups; one
+evaluation per gradient memory mode (uncompute, checkpoint, recompute, and
+store when it fits), each with its device memory and time.
 """
 import argparse
 import json
@@ -25,6 +38,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+HBM_BYTES = 288 * 2**30
+
+KERNELS = {
+    "forward_pass": "k_fwd_load_pass<float,12,4>", "forward_pass2": "k_fwd2_load_pass<float,12,4>",
+    "backward_pass": "k_bwd_pass<float,12,4>", "backward_ld": "k_bwd_ld_pass<float,12,4>",
+    "backward_gf": "k_bwd_gf_pass<float,12,4>", "backward_gf_ld": "k_bwd_gf_ld_pass<float,12,4>",
+    "turnaround": "k_turn_load_pass<float>", "first_layer": "k_layer0_grad<float,12,4>",
+    "energy": "k_energy_diag<float>", "offdiag": "k_offdiag_pass<float,12,4>",
+}
 
 
 def parse():
@@ -32,6 +54,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="n28", choices=["n28", "n32", "batch"])
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -57,6 +80,69 @@ def time_steps(step, k, torch):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return wall, ev0.elapsed_time(ev1) / 1000.0
+
+
+def measure(inst, mode, steps, warmup, h=None):
+    """Time `steps` evaluations (after `warmup`) of E and its gradient through
+    GVEnergy in complex64; per-kernel-class HIP-event profile of the timed
+    region.  h: a PauliSum already prepared for complex64 / fused."""
+    import torch
+    from paper_2607_02749_amd import gv
+    an = gv.Ansatz(inst.n, inst.layers, inst.ent, inst.final_rotation)
+    st = gv.State(inst.n, "c64", "fused", an, mode)
+    diag_ms = None
+    if h is None:
+        t0 = time.perf_counter()
+        h = gv.PauliSum(inst.n, inst.x, inst.z, inst.c).prepare(st)
+        torch.cuda.synchronize()
+        diag_ms = (time.perf_counter() - t0) * 1e3
+    theta = torch.tensor(inst.theta, dtype=torch.float64, device=st.device, requires_grad=True)
+    last = {}
+
+    def step():
+        E = gv.GVEnergy.apply(theta, st, h, an, None, mode)
+        E.backward()
+        last["E"] = E.detach()
+        last["g"] = theta.grad
+        theta.grad = None
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    st.profile(True)
+    st.profile_reset()
+    wall, ev = time_steps(step, steps, torch)
+    prof = st.profile_read()
+    st.profile(False)
+    sb, wb = gv.query_sizes(an, "c64", "fused", mode)
+    out = {"wall": wall, "ev": ev, "prof": prof, "E": last["E"].item(),
+           "g": last["g"].cpu().numpy(), "state_bytes": sb, "work_bytes": wb,
+           "h_bytes": h.device_bytes, "diag_ms": diag_ms}
+    del st, theta, last
+    torch.cuda.empty_cache()
+    return out, h
+
+
+def roofline(prof, steps):
+    kinds = {k: v for k, v in prof.items() if v[0] > 0}
+    dom = max(kinds, key=lambda k: kinds[k][1])
+    n_l, ms_l, bytes_l = kinds[dom]
+    avg_ms = ms_l / n_l
+    achieved = (bytes_l / n_l) / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        tr = json.load(open(tpath)).get(dom)
+        if tr and tr.get("kernel_source_hash") == _kernel_hash():
+            traffic = tr.get("bytes_per_launch")
+    breakdown = {k: {"launches_per_step": v[0] / steps, "ms_per_step": v[1] / steps,
+                     "GBps": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None}
+                 for k, v in kinds.items()}
+    roof = {"bound": "hbm", "kernel": KERNELS.get(dom, dom), "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic, "avg_launch_ms": avg_ms,
+            "algorithmic_bytes_per_launch": bytes_l / n_l}
+    return roof, breakdown
 
 
 def cpu_baseline(inst):
@@ -96,89 +182,45 @@ def cpu_baseline(inst):
     }
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this engine has no "
-              "multi-GPU path", file=sys.stderr)
-        sys.exit(2)
-    import torch
-    from paper_2607_02749_amd import gv, synth
-
-    inst = synth.workload_n28()
-    an = gv.Ansatz(inst.n, inst.layers, inst.ent)
-    log("workload ready", inst.n, inst.layers, inst.num_terms)
-
-    st = gv.State(inst.n, "c64", "fused", an, args.mode)
-    t0 = time.perf_counter()
-    h = gv.PauliSum(inst.n, inst.x, inst.z, inst.c).prepare(st)
+def copy_probe(torch):
+    src = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    dst.copy_(src)
     torch.cuda.synchronize()
-    diag_ms = (time.perf_counter() - t0) * 1e3
-    theta = torch.tensor(inst.theta, dtype=torch.float64, device=st.device, requires_grad=True)
-
-    last = {}
-
-    def step():
-        E = gv.GVEnergy.apply(theta, st, h, an, None, args.mode)
-        E.backward()
-        last["E"] = E.detach()
-        last["g"] = theta.grad
-        theta.grad = None
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log("warmup done")
-    st.profile(True)
-    st.profile_reset()
-    wall, ev = time_steps(step, args.steps, torch)
-    prof = st.profile_read()
-    st.profile(False)
-    log("timed", args.steps, "steps in", wall, "s")
-
-    copy = None
-    if args.copy_probe:
-        src = torch.empty(1 << 31, dtype=torch.uint8, device=st.device)
-        dst = torch.empty_like(src)
-        src.fill_(1)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(5):
         dst.copy_(src)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(5):
-            dst.copy_(src)
-        ev1.record()
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / 5
-        copy = {"bytes": 2 * src.numel(), "ms": ms, "GBps": 2 * src.numel() / (ms * 1e-3) / 1e9}
-        del src, dst
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / 5
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes": 2 * (1 << 31), "ms": ms, "GBps": 2 * (1 << 31) / (ms * 1e-3) / 1e9}
 
-    value = args.steps / wall
-    kinds = {k: v for k, v in prof.items() if v[0] > 0}
-    dom = max(kinds, key=lambda k: kinds[k][1])
-    n_l, ms_l, bytes_l = kinds[dom]
-    avg_ms = ms_l / n_l
-    achieved = (bytes_l / n_l) / (avg_ms * 1e-3) / 1e9
-    kernel_names = {"backward_pass": "k_bwd_pass<float,12,4>", "forward_pass": "k_fwd_pass<float,12,4>",
-                    "energy": "k_energy_diag<float>", "init": "k_init_state<float>"}
-    breakdown = {k: {"launches_per_step": v[0] / args.steps, "ms_per_step": v[1] / args.steps,
-                     "GBps": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None}
-                 for k, v in kinds.items()}
+
+def bench_n28(args, torch, gv, synth):
+    inst = synth.workload_n28()
+    log("workload ready", inst.n, inst.layers, inst.num_terms)
+    m, h = measure(inst, args.mode, args.steps, args.warmup)
+    log("timed", args.steps, "steps in", m["wall"], "s")
+    roof, breakdown = roofline(m["prof"], args.steps)
+    copy = copy_probe(torch) if args.copy_probe else None
 
     parity = None
     gold_path = os.path.join(ROOT, "tests", "golden", "oracle_n28.json")
     if os.path.exists(gold_path):
         gold = json.load(open(gold_path))
         e_ref, g_ref = gold["energy"][0], np.array(gold["grad"])
-        e = last["E"].item()
-        g = last["g"].cpu().numpy()
-        parity = {"energy_rel": abs(e - e_ref) / abs(e_ref),
-                  "grad_rel_l2": float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))}
+        parity = {"energy_rel": abs(m["E"] - e_ref) / abs(e_ref),
+                  "grad_rel_l2": float(np.linalg.norm(m["g"] - g_ref) / np.linalg.norm(g_ref))}
+    del h
+    torch.cuda.empty_cache()
 
     plain = None
     if not args.no_plain:
-        del st, h
-        torch.cuda.empty_cache()
+        an = gv.Ansatz(inst.n, inst.layers, inst.ent)
         st2 = gv.State(inst.n, "c128", "plain", an)
         h2 = gv.PauliSum(inst.n, inst.x, inst.z, inst.c).prepare(st2)
         th2 = torch.tensor(inst.theta, dtype=torch.float64, device=st2.device)
@@ -199,35 +241,144 @@ def main():
         del st2, h2
 
     cpu = None if args.no_cpu else cpu_baseline(inst)
-
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tpath):
-        tr = json.load(open(tpath)).get(dom)
-        if tr and tr.get("kernel_source_hash") == _kernel_hash():
-            traffic = tr.get("bytes_per_launch")
-
-    out = {
+    return {
         "metric": "energy+adjoint-grad evals/s at n=28 c64 vs plain c128; HBM GB/s vs peak",
-        "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "value": args.steps / m["wall"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": m["wall"] / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
         "data": "synthetic",
         "config": {"workload": "n28_L6_czlinear_20000z", "n": inst.n, "layers": inst.layers,
                    "params": inst.num_params, "terms": inst.num_terms, "state": "complex64",
                    "reductions": "fp64", "gradient": "adjoint via torch.autograd.Function",
-                   "grad_mode": args.mode, "seed": 0, "diag_build_ms": diag_ms,
-                   "event_ms_per_step": ev / args.steps * 1e3},
-        "roofline": {"bound": "hbm", "kernel": kernel_names.get(dom, dom), "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "avg_launch_ms": avg_ms,
-                     "algorithmic_bytes_per_launch": bytes_l / n_l},
+                   "grad_mode": args.mode, "seed": 0, "diag_build_ms": m["diag_ms"],
+                   "event_ms_per_step": m["ev"] / args.steps * 1e3,
+                   "device_bytes": {"state": m["state_bytes"], "work": m["work_bytes"],
+                                    "hamiltonian": m["h_bytes"]}},
+        "roofline": roof,
         "kernels": breakdown,
         "parity_vs_oracle": parity,
         "plain_c128": plain,
         "copy_probe": copy,
         "cpu_baseline": cpu,
     }
+
+
+def bench_n32(args, torch, gv, synth):
+    """One evaluation per gradient memory mode at n = 32 (the workload does
+    not fit the oracle: parity at this size is covered by the properties in
+    tests/test_gpu_fullsize.py)."""
+    inst = synth.workload_n32()
+    log("workload ready", inst.n, inst.layers, inst.num_terms)
+    an = gv.Ansatz(inst.n, inst.layers, inst.ent)
+    h = None
+    modes = {}
+    e_ref = g_ref = None
+    first = None
+    for mode in ("uncompute", "checkpoint", "recompute", "store"):
+        sb, wb = gv.query_sizes(an, "c64", "fused", mode)
+        hb = h.device_bytes if h is not None else None
+        need = sb + wb + (hb or (8 << inst.n))
+        if need > HBM_BYTES - (8 << 30):
+            modes[mode] = {"fits": False, "device_bytes": need}
+            log(mode, "does not fit:", need / 2**30, "GiB")
+            continue
+        m, h = measure(inst, mode, args.steps, args.warmup, h)
+        roof, breakdown = roofline(m["prof"], args.steps)
+        if e_ref is None:
+            e_ref, g_ref, first = m["E"], m["g"], m
+        modes[mode] = {"fits": True, "ms_per_eval": m["wall"] / args.steps * 1e3,
+                       "device_bytes": {"state": sb, "work": wb, "hamiltonian": m["h_bytes"]},
+                       "energy_rel_vs_uncompute": abs(m["E"] - e_ref) / abs(e_ref),
+                       "grad_rel_l2_vs_uncompute": float(np.linalg.norm(m["g"] - g_ref)
+                                                         / np.linalg.norm(g_ref)),
+                       "roofline": roof, "kernels": breakdown}
+        log(mode, modes[mode]["ms_per_eval"], "ms/eval")
+    u = modes["uncompute"]
+    return {
+        "metric": "energy+adjoint-grad evals/s at n=32 c64 per gradient memory mode",
+        "value": 1e3 / u["ms_per_eval"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": u["ms_per_eval"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": "n32_L4_czlinear_50000z_2000offdiag_64groups", "n": inst.n,
+                   "layers": inst.layers, "params": inst.num_params, "terms": inst.num_terms,
+                   "grad_mode": "uncompute", "diag_build_ms": first["diag_ms"]},
+        "roofline": u["roofline"],
+        "modes": modes,
+        "cpu_baseline": None,
+    }
+
+
+def bench_batch(args, torch, gv, synth):
+    """Config: 256 instances, complex64, one graph replay per step."""
+    import oracle
+    from paper_2607_02749_amd import autotune
+    insts = synth.workload_batch(count=256)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    items = []
+    for inst in insts:
+        an = gv.Ansatz(inst.n, inst.layers, inst.ent, inst.final_rotation)
+        th = torch.tensor(inst.theta, dtype=torch.float64, device=dev)
+        items.append((an, th, gv.PauliSum(inst.n, inst.x, inst.z, inst.c), inst.cluster_mask))
+    tune = autotune.tune_batch(items, "c64")
+    log("tuned", {k: tune[k] for k in ("blocks_per_cu", "order", "ms", "cached")})
+    b = gv.Batch(items, "c64", blocks_per_cu=tune["blocks_per_cu"], order=tune["order"], graph=True)
+    for _ in range(args.warmup):
+        b.run()
+    wall, ev = time_steps(b.run, args.steps, torch)
+    # parity: the smallest instances against the oracle (restricted gradient)
+    order = sorted(range(len(insts)), key=lambda i: (insts[i].n, insts[i].layers))[:4]
+    worst_e = worst_g = 0.0
+    for i in order:
+        inst = insts[i]
+        mask = oracle.param_mask(inst.n, inst.layers, inst.cluster_mask)
+        e_ref, g_ref = oracle.energy_grad(inst.n, inst.layers, inst.ent, inst.theta, inst.x,
+                                          inst.z, inst.c, mask=mask)
+        e = b.energies[i, 0].item()
+        g = b.grads[i].cpu().numpy()
+        worst_e = max(worst_e, abs(e - e_ref.real) / abs(e_ref.real))
+        worst_g = max(worst_g, float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)))
+    # algorithmic bytes of one batch: per instance and layer, the tile passes
+    # (one per 12-bit tile set: 1 pass for n <= 12, 2 for n <= 20) read and
+    # write psi forward and psi, lam backward, plus psi, D and lam for the
+    # energy (layer 0 is generated)
+    total = 0.0
+    for inst in insts:
+        A = 1 << inst.n
+        npass = 1 if inst.n <= 12 else 2
+        R = inst.layers + inst.final_rotation
+        total += A * 8 * (2 * npass * (R - 1) + 4 * npass * R) + A * (8 + 8 + 8)
+    ms = ev / args.steps * 1e3
+    achieved = total / (ms * 1e-3) / 1e9
+    return {
+        "metric": "batched energy+restricted-grad instance evals/s (256 uneven instances, c64)",
+        "value": len(insts) * args.steps / wall, "unit": "instance evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "batch256_n12-20_L3-5", "instances": len(insts),
+                   "n_range": [min(x.n for x in insts), max(x.n for x in insts)],
+                   "graph": True, "tuning": {k: tune[k] for k in ("blocks_per_cu", "order")},
+                   "event_ms_per_step": ms},
+        "roofline": {"bound": "hbm", "kernel": "k_batch<float>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "avg_launch_ms": ms,
+                     "algorithmic_bytes_per_launch": total},
+        "parity_vs_oracle": {"instances": order, "energy_rel_max": worst_e,
+                             "grad_rel_l2_max": worst_g},
+        "cpu_baseline": None,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this engine has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2607_02749_amd import gv, synth
+    run = {"n28": bench_n28, "n32": bench_n32, "batch": bench_batch}[args.workload]
+    out = run(args, torch, gv, synth)
     print(json.dumps(out))
 
 

@@ -971,7 +971,9 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
 
     if (use_snake(*a)) {
         const bool store = mode == GV_GRAD_STORE;
-        if (gv_status r = snake_setup(st, *a, theta, turn, mode == GV_GRAD_CHECKPOINT, &c)) return r;
+        // checkpoint slots mark the states that CHECKPOINT keeps and RECOMPUTE rebuilds
+        const bool slots = mode == GV_GRAD_CHECKPOINT || mode == GV_GRAD_RECOMPUTE;
+        if (gv_status r = snake_setup(st, *a, theta, turn, slots, &c)) return r;
         const std::vector<FwdOp> &ops = c.ops;
         const int nops = (int)ops.size();
         for (const FwdOp &op : ops)

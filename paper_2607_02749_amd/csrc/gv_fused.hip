@@ -111,7 +111,8 @@ struct Tile {
     }
 };
 
-__device__ __forceinline__ u64 tile_base(u64 tile, const FusedArgs &a)
+template <typename Args>
+__device__ __forceinline__ u64 tile_base(u64 tile, const Args &a)
 {
     u64 b = 0;
     for (int i = 0; i < a.nruns; ++i)
@@ -121,8 +122,8 @@ __device__ __forceinline__ u64 tile_base(u64 tile, const FusedArgs &a)
 
 // physical offset of the thread bits of the assignment with register bits
 // [l, l + LOGR) (the other tile bits take thread-id bits in ascending order)
-template <int K, int LOGR>
-__device__ __forceinline__ u64 thread_off(int t, int l, const FusedArgs &a)
+template <int K, int LOGR, typename Args>
+__device__ __forceinline__ u64 thread_off(int t, int l, const Args &a)
 {
     u64 off = 0;
     int tb = 0;
@@ -1136,37 +1137,63 @@ struct OffArgs {
     int estride;
 };
 
+// A term of a cover pass as the inner loop uses it: z, its coefficient
+// with the fixed signs folded in (c, times -1 for ph & 2 and for the parity
+// of x & z), and per register r the sign of the register bits' share of
+// (i ^ x) & z (bit r of `regsign`) plus the real / imaginary choice (ph odd).
+struct OffStaged {
+    u64 z;
+    double cf;
+    uint32_t regsign_imag;   // bits 0..15: register signs; bit 31: i^ph is imaginary
+    uint32_t pad;
+};
+constexpr int kOffStage = 512;  // terms staged in LDS per pass (the rest read in place)
+
 // One cover pass: the psi tile sits in LDS, so for every class (flip mask x
 // inside the tile) each amplitude reads its partner psi_{i^x} there and adds
-// F(i^x) psi_{i^x} to lam_i; the class factor F is summed over the class's
-// terms in the amplitude precision.  The pass's share of <psi|H|psi> goes to
-// FP64 partials.
+// F(i^x) psi_{i^x} to lam_i, where F(i^x) = sum_k c_k i^{ph_k}
+// (-1)^{popcount((i^x) & z_k)}.  The parity splits over the index bits:
+// x & z (fixed per term), the tile base and the thread's bits (once per
+// tile and thread), and the register bits (a fixed sign pattern over the
+// registers), so each term costs one select and one add per amplitude.
+// The pass's share of <psi|H|psi> goes to FP64 partials.
 template <typename R, int K, int LOGR>
 __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const OffArgs &a, u64 t0,
-                                         u64 tstep, int col, cx<R> *lds, double *sh)
+                                         u64 tstep, int col, cx<R> *lds, double *sh,
+                                         OffStaged *stg)
 {
     using T = Tile<K, LOGR>;
     const int t = threadIdx.x;
     constexpr int LD = T::lo(0);
-    FusedArgs fa;  // only the tile geometry is used
-    for (int j = 0; j < K; ++j) fa.pos[j] = a.pos[j];
-    fa.nruns = a.nruns;
-    for (int k = 0; k < a.nruns; ++k) {
-        fa.run_src[k] = a.run_src[k];
-        fa.run_w[k] = a.run_w[k];
-        fa.run_dst[k] = a.run_dst[k];
-    }
-    const u64 toff = thread_off<K, LOGR>(t, LD, fa);
+    const u64 toff = thread_off<K, LOGR>(t, LD, a);
     RegMap<LOGR, false> m;
     m.init(a.pos + LD);
+    // stage the pass's terms (classes c0 .. c1-1 own terms k0 .. k1-1)
+    const int k0 = a.cls[a.c0].t0, k1 = a.cls[a.c1 - 1].t1;
+    const int nst = min(k1 - k0, kOffStage);
+    for (int c = a.c0; c < a.c1; ++c) {
+        const OffClass C = a.cls[c];
+        for (int k = C.t0 + t; k < C.t1; k += blockDim.x) {
+            if (k - k0 >= nst) break;
+            const OffTerm tm = a.terms[k];
+            uint32_t pat = 0;
+            for (int r = 0; r < T::NR; ++r)
+                if (__popcll(m.off(r) & tm.z) & 1) pat |= 1u << r;
+            double cf = tm.c;
+            if ((tm.ph & 2) ^ ((__popcll(C.x & tm.z) & 1) << 1)) cf = -cf;
+            stg[k - k0] = OffStaged{tm.z, cf, pat | ((uint32_t)(tm.ph & 1) << 31), 0u};
+        }
+    }
+    __syncthreads();
     double er = 0.0, ei = 0.0;
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
-        const u64 base = tile_base(tile, fa);
+        const u64 base = tile_base(tile, a);
+        const u64 bt = base | toff;
         cx<R> v[T::NR], acc[T::NR];
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
-            v[r] = psi[base | toff | m.off(r)];
+            v[r] = psi[bt | m.off(r)];
             lds[T::pad(T::u_of(t, r, LD))] = v[r];
             acc[r].re = acc[r].im = R(0);
         }
@@ -1177,14 +1204,25 @@ __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const Off
 #pragma unroll
             for (int r = 0; r < T::NR; ++r) A[r] = B[r] = R(0);
             for (int k = C.t0; k < C.t1; ++k) {
-                const OffTerm tm = a.terms[k];
-                const R cc = (R)tm.c;
+                OffStaged q;
+                if (k - k0 < nst) {
+                    q = stg[k - k0];
+                } else {   // beyond the staging buffer: build the entry in place
+                    const OffTerm tm = a.terms[k];
+                    uint32_t pat = 0;
+                    for (int r = 0; r < T::NR; ++r)
+                        if (__popcll(m.off(r) & tm.z) & 1) pat |= 1u << r;
+                    double cf = tm.c;
+                    if ((tm.ph & 2) ^ ((__popcll(C.x & tm.z) & 1) << 1)) cf = -cf;
+                    q = OffStaged{tm.z, cf, pat | ((uint32_t)(tm.ph & 1) << 31), 0u};
+                }
+                const R w = (__popcll(bt & q.z) & 1) ? -(R)q.cf : (R)q.cf;
+                if (q.regsign_imag >> 31) {
 #pragma unroll
-                for (int r = 0; r < T::NR; ++r) {
-                    const u64 ip = (base | toff | m.off(r)) ^ C.x;
-                    const R sg = (__popcll(ip & tm.z) & 1) ? -cc : cc;
-                    if (tm.ph & 1) B[r] += (tm.ph & 2) ? -sg : sg;
-                    else A[r] += (tm.ph & 2) ? -sg : sg;
+                    for (int r = 0; r < T::NR; ++r) B[r] += ((q.regsign_imag >> r) & 1) ? -w : w;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < T::NR; ++r) A[r] += ((q.regsign_imag >> r) & 1) ? -w : w;
                 }
             }
 #pragma unroll
@@ -1199,7 +1237,7 @@ __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const Off
             er += (double)v[r].re * acc[r].re + (double)v[r].im * acc[r].im;
             ei += (double)v[r].re * acc[r].im - (double)v[r].im * acc[r].re;
             if (lam) {
-                const u64 i = base | toff | m.off(r);
+                const u64 i = bt | m.off(r);
                 cx<R> o = lam[i];
                 o.re += acc[r].re;
                 o.im += acc[r].im;
@@ -1222,8 +1260,9 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_offdiag_pass(const void *ps
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
+    __shared__ OffStaged stg[kOffStage];
     off_body<R, K, LOGR>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x, gridDim.x, blockIdx.x,
-                         lds, sh);
+                         lds, sh, stg);
 }
 
 // ------------------------------------------------------------ table kernels
@@ -1610,7 +1649,7 @@ __device__ __forceinline__ DiagTab batch_layer_tab(const BatchInst &I, int layer
 }
 
 template <typename R>
-__device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh)
+__device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh, OffStaged *stg)
 {
     constexpr int K = 12, LOGR = 4;
     const int t = threadIdx.x, nt = blockDim.x;
@@ -1677,7 +1716,7 @@ __device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh)
         o.terms = I.terms;
         o.epart = I.energy;
         o.estride = 1;
-        off_body<R, K, LOGR>(psi, lam, o, 0, 1, 0, lds, sh);
+        off_body<R, K, LOGR>(psi, lam, o, 0, 1, 0, lds, sh, stg);
         __syncthreads();
     }
     // reverse sweep
@@ -1708,6 +1747,7 @@ __global__ __launch_bounds__(256) void k_batch(const BatchInst *insts, const int
 {
     __shared__ cx<R> lds[Tile<12, 4>::LDS];
     __shared__ double sh[8];
+    __shared__ OffStaged stg[kOffStage];
     __shared__ int next;
     for (;;) {
         if (threadIdx.x == 0) next = (int)atomicAdd(counter, 1u);
@@ -1715,7 +1755,7 @@ __global__ __launch_bounds__(256) void k_batch(const BatchInst *insts, const int
         const int idx = next;
         __syncthreads();
         if (idx >= count) break;   // every block leaves once the queue is empty
-        batch_instance<R>(insts[order[idx]], lds, sh);
+        batch_instance<R>(insts[order[idx]], lds, sh, stg);
     }
 }
 

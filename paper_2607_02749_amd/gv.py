@@ -263,6 +263,13 @@ class PauliSum:
                "gv_pauli_sum_prepare_for")
         return self
 
+    @property
+    def device_bytes(self) -> int:
+        """Bytes of the device form (the FP64 diagonal and the off-diagonal tables)."""
+        nb = ctypes.c_size_t()
+        _check(lib().gv_pauli_sum_device_bytes(self.handle, ctypes.byref(nb)), "device_bytes")
+        return nb.value
+
     def diagonal(self) -> torch.Tensor:
         """The FP64 diagonal of the Z-only part (valid after prepare)."""
         return self.device_buffer[: 8 << self.n].view(torch.float64)
