@@ -320,13 +320,16 @@ def bench_batch(args, torch, gv, synth):
         th = torch.tensor(inst.theta, dtype=torch.float64, device=dev)
         items.append((an, th, gv.PauliSum(inst.n, inst.x, inst.z, inst.c), inst.cluster_mask))
     tune = autotune.tune_batch(items, "c64")
-    log("tuned", {k: tune[k] for k in ("blocks_per_cu", "order", "ms", "cached")})
-    b = gv.Batch(items, "c64", blocks_per_cu=tune["blocks_per_cu"], order=tune["order"], graph=True)
+    log("tuned", {k: tune[k] for k in ("blocks_per_cu", "order", "split_n", "ms", "cached")})
+    b = gv.Batch(items, "c64", blocks_per_cu=tune["blocks_per_cu"], order=tune["order"],
+                 split_n=tune["split_n"], graph=True)
     for _ in range(args.warmup):
         b.run()
     wall, ev = time_steps(b.run, args.steps, torch)
-    # parity: the smallest instances against the oracle (restricted gradient)
-    order = sorted(range(len(insts)), key=lambda i: (insts[i].n, insts[i].layers))[:4]
+    # parity: the two smallest instances (persistent kernel) and the two
+    # largest (whole-GPU passes) against the oracle (restricted gradient)
+    by_size = sorted(range(len(insts)), key=lambda i: (insts[i].n, insts[i].layers))
+    order = by_size[:2] + by_size[-2:]
     worst_e = worst_g = 0.0
     for i in order:
         inst = insts[i]
@@ -357,7 +360,8 @@ def bench_batch(args, torch, gv, synth):
         "data": "synthetic",
         "config": {"workload": "batch256_n12-20_L3-5", "instances": len(insts),
                    "n_range": [min(x.n for x in insts), max(x.n for x in insts)],
-                   "graph": True, "tuning": {k: tune[k] for k in ("blocks_per_cu", "order")},
+                   "graph": True,
+                   "tuning": {k: tune[k] for k in ("blocks_per_cu", "order", "split_n")},
                    "event_ms_per_step": ms},
         "roofline": {"bound": "hbm", "kernel": "k_batch<float>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

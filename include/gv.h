@@ -188,8 +188,12 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *params_dev,
  * its own ansatz size, angles, Hamiltonian and qubit block -- in one
  * persistent kernel: each block of the grid takes whole instances from an
  * atomic queue (largest first by default) and runs their forward sweep,
- * energy and reverse sweep.  The grid and order come from gv_batch_tuning
- * (an autotuner picks them; see paper_2607_02749_amd/autotune.py).
+ * energy and reverse sweep.  Instances with n >= split_n instead run as
+ * whole-GPU tile passes (the path of gv_energy_grad, uncompute mode) on
+ * side streams forked from and joined back to the batch's stream, alongside
+ * the persistent kernel, so one large instance is not left to a single
+ * compute unit.  Grid, order and split come from gv_batch_tuning (an
+ * autotuner picks them; see paper_2607_02749_amd/autotune.py).
  * Limits: 12 <= n <= 30; CZ or no entangler; every Hamiltonian prepared with
  * gv_pauli_sum_prepare_for(h, prec, GV_ENGINE_FUSED, ...).
  */
@@ -205,13 +209,17 @@ typedef struct {
 typedef struct {
     int32_t blocks_per_cu;     /* persistent blocks per compute unit, 1..8 (default 2) */
     int32_t order;             /* 0: largest instance first (default), 1: input order */
+    int32_t split_n;           /* n from which instances run as whole-GPU passes;
+                                  0: default (17), > 30: never */
 } gv_batch_tuning;
 
 typedef struct gv_batch_s *gv_batch;
 
-/* Workspace bytes for a batch (per-instance states, tables, descriptors). */
+/* Workspace bytes for a batch (per-instance states, tables, descriptors,
+ * and the work regions of the whole-GPU instances, which depend on
+ * tuning->split_n; tuning may be NULL for the defaults). */
 gv_status gv_batch_query(int32_t count, const gv_instance *inst, gv_precision prec,
-                         size_t *work_bytes);
+                         const gv_batch_tuning *tuning, size_t *work_bytes);
 /* Plan a batch over caller memory `work` (256-byte aligned, >= query).
  * tuning may be NULL.  use_graph != 0 records the launches once as a HIP
  * graph that gv_batch_run replays; between runs the caller may rewrite the

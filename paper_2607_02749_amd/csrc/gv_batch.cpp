@@ -11,8 +11,11 @@
 
 #include "gv_internal.hpp"
 
+constexpr int kSideStreams = 4;
+
 struct gv_batch_s {
     int count = 0;
+    int nsmall = 0;                 // instances in the persistent kernel's queue
     gv_precision prec = GV_C64;
     void *work = nullptr;
     size_t work_bytes = 0;
@@ -25,6 +28,15 @@ struct gv_batch_s {
     hipStream_t capture_stream = nullptr;
     hipGraph_t g = nullptr;
     hipGraphExec_t exec = nullptr;
+    // instances run as whole-GPU passes: their instance records, states (the
+    // batch's psi buffer of the instance and a work region of their own) and
+    // device gradient masks; side streams with fork / join events
+    std::vector<gv_instance> large;
+    std::vector<gv_state_s> states;
+    std::vector<uint8_t *> masks;
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSideStreams] = {};
 };
 
 namespace gv {
@@ -37,7 +49,14 @@ struct BatchLayout {
     size_t counter, insts, order, total;
     std::vector<size_t> offp, ry, dtab, gtab, g0tab, psi, lam;
     std::vector<size_t> stride;
+    std::vector<size_t> fwork, fwork_bytes, mask;   // whole-GPU instances (0 bytes otherwise)
 };
+
+int split_of(const gv_batch_tuning *tu)
+{
+    const int s = tu ? tu->split_n : 0;
+    return s <= 0 ? 17 : s;
+}
 
 gv_status check_instances(int count, const gv_instance *inst, gv_precision prec)
 {
@@ -71,7 +90,7 @@ gv_status check_instances(int count, const gv_instance *inst, gv_precision prec)
     return GV_OK;
 }
 
-BatchLayout batch_layout(int count, const gv_instance *inst, gv_precision prec)
+BatchLayout batch_layout(int count, const gv_instance *inst, gv_precision prec, int split)
 {
     BatchLayout L;
     const size_t s = amp_bytes(prec);
@@ -102,9 +121,56 @@ BatchLayout batch_layout(int count, const gv_instance *inst, gv_precision prec)
         off += align_up(((size_t)1 << a.n) * s);
         L.lam.push_back(off);
         off += align_up(((size_t)1 << a.n) * s);
+        size_t fw = 0, mk = 0;
+        if (a.n >= split) {
+            WorkLayout wl;
+            if (work_layout(a, prec, GV_ENGINE_FUSED, GV_GRAD_UNCOMPUTE, &wl) == GV_OK) fw = wl.total;
+            mk = (size_t)2 * a.n * R;
+        }
+        L.fwork.push_back(off);
+        L.fwork_bytes.push_back(fw);
+        off += align_up(fw);
+        L.mask.push_back(off);
+        off += align_up(mk + 8);
     }
     L.total = off;
     return L;
+}
+
+// One evaluation of every instance, enqueued on s: the persistent kernel
+// for the small instances on s, the whole-GPU instances round-robin on the
+// side streams between a fork and a join event (so a HIP-graph capture of s
+// records both branches).
+gv_status launch_all(gv_batch b, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    const bool fork = !b->large.empty();
+    if (fork) {
+        e = hipEventRecord(b->fork, s);
+        for (int k = 0; k < kSideStreams && e == hipSuccess; ++k)
+            e = hipStreamWaitEvent(b->side[k], b->fork, 0);
+        if (e != hipSuccess) return check_hip(e, "batch fork");
+    }
+    e = batch_tables(b->prec, b->dev_insts, b->count, s);
+    if (e == hipSuccess && b->nsmall > 0)
+        e = batch_run(b->prec, b->dev_insts, b->dev_order, b->nsmall, b->counter, b->grid, s);
+    if (e != hipSuccess) return check_hip(e, "batch launch");
+    for (size_t j = 0; j < b->large.size(); ++j) {
+        gv_state_s &st = b->states[j];
+        st.stream = b->side[j % kSideStreams];
+        const gv_instance &I = b->large[j];
+        if (gv_status r = gv_energy_grad(&st, I.h, I.params_dev, &I.ansatz, b->masks[j],
+                                         GV_GRAD_UNCOMPUTE, I.energy_dev, I.grad_dev))
+            return r;
+    }
+    if (fork) {
+        for (int k = 0; k < kSideStreams && e == hipSuccess; ++k) {
+            e = hipEventRecord(b->join[k], b->side[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join[k], 0);
+        }
+        if (e != hipSuccess) return check_hip(e, "batch join");
+    }
+    return GV_OK;
 }
 
 }  // namespace
@@ -115,11 +181,11 @@ using namespace gv;
 extern "C" {
 
 gv_status gv_batch_query(int32_t count, const gv_instance *inst, gv_precision prec,
-                         size_t *work_bytes)
+                         const gv_batch_tuning *tuning, size_t *work_bytes)
 {
     if (!work_bytes) return set_error(GV_EINVAL, "work_bytes is NULL");
     if (gv_status r = check_instances(count, inst, prec)) return r;
-    *work_bytes = batch_layout(count, inst, prec).total;
+    *work_bytes = batch_layout(count, inst, prec, split_of(tuning)).total;
     return GV_OK;
 }
 
@@ -130,13 +196,15 @@ gv_status gv_batch_create(int32_t count, const gv_instance *inst, gv_precision p
     if (!out) return set_error(GV_EINVAL, "out is NULL");
     if (gv_status r = check_instances(count, inst, prec)) return r;
     if (!work || ((uintptr_t)work % kAlign)) return set_error(GV_EINVAL, "work must be 256-byte aligned");
-    const BatchLayout L = batch_layout(count, inst, prec);
+    gv_batch_tuning tu = {2, 0, 0};
+    if (tuning) tu = *tuning;
+    if (tu.blocks_per_cu < 1 || tu.blocks_per_cu > 8 || tu.order < 0 || tu.order > 1 ||
+        tu.split_n < 0)
+        return set_error(GV_EINVAL, "tuning out of range");
+    const int split = split_of(&tu);
+    const BatchLayout L = batch_layout(count, inst, prec, split);
     if (work_bytes < L.total)
         return set_error(GV_ESIZE, "work buffer %zu bytes < %zu needed", work_bytes, L.total);
-    gv_batch_tuning tu = {2, 0};
-    if (tuning) tu = *tuning;
-    if (tu.blocks_per_cu < 1 || tu.blocks_per_cu > 8 || tu.order < 0 || tu.order > 1)
-        return set_error(GV_EINVAL, "tuning out of range");
 
     char *w = (char *)work;
     const int C = std::min(kBatchK - 1, prec == GV_C64 ? 4 : 3);
@@ -195,10 +263,12 @@ gv_status gv_batch_create(int32_t count, const gv_instance *inst, gv_precision p
         }
         cost[i] = (double)(1ull << a.n) * (double)(b.rot * b.np * 3 + b.noff);
     }
-    std::vector<int> order(count);
-    std::iota(order.begin(), order.end(), 0);
-    if (tu.order == 0)
+    std::vector<int> order, large;
+    for (int i = 0; i < count; ++i) (inst[i].ansatz.n >= split ? large : order).push_back(i);
+    if (tu.order == 0) {
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+        std::stable_sort(large.begin(), large.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    }
 
     gv_batch b = new (std::nothrow) gv_batch_s;
     if (!b) return set_error(GV_EINVAL, "out of host memory");
@@ -210,16 +280,44 @@ gv_status gv_batch_create(int32_t count, const gv_instance *inst, gv_precision p
     b->dev_insts = (BatchInst *)(w + L.insts);
     b->dev_order = (int *)(w + L.order);
     b->counter = (unsigned *)(w + L.counter);
+    b->nsmall = (int)order.size();
     int cus = 0, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
-    b->grid = std::max(1, std::min(count, tu.blocks_per_cu * cus));
+    b->grid = std::max(1, std::min(b->nsmall, tu.blocks_per_cu * cus));
 
     hipError_t e = hipSuccess;
-    if (count > 0) {
+    for (int i : large) {
+        const gv_instance &I = inst[i];
+        const gv_ansatz &a = I.ansatz;
+        const int64_t P = 2ll * a.n * (a.layers + a.final_rotation);
+        std::vector<uint8_t> m((size_t)P);
+        for (int64_t p = 0; p < P; ++p) m[(size_t)p] = (uint8_t)((I.qubit_mask >> (p % a.n)) & 1);
+        uint8_t *dm = (uint8_t *)(w + L.mask[i]);
+        if (e == hipSuccess) e = hipMemcpy(dm, m.data(), m.size(), hipMemcpyHostToDevice);
+        gv_state_s st;
+        st.n = a.n;
+        st.prec = prec;
+        st.engine = GV_ENGINE_FUSED;
+        st.amps = w + L.psi[i];
+        st.amps_bytes = ((size_t)1 << a.n) * amp_bytes(prec);
+        st.work = w + L.fwork[i];
+        st.work_bytes = L.fwork_bytes[i];
+        b->large.push_back(I);
+        b->states.push_back(st);
+        b->masks.push_back(dm);
+    }
+    if (!large.empty()) {
+        for (int k = 0; k < kSideStreams && e == hipSuccess; ++k) {
+            e = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming);
+        }
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    }
+    if (e == hipSuccess && count > 0) {
         e = hipMemcpy(b->dev_insts, hi.data(), hi.size() * sizeof(BatchInst), hipMemcpyHostToDevice);
-        if (e == hipSuccess)
+        if (e == hipSuccess && !order.empty())
             e = hipMemcpy(b->dev_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice);
         for (int i = 0; i < count && e == hipSuccess; ++i)
             if (!offp[i].empty())
@@ -230,12 +328,12 @@ gv_status gv_batch_create(int32_t count, const gv_instance *inst, gv_precision p
         e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t e1 = batch_tables(prec, b->dev_insts, count, b->capture_stream);
-            hipError_t e2 = e1 == hipSuccess ? batch_run(prec, b->dev_insts, b->dev_order, count,
-                                                         b->counter, b->grid, b->capture_stream)
-                                             : e1;
+            const gv_status r = launch_all(b, b->capture_stream);
             e = hipStreamEndCapture(b->capture_stream, &b->g);
-            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess && r != GV_OK) {
+                gv_batch_destroy(b);
+                return r;
+            }
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->g, nullptr, nullptr, 0);
         b->graph = e == hipSuccess;
@@ -252,10 +350,7 @@ gv_status gv_batch_run(gv_batch b)
 {
     if (!b) return set_error(GV_EINVAL, "batch is NULL");
     if (b->graph) return check_hip(hipGraphLaunch(b->exec, b->stream), "graph launch");
-    hipError_t e = batch_tables(b->prec, b->dev_insts, b->count, b->stream);
-    if (e == hipSuccess)
-        e = batch_run(b->prec, b->dev_insts, b->dev_order, b->count, b->counter, b->grid, b->stream);
-    return check_hip(e, "batch launch");
+    return launch_all(b, b->stream);
 }
 
 gv_status gv_batch_destroy(gv_batch b)
@@ -264,6 +359,11 @@ gv_status gv_batch_destroy(gv_batch b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->g) (void)hipGraphDestroy(b->g);
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    for (int k = 0; k < kSideStreams; ++k) {
+        if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
+        if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     delete b;
     return GV_OK;
 }

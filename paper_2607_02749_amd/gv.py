@@ -49,7 +49,8 @@ class _Instance(ctypes.Structure):
 
 
 class _Tuning(ctypes.Structure):
-    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("order", ctypes.c_int32)]
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("split_n", ctypes.c_int32)]
 
 
 _lib = None
@@ -84,7 +85,7 @@ def lib():
     L.gv_energy_grad.argtypes = [vp, vp, vp, AP, vp, i32, vp, vp]
     L.gv_pauli_sum_prepare_for.argtypes = [vp, i32, i32, vp, vp, sz]
     IP = ctypes.POINTER(_Instance)
-    L.gv_batch_query.argtypes = [i32, IP, i32, ctypes.POINTER(sz)]
+    L.gv_batch_query.argtypes = [i32, IP, i32, ctypes.POINTER(_Tuning), ctypes.POINTER(sz)]
     L.gv_batch_create.argtypes = [i32, IP, i32, ctypes.POINTER(_Tuning), vp, sz, vp, i32,
                                   ctypes.POINTER(vp)]
     L.gv_batch_run.argtypes = [vp]
@@ -348,10 +349,12 @@ class Batch:
     qubit_mask).  Each PauliSum is prepared here for the batch precision.
     After run(), energies[i] holds (re, im) and grads[i] the gradient of
     item i (0 outside its qubit block).  Rewriting the theta tensors in place
-    and calling run() again evaluates the new angles."""
+    and calling run() again evaluates the new angles.  Instances with
+    n >= split_n run as whole-GPU tile passes beside the persistent kernel
+    (None: the library default)."""
 
     def __init__(self, items, precision="c64", blocks_per_cu=None, order=None, graph=True,
-                 device="cuda"):
+                 device="cuda", split_n=None):
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
@@ -379,12 +382,16 @@ class Batch:
             arr[i].energy_dev = self.energy_buf[i].data_ptr()
             arr[i].grad_dev = g.data_ptr()
         self._arr = arr
-        wb = ctypes.c_size_t()
-        _check(lib().gv_batch_query(count, arr, self.precision, ctypes.byref(wb)), "gv_batch_query")
-        self._work_owner, self.work = _aligned_bytes(wb.value, dev)
         tu = None
-        if blocks_per_cu is not None or order is not None:
-            tu = _Tuning(2 if blocks_per_cu is None else blocks_per_cu, 0 if order is None else order)
+        if blocks_per_cu is not None or order is not None or split_n is not None:
+            tu = _Tuning(2 if blocks_per_cu is None else blocks_per_cu, 0 if order is None else order,
+                         0 if split_n is None else split_n)
+        self.tuning = tu
+        wb = ctypes.c_size_t()
+        _check(lib().gv_batch_query(count, arr, self.precision,
+                                    None if tu is None else ctypes.byref(tu), ctypes.byref(wb)),
+               "gv_batch_query")
+        self._work_owner, self.work = _aligned_bytes(wb.value, dev)
         b = ctypes.c_void_p()
         _check(lib().gv_batch_create(count, arr, self.precision,
                                      None if tu is None else ctypes.byref(tu), _ptr(self.work),

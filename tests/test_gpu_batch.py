@@ -30,10 +30,12 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("precision", ["c64", "c128"])
-def test_batch_matches_oracle(precision):
+@pytest.mark.parametrize("split_n", [None, 13])
+def test_batch_matches_oracle(precision, split_n):
+    # split_n = 13: every instance with n >= 13 runs as whole-GPU tile passes
     insts = synth.workload_batch(count=10, seed=3, n_lo=12, n_hi=15)
     items = make_items(insts)
-    b = gv.Batch(items, precision, graph=False)
+    b = gv.Batch(items, precision, graph=False, split_n=split_n)
     b.run()
     torch.cuda.synchronize()
     te, tg = TOL[precision]
@@ -69,11 +71,12 @@ def test_full_batch_matches_single_instance_runs():
         assert rel(b.grads[i].cpu().numpy(), g.cpu().numpy()) <= 1e-5
 
 
-def test_graph_replays_follow_new_angles():
+@pytest.mark.parametrize("split_n", [None, 13])
+def test_graph_replays_follow_new_angles(split_n):
     insts = synth.workload_batch(count=16, seed=5, n_lo=12, n_hi=14)
     items = make_items(insts)
-    g_batch = gv.Batch(items, "c64", graph=True)
-    eager = gv.Batch(make_items(insts), "c64", graph=False)
+    g_batch = gv.Batch(items, "c64", graph=True, split_n=split_n)
+    eager = gv.Batch(make_items(insts), "c64", graph=False, split_n=split_n)
     rng = np.random.default_rng(9)
     for rep in range(3):
         for (an, th, _, _), (_, th2, _, _) in zip(items, eager.items):
@@ -95,12 +98,14 @@ def test_autotuned_batch_matches_default(tmp_path):
     insts = synth.workload_batch(count=24, seed=11, n_lo=12, n_hi=16)
     items = make_items(insts)
     path = str(tmp_path / "tune.json")
-    r = autotune.tune_batch(items, "c64", blocks=(1, 2), orders=(0, 1), reps=2, path=path)
+    r = autotune.tune_batch(items, "c64", blocks=(1, 2), orders=(0, 1), splits=(31,), reps=2,
+                            path=path)
     assert not r["cached"] and len(r["timings"]) == 4
-    r2 = autotune.tune_batch(items, "c64", blocks=(1, 2), orders=(0, 1), path=path)
+    r2 = autotune.tune_batch(items, "c64", blocks=(1, 2), orders=(0, 1), splits=(31,), path=path)
     assert r2["cached"] and (r2["blocks_per_cu"], r2["order"]) == (r["blocks_per_cu"], r["order"])
-    tuned = gv.Batch(items, "c64", blocks_per_cu=r["blocks_per_cu"], order=r["order"])
-    ref = gv.Batch(make_items(insts), "c64")
+    tuned = gv.Batch(items, "c64", blocks_per_cu=r["blocks_per_cu"], order=r["order"],
+                     split_n=r["split_n"])
+    ref = gv.Batch(make_items(insts), "c64", split_n=31)
     tuned.run()
     ref.run()
     torch.cuda.synchronize()
