@@ -362,6 +362,7 @@ def bench_batch(args, torch, gv, synth):
                    "n_range": [min(x.n for x in insts), max(x.n for x in insts)],
                    "graph": True,
                    "tuning": {k: tune[k] for k in ("blocks_per_cu", "order", "split_n")},
+                   "tuning_sweep_ms": tune.get("timings"),
                    "event_ms_per_step": ms},
         "roofline": {"bound": "hbm", "kernel": "k_batch<float>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -75,8 +75,9 @@ typedef enum {
 /* How the reverse sweep recovers the forward states at large n. */
 typedef enum {
     GV_GRAD_UNCOMPUTE = 0,    /* undo gates on the final state; no extra memory */
-    GV_GRAD_CHECKPOINT = 1,   /* store the state at the layers-1 inner layer boundaries */
-    GV_GRAD_RECOMPUTE = 2,    /* re-run the forward from |0> to each layer boundary */
+    GV_GRAD_CHECKPOINT = 1,   /* store the state at the layers-2 inner layer boundaries
+                                 (the first layer is regenerated) */
+    GV_GRAD_RECOMPUTE = 2,    /* re-run the forward from |0> to each of those boundaries */
     GV_GRAD_STORE = 3         /* keep the state after every fused tile pass (each pass
                                  writes its own buffer); the reverse sweep reads them back
                                  and writes only lambda.  Most memory, least traffic.
@@ -175,7 +176,8 @@ gv_status gv_energy(gv_state st, gv_pauli_sum h, double *energy_dev);
  *                  entries of grad_dev are written as 0;
  *   mode: how forward states are recovered in the reverse sweep;
  *   energy_dev: 2 device doubles (re, im); grad_dev: P device doubles.
- * Leaves psi(theta) in the state's amplitude buffer. */
+ * The reverse sweep uses the state's amplitude buffer as scratch: afterwards
+ * it does not hold psi(theta) (gv_apply_ansatz recomputes it). */
 gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *params_dev,
                          const gv_ansatz *ansatz, const uint8_t *grad_mask_dev,
                          gv_grad_mode mode, double *energy_dev, double *grad_dev);

@@ -22,7 +22,7 @@ from typing import Callable, Dict, Iterable, List, Optional, Sequence, Tuple
 
 ORDERS = {"largest_first": 0, "input": 1}
 DEFAULT_BLOCKS = (1, 2, 4, 8)
-DEFAULT_SPLITS = (15, 17, 31)   # 31: never split
+DEFAULT_SPLITS = (15, 16, 17, 18, 31)   # 31: never split
 
 
 def cache_path() -> str:

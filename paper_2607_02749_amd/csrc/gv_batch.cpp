@@ -11,7 +11,7 @@
 
 #include "gv_internal.hpp"
 
-constexpr int kSideStreams = 4;
+constexpr int kSideStreams = 8;
 
 struct gv_batch_s {
     int count = 0;

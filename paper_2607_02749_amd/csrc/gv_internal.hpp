@@ -193,10 +193,10 @@ Chunks make_chunks(int n, int K, int LOGR);
 // Work-buffer layout for gv_energy_grad / gv_energy.
 struct WorkLayout {
     size_t lam = 0;          // adjoint vector
-    size_t ckpt = 0;         // checkpoints, (rot_layers-1) vectors (CHECKPOINT)
+    size_t ckpt = 0;         // stored states: L-2 boundaries (CHECKPOINT) or pass outputs (STORE)
     size_t scratch = 0;      // one vector (CNOT gather)
-    size_t ry_tab = 0;       // per parameter: forward and backward (cos, sin) doubles
-    size_t dtab = 0;         // per rotation layer: forward + backward diagonal tables
+    size_t ry_tab = 0;       // per parameter: (cos, sin) of the half angle, amplitude precision
+    size_t dtab = 0;         // per rotation layer: diagonal tables in pass 0's load layout
     size_t gtab = 0;         // first-layer tables D_0 R_0|0..0>
     size_t g0tab = 0;        // first-layer tables R_0|0..0>
     size_t part = 0;         // gradient partials: P rows x grid columns
