@@ -203,6 +203,9 @@ gv_status work_layout(const gv_ansatz &a, gv_precision prec, gv_engine eng, gv_g
         if (!make_tile_plan(a.n, choose_K(a.n), choose_C(prec, choose_K(a.n)), &plan))
             return set_error(GV_EUNSUPPORTED, "no tile plan for n=%d", a.n);
         w.grid = fused_grid(prec, plan, a.n);
+        // the energy partials (2 x kEnergyGrid) also take one column per block
+        if (w.grid > kEnergyGrid)
+            return set_error(GV_EUNSUPPORTED, "grid %d exceeds the energy partials", w.grid);
         const int K = choose_K(a.n);
         const Chunks ch = make_chunks(a.n, K, choose_logr(K));
         w.dtab_stride = align_up((size_t)ch.off[4] * s);
