@@ -126,7 +126,8 @@ Chunks make_chunks(int n, int K, int LOGR)
     return c;
 }
 
-static const int kEnergyGrid = 1024;
+static const int kEnergyGrid = 1024;  // blocks of the stand-alone energy kernels
+static const int kPartCols = 4096;    // energy-partial columns the work buffer holds
 
 static int choose_K(int n) { return n >= 12 ? 12 : (n >= 10 ? 10 : 8); }
 static int choose_logr(int K) { return K == 8 ? 3 : 4; }
@@ -197,14 +198,14 @@ gv_status work_layout(const gv_ansatz &a, gv_precision prec, gv_engine eng, gv_g
     const int R = rot_layers(a);
     size_t off = 0;
     w.epart = off;
-    off += align_up(2 * kEnergyGrid * sizeof(double));
+    off += align_up(2 * kPartCols * sizeof(double));
     if (fused_ok(eng, a.n)) {
         TilePlan plan;
         if (!make_tile_plan(a.n, choose_K(a.n), choose_C(prec, choose_K(a.n)), &plan))
             return set_error(GV_EUNSUPPORTED, "no tile plan for n=%d", a.n);
         w.grid = fused_grid(prec, plan, a.n);
-        // the energy partials (2 x kEnergyGrid) also take one column per block
-        if (w.grid > kEnergyGrid)
+        // the energy partials (2 x kPartCols) also take one column per block
+        if (w.grid > kPartCols)
             return set_error(GV_EUNSUPPORTED, "grid %d exceeds the energy partials", w.grid);
         const int K = choose_K(a.n);
         const Chunks ch = make_chunks(a.n, K, choose_logr(K));

@@ -61,8 +61,8 @@ struct FusedArgs {
     int diag_phi, diag_lam;  // reverse, pass 0: times conj(dt) on load
     int phi_gen;             // reverse, pass 0: phi from gt instead of a load
     int store_phi, store_lam;
-    int nruns;               // tile id -> outside bits, as runs of contiguous bits
-    int8_t run_src[kMaxTileBits + 1], run_w[kMaxTileBits + 1], run_dst[kMaxTileBits + 1];
+    int nruns;               // tile id -> outside bits, as runs of contiguous bits:
+    uint32_t run[kMaxTileBits + 1];  // source bit | width << 8 | destination bit << 16
     u64 ntiles;
     const void *ry;          // [P] (cos, sin) of half angles, amplitude precision
     DiagTab dt;              // layer diagonal (or the first layer's generator in forward)
@@ -114,9 +114,12 @@ struct Tile {
 template <typename Args>
 __device__ __forceinline__ u64 tile_base(u64 tile, const Args &a)
 {
+    // one word per run keeps the loop on scalar loads
     u64 b = 0;
-    for (int i = 0; i < a.nruns; ++i)
-        b |= ((tile >> a.run_src[i]) & ((1ull << a.run_w[i]) - 1)) << a.run_dst[i];
+    for (int i = 0; i < a.nruns; ++i) {
+        const uint32_t r = a.run[i];
+        b |= ((tile >> (r & 255u)) & ((1ull << ((r >> 8) & 255u)) - 1)) << (r >> 16);
+    }
     return b;
 }
 
@@ -163,6 +166,15 @@ struct RegMap {
         }
     }
 };
+
+// A tile's element offset, recomputed where the tile is stored: the empty
+// asm hides that it equals the load offset, so the compiler does not keep
+// one 64-bit address per register live across the whole tile.
+__device__ __forceinline__ u64 fresh(u64 o)
+{
+    asm volatile("" : "+v"(o));
+    return o;
+}
 
 template <typename R>
 __device__ __forceinline__ cx<R> cneg(cx<R> v)
@@ -290,9 +302,32 @@ __device__ __forceinline__ void rot_pair(cx<R> &x, cx<R> &y, R c, R sn)
     y.im = sn * a.im + c * b.im;
 }
 
+// (cos, sin) of the half angles of one rotation layer's RY gates on the K
+// tile qubits, read once per block: inside the tile loop each gate would
+// otherwise wait for its own load.  Only the pass's active qubits are read
+// (the gates the assignments apply); the others hold the identity.
+template <typename R, int K>
+struct RyC {
+    R c[K], s[K];
+    __device__ __forceinline__ RyC(const FusedArgs &a, int layer)
+    {
+        const cx<R> *ry = (const cx<R> *)a.ry + (int64_t)layer * a.nparam_layer;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            c[j] = R(1);
+            s[j] = R(0);
+            if ((a.active >> j) & 1) {
+                const cx<R> e = ry[a.pos[j]];
+                c[j] = e.re;
+                s[j] = e.im;
+            }
+        }
+    }
+};
+
 // forward rotations of the tile bits that are new in assignment AI
 template <typename R, int K, int LOGR, int AI>
-__device__ __forceinline__ void fwd_assign(cx<R> (&v)[1 << LOGR], const FusedArgs &a, int layer)
+__device__ __forceinline__ void fwd_assign(cx<R> (&v)[1 << LOGR], const FusedArgs &a, const RyC<R, K> &rc)
 {
     using T = Tile<K, LOGR>;
     constexpr int LO = T::lo(AI);
@@ -301,8 +336,7 @@ __device__ __forceinline__ void fwd_assign(cx<R> (&v)[1 << LOGR], const FusedArg
     for (int k = 0; k < LOGR; ++k) {
         const int j = LO + k;
         if (!((NEW >> j) & 1) || !((a.active >> j) & 1)) continue;
-        const cx<R> e = ((const cx<R> *)a.ry)[(int64_t)layer * a.nparam_layer + a.pos[j]];
-        const R c = e.re, sn = e.im;
+        const R c = rc.c[j], sn = rc.s[j];
 #pragma unroll
         for (int r = 0; r < T::NR; ++r)
             if (!(r & (1 << k))) rot_pair(v[r], v[r | (1 << k)], c, sn);
@@ -314,7 +348,7 @@ __device__ __forceinline__ void fwd_assign(cx<R> (&v)[1 << LOGR], const FusedArg
 // then RY(-theta) on both vectors
 template <typename R, int K, int LOGR, int AI>
 __device__ __forceinline__ void bwd_assign(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
-                                           double (&accY)[K], const FusedArgs &a, int layer)
+                                           double (&accY)[K], const FusedArgs &a, const RyC<R, K> &rc)
 {
     using T = Tile<K, LOGR>;
     constexpr int LO = T::lo(AI);
@@ -323,8 +357,7 @@ __device__ __forceinline__ void bwd_assign(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 <
     for (int k = 0; k < LOGR; ++k) {
         const int j = LO + k;
         if (!((NEW >> j) & 1) || !((a.active >> j) & 1)) continue;
-        const cx<R> e = ((const cx<R> *)a.ry)[(int64_t)layer * a.nparam_layer + a.pos[j]];
-        const R c = e.re, sn = -e.im;
+        const R c = rc.c[j], sn = -rc.s[j];
         R g = 0;
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
@@ -364,7 +397,7 @@ __device__ __forceinline__ void ygrad_assign(const cx<R> (&f)[1 << LOGR], const 
 
 // RY(-theta) of the tile bits new in assignment AI on one vector
 template <typename R, int K, int LOGR, int AI>
-__device__ __forceinline__ void inv_assign(cx<R> (&v)[1 << LOGR], const FusedArgs &a, int layer)
+__device__ __forceinline__ void inv_assign(cx<R> (&v)[1 << LOGR], const FusedArgs &a, const RyC<R, K> &rc)
 {
     using T = Tile<K, LOGR>;
     constexpr int LO = T::lo(AI);
@@ -373,8 +406,7 @@ __device__ __forceinline__ void inv_assign(cx<R> (&v)[1 << LOGR], const FusedArg
     for (int k = 0; k < LOGR; ++k) {
         const int j = LO + k;
         if (!((NEW >> j) & 1) || !((a.active >> j) & 1)) continue;
-        const cx<R> e = ((const cx<R> *)a.ry)[(int64_t)layer * a.nparam_layer + a.pos[j]];
-        const R c = e.re, sn = -e.im;
+        const R c = rc.c[j], sn = -rc.s[j];
 #pragma unroll
         for (int r = 0; r < T::NR; ++r)
             if (!(r & (1 << k))) rot_pair(v[r], v[r | (1 << k)], c, sn);
@@ -401,121 +433,144 @@ __device__ __forceinline__ void exchange(cx<R> (&v)[1 << LOGR], cx<R> *lds, int 
     }
 }
 
-template <typename R, int K, int LOGR, int AI>
+// The chains below run assignments one after the other, each after an
+// exchange into its layout.  SKIP marks assignments in the middle of a chain
+// whose tile bits hold no active gate (in every pass after the first, the
+// kept low bits): they are skipped, the data going straight from the layout
+// it is in (LF) to the next assignment's.  The first and last layouts never
+// change.
+
+template <typename R, int K, int LOGR, int AI, int SKIP, int LF = Tile<K, LOGR>::lo(AI - 1)>
 struct FwdChain {
     __device__ static __forceinline__ void run(cx<R> (&v)[1 << LOGR], cx<R> *lds, int t,
-                                               const FusedArgs &a, int layer)
+                                               const FusedArgs &a, const RyC<R, K> &rc)
     {
         using T = Tile<K, LOGR>;
-        exchange<R, K, LOGR, T::lo(AI - 1), T::lo(AI)>(v, lds, t);
-        fwd_assign<R, K, LOGR, AI>(v, a, layer);
-        if constexpr (AI + 1 < T::NA) FwdChain<R, K, LOGR, AI + 1>::run(v, lds, t, a, layer);
+        if constexpr ((AI + 1 < T::NA) && ((SKIP >> AI) & 1))
+            return FwdChain<R, K, LOGR, AI + 1, SKIP, LF>::run(v, lds, t, a, rc);
+        exchange<R, K, LOGR, LF, T::lo(AI)>(v, lds, t);
+        fwd_assign<R, K, LOGR, AI>(v, a, rc);
+        if constexpr (AI + 1 < T::NA) FwdChain<R, K, LOGR, AI + 1, SKIP>::run(v, lds, t, a, rc);
     }
 };
 
 // forward assignments in the order AI, AI-1, ..., 0 (each after an exchange
 // from AI+1): the second layer of a two-layer pass
-template <typename R, int K, int LOGR, int AI>
+template <typename R, int K, int LOGR, int AI, int SKIP, int LF = Tile<K, LOGR>::lo(AI + 1)>
 struct FwdChainRev {
     __device__ static __forceinline__ void run(cx<R> (&v)[1 << LOGR], cx<R> *lds, int t,
-                                               const FusedArgs &a, int layer)
+                                               const FusedArgs &a, const RyC<R, K> &rc)
     {
         using T = Tile<K, LOGR>;
-        exchange<R, K, LOGR, T::lo(AI + 1), T::lo(AI)>(v, lds, t);
-        fwd_assign<R, K, LOGR, AI>(v, a, layer);
-        if constexpr (AI > 0) FwdChainRev<R, K, LOGR, AI - 1>::run(v, lds, t, a, layer);
+        if constexpr ((AI > 0) && ((SKIP >> AI) & 1))
+            return FwdChainRev<R, K, LOGR, AI - 1, SKIP, LF>::run(v, lds, t, a, rc);
+        exchange<R, K, LOGR, LF, T::lo(AI)>(v, lds, t);
+        fwd_assign<R, K, LOGR, AI>(v, a, rc);
+        if constexpr (AI > 0) FwdChainRev<R, K, LOGR, AI - 1, SKIP>::run(v, lds, t, a, rc);
     }
 };
 
 // reverse assignments AI = 1 .. NA-1, each after an exchange from AI-1
-template <typename R, int K, int LOGR, int AI>
+template <typename R, int K, int LOGR, int AI, int SKIP, int LF = Tile<K, LOGR>::lo(AI - 1)>
 struct BwdChain {
     __device__ static __forceinline__ void run(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
                                                double (&accY)[K], cx<R> *lds, int t,
-                                               const FusedArgs &a, int layer)
+                                               const FusedArgs &a, const RyC<R, K> &rc)
     {
         using T = Tile<K, LOGR>;
-        exchange<R, K, LOGR, T::lo(AI - 1), T::lo(AI)>(f, lds, t);
-        exchange<R, K, LOGR, T::lo(AI - 1), T::lo(AI)>(l, lds, t);
-        bwd_assign<R, K, LOGR, AI>(f, l, accY, a, layer);
+        if constexpr ((AI + 1 < T::NA) && ((SKIP >> AI) & 1))
+            return BwdChain<R, K, LOGR, AI + 1, SKIP, LF>::run(f, l, accY, lds, t, a, rc);
+        exchange<R, K, LOGR, LF, T::lo(AI)>(f, lds, t);
+        exchange<R, K, LOGR, LF, T::lo(AI)>(l, lds, t);
+        bwd_assign<R, K, LOGR, AI>(f, l, accY, a, rc);
         if constexpr (AI + 1 < T::NA)
-            BwdChain<R, K, LOGR, AI + 1>::run(f, l, accY, lds, t, a, layer);
+            BwdChain<R, K, LOGR, AI + 1, SKIP>::run(f, l, accY, lds, t, a, rc);
     }
 };
 
 // reverse assignments in the order AI, AI-1, ..., 0 (each after an exchange
 // from AI+1), used where the data ends a forward or reverse part in the last
 // assignment
-template <typename R, int K, int LOGR, int AI>
+template <typename R, int K, int LOGR, int AI, int SKIP, int LF = Tile<K, LOGR>::lo(AI + 1)>
 struct BwdChainRev {
     __device__ static __forceinline__ void run(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
                                                double (&accY)[K], cx<R> *lds, int t,
-                                               const FusedArgs &a, int layer)
+                                               const FusedArgs &a, const RyC<R, K> &rc)
     {
         using T = Tile<K, LOGR>;
-        exchange<R, K, LOGR, T::lo(AI + 1), T::lo(AI)>(f, lds, t);
-        exchange<R, K, LOGR, T::lo(AI + 1), T::lo(AI)>(l, lds, t);
-        bwd_assign<R, K, LOGR, AI>(f, l, accY, a, layer);
-        if constexpr (AI > 0) BwdChainRev<R, K, LOGR, AI - 1>::run(f, l, accY, lds, t, a, layer);
+        if constexpr ((AI > 0) && ((SKIP >> AI) & 1))
+            return BwdChainRev<R, K, LOGR, AI - 1, SKIP, LF>::run(f, l, accY, lds, t, a, rc);
+        exchange<R, K, LOGR, LF, T::lo(AI)>(f, lds, t);
+        exchange<R, K, LOGR, LF, T::lo(AI)>(l, lds, t);
+        bwd_assign<R, K, LOGR, AI>(f, l, accY, a, rc);
+        if constexpr (AI > 0) BwdChainRev<R, K, LOGR, AI - 1, SKIP>::run(f, l, accY, lds, t, a, rc);
     }
 };
 
 // partials of assignments AI .. NA-1, each after an exchange of both vectors
-template <typename R, int K, int LOGR, int AI>
+template <typename R, int K, int LOGR, int AI, int SKIP, int LF = Tile<K, LOGR>::lo(AI - 1)>
 struct GradChain {
     __device__ static __forceinline__ void run(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
                                                double (&accY)[K], cx<R> *lds, int t,
                                                const FusedArgs &a)
     {
         using T = Tile<K, LOGR>;
-        exchange<R, K, LOGR, T::lo(AI - 1), T::lo(AI)>(f, lds, t);
-        exchange<R, K, LOGR, T::lo(AI - 1), T::lo(AI)>(l, lds, t);
+        if constexpr ((AI + 1 < T::NA) && ((SKIP >> AI) & 1))
+            return GradChain<R, K, LOGR, AI + 1, SKIP, LF>::run(f, l, accY, lds, t, a);
+        exchange<R, K, LOGR, LF, T::lo(AI)>(f, lds, t);
+        exchange<R, K, LOGR, LF, T::lo(AI)>(l, lds, t);
         ygrad_assign<R, K, LOGR, AI>(f, l, accY, a);
-        if constexpr (AI + 1 < T::NA) GradChain<R, K, LOGR, AI + 1>::run(f, l, accY, lds, t, a);
+        if constexpr (AI + 1 < T::NA) GradChain<R, K, LOGR, AI + 1, SKIP>::run(f, l, accY, lds, t, a);
     }
 };
 
 // RY(-theta) of assignments AI, AI-1, .., 0 on one vector, each after an
 // exchange from AI+1
-template <typename R, int K, int LOGR, int AI>
+template <typename R, int K, int LOGR, int AI, int SKIP, int LF = Tile<K, LOGR>::lo(AI + 1)>
 struct InvChainRev {
     __device__ static __forceinline__ void run(cx<R> (&v)[1 << LOGR], cx<R> *lds, int t,
-                                               const FusedArgs &a, int layer)
+                                               const FusedArgs &a, const RyC<R, K> &rc)
     {
         using T = Tile<K, LOGR>;
-        exchange<R, K, LOGR, T::lo(AI + 1), T::lo(AI)>(v, lds, t);
-        inv_assign<R, K, LOGR, AI>(v, a, layer);
-        if constexpr (AI > 0) InvChainRev<R, K, LOGR, AI - 1>::run(v, lds, t, a, layer);
+        if constexpr ((AI > 0) && ((SKIP >> AI) & 1))
+            return InvChainRev<R, K, LOGR, AI - 1, SKIP, LF>::run(v, lds, t, a, rc);
+        exchange<R, K, LOGR, LF, T::lo(AI)>(v, lds, t);
+        inv_assign<R, K, LOGR, AI>(v, a, rc);
+        if constexpr (AI > 0) InvChainRev<R, K, LOGR, AI - 1, SKIP>::run(v, lds, t, a, rc);
     }
 };
 
 // partials of assignments AI, AI-1, .., 0, each after an exchange of both
 // vectors from AI+1
-template <typename R, int K, int LOGR, int AI>
+template <typename R, int K, int LOGR, int AI, int SKIP, int LF = Tile<K, LOGR>::lo(AI + 1)>
 struct GradChainRev {
     __device__ static __forceinline__ void run(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
                                                double (&accY)[K], cx<R> *lds, int t,
                                                const FusedArgs &a)
     {
         using T = Tile<K, LOGR>;
-        exchange<R, K, LOGR, T::lo(AI + 1), T::lo(AI)>(f, lds, t);
-        exchange<R, K, LOGR, T::lo(AI + 1), T::lo(AI)>(l, lds, t);
+        if constexpr ((AI > 0) && ((SKIP >> AI) & 1))
+            return GradChainRev<R, K, LOGR, AI - 1, SKIP, LF>::run(f, l, accY, lds, t, a);
+        exchange<R, K, LOGR, LF, T::lo(AI)>(f, lds, t);
+        exchange<R, K, LOGR, LF, T::lo(AI)>(l, lds, t);
         ygrad_assign<R, K, LOGR, AI>(f, l, accY, a);
-        if constexpr (AI > 0) GradChainRev<R, K, LOGR, AI - 1>::run(f, l, accY, lds, t, a);
+        if constexpr (AI > 0) GradChainRev<R, K, LOGR, AI - 1, SKIP>::run(f, l, accY, lds, t, a);
     }
 };
 
 // RY(-theta) of assignments AI .. NA-1 on one vector, each after an exchange
 // from AI-1
-template <typename R, int K, int LOGR, int AI>
+template <typename R, int K, int LOGR, int AI, int SKIP, int LF = Tile<K, LOGR>::lo(AI - 1)>
 struct InvChain {
     __device__ static __forceinline__ void run(cx<R> (&v)[1 << LOGR], cx<R> *lds, int t,
-                                               const FusedArgs &a, int layer)
+                                               const FusedArgs &a, const RyC<R, K> &rc)
     {
         using T = Tile<K, LOGR>;
-        exchange<R, K, LOGR, T::lo(AI - 1), T::lo(AI)>(v, lds, t);
-        inv_assign<R, K, LOGR, AI>(v, a, layer);
-        if constexpr (AI + 1 < T::NA) InvChain<R, K, LOGR, AI + 1>::run(v, lds, t, a, layer);
+        if constexpr ((AI + 1 < T::NA) && ((SKIP >> AI) & 1))
+            return InvChain<R, K, LOGR, AI + 1, SKIP, LF>::run(v, lds, t, a, rc);
+        exchange<R, K, LOGR, LF, T::lo(AI)>(v, lds, t);
+        inv_assign<R, K, LOGR, AI>(v, a, rc);
+        if constexpr (AI + 1 < T::NA) InvChain<R, K, LOGR, AI + 1, SKIP>::run(v, lds, t, a, rc);
     }
 };
 
@@ -530,9 +585,10 @@ __device__ __forceinline__ void load_tile(cx<R> (&v)[1 << LOGR], const cx<R> *sr
                                           P0Diag<R, K, LOGR> &pd, const DiagTab &d, int t)
 {
     constexpr int NR = 1 << LOGR;
+    const cx<R> *sp = src + (base | toff);
     if constexpr (PL) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) v[r] = src[base | toff | m.off(r)];
+        for (int r = 0; r < NR; ++r) v[r] = sp[m.off(r)];
         return;
     }
     if (mode != IN_LOAD) pd.tile(d, base, t);
@@ -541,7 +597,7 @@ __device__ __forceinline__ void load_tile(cx<R> (&v)[1 << LOGR], const cx<R> *sr
         for (int r = 0; r < NR; ++r) v[r] = pd.at(d, r);
     } else {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) v[r] = src[base | toff | m.off(r)];
+        for (int r = 0; r < NR; ++r) v[r] = sp[m.off(r)];
         if (mode == IN_LOAD_DIAG) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) v[r] = cmul(v[r], pd.at(d, r));
@@ -553,7 +609,18 @@ __device__ __forceinline__ void load_tile(cx<R> (&v)[1 << LOGR], const cx<R> *sr
 // of blocks (t0 = blockIdx.x, tstep = gridDim.x) or a single block that owns
 // a whole batch instance (t0 = 0, tstep = 1) can run them; col is the
 // partial-sum column the block writes.
-template <typename R, int K, int LOGR, bool CONTIG, bool PL = false>
+// The SKIP mask of a pass's chains: assignment 1 when it is a middle one and
+// holds no active gate.  The kernels test it once and run one of two
+// straight-line bodies.
+template <int K, int LOGR>
+__device__ __forceinline__ bool mid_idle(const FusedArgs &a)
+{
+    using T = Tile<K, LOGR>;
+    if constexpr (T::NA >= 3) return !(a.active & T::newbits(1));
+    else return false;
+}
+
+template <typename R, int K, int LOGR, bool CONTIG, bool PL = false, int SKIP = 0>
 __device__ __forceinline__ void fwd_body(cx<R> *psi, const cx<R> *src, const FusedArgs &a,
                                          u64 t0, u64 tstep, cx<R> *lds)
 {
@@ -566,14 +633,16 @@ __device__ __forceinline__ void fwd_body(cx<R> *psi, const cx<R> *src, const Fus
     mst.init(a.pos + ST);
     P0Diag<R, K, LOGR> pd;
     if (a.in_mode != IN_LOAD) pd.init(a.dt, t);
+    const RyC<R, K> rc(a, a.layer);
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> v[T::NR];
         load_tile<R, K, LOGR, CONTIG, PL>(v, src, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
-        fwd_assign<R, K, LOGR, 0>(v, a, a.layer);
-        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(v, lds, t, a, a.layer);
+        fwd_assign<R, K, LOGR, 0>(v, a, rc);
+        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1, SKIP>::run(v, lds, t, a, rc);
+        cx<R> *pp = psi + fresh(base | toff_st);
 #pragma unroll
-        for (int r = 0; r < T::NR; ++r) psi[base | toff_st | mst.off(r)] = v[r];
+        for (int r = 0; r < T::NR; ++r) pp[mst.off(r)] = v[r];
     }
 }
 
@@ -582,7 +651,12 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_pass(void *psi_, const 
                                                               FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
-    fwd_body<R, K, LOGR, CONTIG>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x, gridDim.x, lds);
+    if (mid_idle<K, LOGR>(a))
+        fwd_body<R, K, LOGR, CONTIG, false, 2>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
+                                               gridDim.x, lds);
+    else
+        fwd_body<R, K, LOGR, CONTIG, false, 0>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
+                                               gridDim.x, lds);
 }
 
 // the same for a plain load (no diagonal on load, no generated layer)
@@ -591,8 +665,12 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_load_pass(void *psi_, c
                                                                    FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
-    fwd_body<R, K, LOGR, CONTIG, true>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
-                                       gridDim.x, lds);
+    if (mid_idle<K, LOGR>(a))
+        fwd_body<R, K, LOGR, CONTIG, true, 2>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
+                                           gridDim.x, lds);
+    else
+        fwd_body<R, K, LOGR, CONTIG, true, 0>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
+                                           gridDim.x, lds);
 }
 
 // Block sums of the gradient partials of the pass's active tile qubits for
@@ -652,7 +730,7 @@ __device__ __forceinline__ void z_partials(const cx<R> (&f)[1 << LOGR], const cx
 
 // LDG: both vectors first lose the diagonal of `layer` in the load layout
 // (a.ld), for the reverse of a two-layer pass.
-template <typename R, int K, int LOGR, bool CONTIG, bool LDG>
+template <typename R, int K, int LOGR, bool CONTIG, bool LDG, int SKIP = 0>
 __device__ __forceinline__ void bwd_body(const cx<R> *phi_in, cx<R> *phi, cx<R> *lam,
                                          const FusedArgs &a, u64 t0, u64 tstep, int col,
                                          cx<R> *lds, double *sh)
@@ -675,6 +753,7 @@ __device__ __forceinline__ void bwd_body(const cx<R> *phi_in, cx<R> *phi, cx<R> 
 #pragma unroll
     for (int k = 0; k < LOGR; ++k) accZr[k] = 0.0;
 
+    const RyC<R, K> rc(a, a.layer);
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> f[T::NR], l[T::NR];
@@ -684,10 +763,10 @@ __device__ __forceinline__ void bwd_body(const cx<R> *phi_in, cx<R> *phi, cx<R> 
             for (int r = 0; r < T::NR; ++r) f[r] = pg.at(a.gt, r);
         } else {
 #pragma unroll
-            for (int r = 0; r < T::NR; ++r) f[r] = phi_in[base | toff_ld | mld.off(r)];
+            for (int r = 0; r < T::NR; ++r) f[r] = (phi_in + (base | toff_ld))[mld.off(r)];
         }
 #pragma unroll
-        for (int r = 0; r < T::NR; ++r) l[r] = lam[base | toff_ld | mld.off(r)];
+        for (int r = 0; r < T::NR; ++r) l[r] = (lam + (base | toff_ld))[mld.off(r)];
         if (any_diag) {
             pd.tile(a.dt, base, t);
 #pragma unroll
@@ -708,13 +787,14 @@ __device__ __forceinline__ void bwd_body(const cx<R> *phi_in, cx<R> *phi, cx<R> 
         }
         // RZ gradients of the active tile qubits: sum_i z_q(i) Im(conj(lam_i) phi_i)
         z_partials<R, K, LOGR, 0>(f, l, accZr, ztot, a);
-        bwd_assign<R, K, LOGR, 0>(f, l, accY, a, a.layer);
-        if constexpr (T::NA > 1) BwdChain<R, K, LOGR, 1>::run(f, l, accY, lds, t, a, a.layer);
+        bwd_assign<R, K, LOGR, 0>(f, l, accY, a, rc);
+        if constexpr (T::NA > 1) BwdChain<R, K, LOGR, 1, SKIP>::run(f, l, accY, lds, t, a, rc);
+        const u64 o = fresh(base | toff_st);
+        cx<R> *pf = phi + o, *pl = lam + o;
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
-            const u64 i = base | toff_st | mst.off(r);
-            if (a.store_phi) phi[i] = f[r];
-            if (a.store_lam) lam[i] = l[r];
+            if (a.store_phi) pf[mst.off(r)] = f[r];
+            if (a.store_lam) pl[mst.off(r)] = l[r];
         }
     }
     write_partials<R, K, LOGR, 0, true>(accY, accZr, ztot, sh, a, a.layer, col);
@@ -726,8 +806,12 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const void *phi_in
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
-    bwd_body<R, K, LOGR, CONTIG, false>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_, a,
-                                        blockIdx.x, gridDim.x, blockIdx.x, lds, sh);
+    if (mid_idle<K, LOGR>(a))
+        bwd_body<R, K, LOGR, CONTIG, false, 2>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_, a,
+                                            blockIdx.x, gridDim.x, blockIdx.x, lds, sh);
+    else
+        bwd_body<R, K, LOGR, CONTIG, false, 0>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_, a,
+                                            blockIdx.x, gridDim.x, blockIdx.x, lds, sh);
 }
 
 // the reverse pass that first undoes the layer diagonal given in a.ld
@@ -737,8 +821,12 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_ld_pass(const void *phi
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
-    bwd_body<R, K, LOGR, CONTIG, true>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_, a,
-                                       blockIdx.x, gridDim.x, blockIdx.x, lds, sh);
+    if (mid_idle<K, LOGR>(a))
+        bwd_body<R, K, LOGR, CONTIG, true, 2>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_, a,
+                                           blockIdx.x, gridDim.x, blockIdx.x, lds, sh);
+    else
+        bwd_body<R, K, LOGR, CONTIG, true, 0>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_, a,
+                                           blockIdx.x, gridDim.x, blockIdx.x, lds, sh);
 }
 
 // Reverse pass that does not write phi back: every RY and RZ partial of the
@@ -747,7 +835,7 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_ld_pass(const void *phi
 // which commutes with Y_q), visiting the assignments 0 .. NA-1 with both
 // vectors; then lam alone is rotated back through NA-1 .. 0 and stored in
 // the load layout.  phi dies after the partials.
-template <typename R, int K, int LOGR, bool CONTIG, bool LDG>
+template <typename R, int K, int LOGR, bool CONTIG, bool LDG, int SKIP = 0>
 __device__ __forceinline__ void bwd_gf_body(const cx<R> *phi_in, cx<R> *lam, const FusedArgs &a,
                                             u64 t0, u64 tstep, int col, cx<R> *lds, double *sh)
 {
@@ -766,13 +854,16 @@ __device__ __forceinline__ void bwd_gf_body(const cx<R> *phi_in, cx<R> *lam, con
 #pragma unroll
     for (int k = 0; k < LOGR; ++k) accZr[k] = 0.0;
 
+    const RyC<R, K> rc(a, a.layer);
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
+        const cx<R> *fp = phi_in + (base | toff_ld);
+        const cx<R> *lp = lam + (base | toff_ld);
         cx<R> f[T::NR], l[T::NR];
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
-            f[r] = phi_in[base | toff_ld | mld.off(r)];
-            l[r] = lam[base | toff_ld | mld.off(r)];
+            f[r] = fp[mld.off(r)];
+            l[r] = lp[mld.off(r)];
         }
         if (a.diag_lam) {
             pd.tile(a.dt, base, t);
@@ -790,11 +881,12 @@ __device__ __forceinline__ void bwd_gf_body(const cx<R> *phi_in, cx<R> *lam, con
         }
         z_partials<R, K, LOGR, 0>(f, l, accZr, ztot, a);
         ygrad_assign<R, K, LOGR, 0>(f, l, accY, a);
-        if constexpr (T::NA > 1) GradChain<R, K, LOGR, 1>::run(f, l, accY, lds, t, a);
-        inv_assign<R, K, LOGR, T::NA - 1>(l, a, a.layer);
-        if constexpr (T::NA > 1) InvChainRev<R, K, LOGR, T::NA - 2>::run(l, lds, t, a, a.layer);
+        if constexpr (T::NA > 1) GradChain<R, K, LOGR, 1, SKIP>::run(f, l, accY, lds, t, a);
+        inv_assign<R, K, LOGR, T::NA - 1>(l, a, rc);
+        if constexpr (T::NA > 1) InvChainRev<R, K, LOGR, T::NA - 2, SKIP>::run(l, lds, t, a, rc);
+        cx<R> *ls = lam + fresh(base | toff_ld);
 #pragma unroll
-        for (int r = 0; r < T::NR; ++r) lam[base | toff_ld | mld.off(r)] = l[r];
+        for (int r = 0; r < T::NR; ++r) ls[mld.off(r)] = l[r];
     }
     write_partials<R, K, LOGR, 0, true>(accY, accZr, ztot, sh, a, a.layer, col);
 }
@@ -805,8 +897,12 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_gf_pass(const void *phi
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
-    bwd_gf_body<R, K, LOGR, CONTIG, false>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, blockIdx.x,
-                                           gridDim.x, blockIdx.x, lds, sh);
+    if (mid_idle<K, LOGR>(a))
+        bwd_gf_body<R, K, LOGR, CONTIG, false, 2>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, blockIdx.x,
+                                               gridDim.x, blockIdx.x, lds, sh);
+    else
+        bwd_gf_body<R, K, LOGR, CONTIG, false, 0>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, blockIdx.x,
+                                               gridDim.x, blockIdx.x, lds, sh);
 }
 
 template <typename R, int K, int LOGR, bool CONTIG>
@@ -815,8 +911,12 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_gf_ld_pass(const void *
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
-    bwd_gf_body<R, K, LOGR, CONTIG, true>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, blockIdx.x,
-                                          gridDim.x, blockIdx.x, lds, sh);
+    if (mid_idle<K, LOGR>(a))
+        bwd_gf_body<R, K, LOGR, CONTIG, true, 2>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, blockIdx.x,
+                                              gridDim.x, blockIdx.x, lds, sh);
+    else
+        bwd_gf_body<R, K, LOGR, CONTIG, true, 0>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, blockIdx.x,
+                                              gridDim.x, blockIdx.x, lds, sh);
 }
 
 // Last forward pass of the last layer + energy + first reverse pass, for a
@@ -829,7 +929,7 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_gf_ld_pass(const void *
 // here: Im(conj(D_i psi_i) psi_i) = 0.  When this is the layer's only pass,
 // the load applies the previous layer's diagonal (or generates the first
 // layer's state).
-template <typename R, int K, int LOGR, bool CONTIG, bool PL>
+template <typename R, int K, int LOGR, bool CONTIG, bool PL, int SKIP = 0>
 __device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const FusedArgs &a,
                                           u64 t0, u64 tstep, int col, cx<R> *lds, double *sh)
 {
@@ -847,17 +947,18 @@ __device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const Fu
     for (int j = 0; j < K; ++j) accY[j] = 0.0;
     double eacc = 0.0;
 
+    const RyC<R, K> rc(a, a.layer);
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> f[T::NR], l[T::NR];
         load_tile<R, K, LOGR, CONTIG, PL>(f, psi, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
-        fwd_assign<R, K, LOGR, 0>(f, a, a.layer);
-        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(f, lds, t, a, a.layer);
+        fwd_assign<R, K, LOGR, 0>(f, a, rc);
+        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1, SKIP>::run(f, lds, t, a, rc);
         // energy and lam in the last assignment's layout
         R et = 0;
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
-            const double d = a.hdiag[base | toff_st | mst.off(r)];
+            const double d = (a.hdiag + (base | toff_st))[mst.off(r)];
             const R p = f[r].re * f[r].re + f[r].im * f[r].im;
             et += (R)d * p;
             l[r].re = (R)d * f[r].re;
@@ -865,11 +966,12 @@ __device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const Fu
         }
         eacc += (double)et;
         ygrad_assign<R, K, LOGR, T::NA - 1>(f, l, accY, a);
-        if constexpr (T::NA > 1) GradChainRev<R, K, LOGR, T::NA - 2>::run(f, l, accY, lds, t, a);
-        inv_assign<R, K, LOGR, 0>(l, a, a.layer);
-        if constexpr (T::NA > 1) InvChain<R, K, LOGR, 1>::run(l, lds, t, a, a.layer);
+        if constexpr (T::NA > 1) GradChainRev<R, K, LOGR, T::NA - 2, SKIP>::run(f, l, accY, lds, t, a);
+        inv_assign<R, K, LOGR, 0>(l, a, rc);
+        if constexpr (T::NA > 1) InvChain<R, K, LOGR, 1, SKIP>::run(l, lds, t, a, rc);
+        cx<R> *pl = lam + fresh(base | toff_st);
 #pragma unroll
-        for (int r = 0; r < T::NR; ++r) lam[base | toff_st | mst.off(r)] = l[r];
+        for (int r = 0; r < T::NR; ++r) pl[mst.off(r)] = l[r];
     }
     write_partials<R, K, LOGR, 0, false>(accY, accZr, 0.0, sh, a, a.layer, col);
     const double e = block_sum(eacc, sh);
@@ -885,8 +987,12 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_pass(const void *psi_,
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
-    turn_body<R, K, LOGR, CONTIG, false>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x,
-                                         gridDim.x, blockIdx.x, lds, sh);
+    if (mid_idle<K, LOGR>(a))
+        turn_body<R, K, LOGR, CONTIG, false, 2>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x,
+                                             gridDim.x, blockIdx.x, lds, sh);
+    else
+        turn_body<R, K, LOGR, CONTIG, false, 0>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x,
+                                             gridDim.x, blockIdx.x, lds, sh);
 }
 
 // Plain-load turnaround for 12-bit tiles, run by 512 threads holding 8
@@ -897,8 +1003,12 @@ __global__ __launch_bounds__(512) void k_turn_load_pass(const void *psi_, void *
 {
     __shared__ cx<R> lds[Tile<12, 3>::LDS];
     __shared__ double sh[512 / 64 + 1];
-    turn_body<R, 12, 3, true, true>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x,
-                                     gridDim.x, blockIdx.x, lds, sh);
+    if (mid_idle<12, 3>(a))
+        turn_body<R, 12, 3, true, true, 2>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x,
+                                           gridDim.x, blockIdx.x, lds, sh);
+    else
+        turn_body<R, 12, 3, true, true, 0>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x,
+                                           gridDim.x, blockIdx.x, lds, sh);
 }
 
 
@@ -909,7 +1019,7 @@ __global__ __launch_bounds__(512) void k_turn_load_pass(const void *psi_, void *
 // gates through the assignments 0 .. NA-1, the first layer's diagonal in
 // the last assignment, then the second layer's RY gates back through
 // NA-1 .. 0, and the tile is stored in the load layout.
-template <typename R, int K, int LOGR, bool CONTIG, bool PL>
+template <typename R, int K, int LOGR, bool CONTIG, bool PL, int SKIP = 0>
 __device__ __forceinline__ void fwd2_body(cx<R> *psi, const cx<R> *src, const FusedArgs &a,
                                           u64 t0, u64 tstep, cx<R> *lds)
 {
@@ -922,19 +1032,22 @@ __device__ __forceinline__ void fwd2_body(cx<R> *psi, const cx<R> *src, const Fu
     P0Diag<R, K, LOGR> pd;
     if (a.in_mode != IN_LOAD) pd.init(a.dt, t);
     LDiag<R, K, LOGR> dg;
+    const RyC<R, K> rc(a, a.layer);
+    const RyC<R, K> rc2(a, a.layer2);
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> v[T::NR];
         load_tile<R, K, LOGR, CONTIG, PL>(v, src, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
-        fwd_assign<R, K, LOGR, 0>(v, a, a.layer);
-        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1>::run(v, lds, t, a, a.layer);
+        fwd_assign<R, K, LOGR, 0>(v, a, rc);
+        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1, SKIP>::run(v, lds, t, a, rc);
         dg.tile(a.ld, tile, base | toff_st, t);
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) v[r] = cmul(v[r], dg.at(a.ld, r));
-        fwd_assign<R, K, LOGR, T::NA - 1>(v, a, a.layer2);
-        if constexpr (T::NA > 1) FwdChainRev<R, K, LOGR, T::NA - 2>::run(v, lds, t, a, a.layer2);
+        fwd_assign<R, K, LOGR, T::NA - 1>(v, a, rc2);
+        if constexpr (T::NA > 1) FwdChainRev<R, K, LOGR, T::NA - 2, SKIP>::run(v, lds, t, a, rc2);
+        cx<R> *pp = psi + fresh(base | toff_ld);
 #pragma unroll
-        for (int r = 0; r < T::NR; ++r) psi[base | toff_ld | mld.off(r)] = v[r];
+        for (int r = 0; r < T::NR; ++r) pp[mld.off(r)] = v[r];
     }
 }
 
@@ -943,8 +1056,12 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd2_pass(void *psi_, const
                                                                FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
-    fwd2_body<R, K, LOGR, CONTIG, false>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
-                                         gridDim.x, lds);
+    if (mid_idle<K, LOGR>(a))
+        fwd2_body<R, K, LOGR, CONTIG, false, 2>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
+                                             gridDim.x, lds);
+    else
+        fwd2_body<R, K, LOGR, CONTIG, false, 0>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
+                                             gridDim.x, lds);
 }
 
 template <typename R, int K, int LOGR, bool CONTIG>
@@ -952,8 +1069,12 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd2_load_pass(void *psi_, 
                                                                     FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
-    fwd2_body<R, K, LOGR, CONTIG, true>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
-                                        gridDim.x, lds);
+    if (mid_idle<K, LOGR>(a))
+        fwd2_body<R, K, LOGR, CONTIG, true, 2>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
+                                            gridDim.x, lds);
+    else
+        fwd2_body<R, K, LOGR, CONTIG, true, 0>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
+                                            gridDim.x, lds);
 }
 
 // ------------------------------------------------ first-layer gradients
@@ -1128,7 +1249,7 @@ struct OffArgs {
     int n;
     int8_t pos[kMaxTileBits];
     int nruns;
-    int8_t run_src[kMaxTileBits + 1], run_w[kMaxTileBits + 1], run_dst[kMaxTileBits + 1];
+    uint32_t run[kMaxTileBits + 1];
     u64 ntiles;
     const OffClass *cls;
     int c0, c1;
@@ -1191,9 +1312,10 @@ __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const Off
         const u64 bt = base | toff;
         cx<R> v[T::NR], acc[T::NR];
         __syncthreads();
+        const cx<R> *pt = psi + bt;
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
-            v[r] = psi[bt | m.off(r)];
+            v[r] = pt[m.off(r)];
             lds[T::pad(T::u_of(t, r, LD))] = v[r];
             acc[r].re = acc[r].im = R(0);
         }
@@ -1232,16 +1354,16 @@ __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const Off
                 acc[r].im += A[r] * pv.im + B[r] * pv.re;
             }
         }
+        cx<R> *lt = lam ? lam + fresh(bt) : nullptr;
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
             er += (double)v[r].re * acc[r].re + (double)v[r].im * acc[r].im;
             ei += (double)v[r].re * acc[r].im - (double)v[r].im * acc[r].re;
-            if (lam) {
-                const u64 i = bt | m.off(r);
-                cx<R> o = lam[i];
+            if (lt) {
+                cx<R> o = lt[m.off(r)];
                 o.re += acc[r].re;
                 o.im += acc[r].im;
-                lam[i] = o;
+                lt[m.off(r)] = o;
             }
         }
     }
@@ -1476,9 +1598,7 @@ void fill_runs(FusedArgs &a, const PassPlan &pp, int K, int n)
         }
         int w = 0;
         while (q + w < n && !in[q + w]) ++w;
-        a.run_src[a.nruns] = (int8_t)src;
-        a.run_w[a.nruns] = (int8_t)w;
-        a.run_dst[a.nruns] = (int8_t)q;
+        a.run[a.nruns] = (uint32_t)src | (uint32_t)w << 8 | (uint32_t)q << 16;
         ++a.nruns;
         src += w;
         q += w;
@@ -1626,11 +1746,7 @@ __device__ __forceinline__ void batch_fill_pass(FusedArgs &a, const BatchInst &I
     for (int j = 0; j < kMaxTileBits; ++j) a.pos[j] = I.pass[p].pos[j];
     a.active = I.pass[p].active;
     a.nruns = I.pass[p].nruns;
-    for (int k = 0; k <= kMaxTileBits; ++k) {
-        a.run_src[k] = I.pass[p].run_src[k];
-        a.run_w[k] = I.pass[p].run_w[k];
-        a.run_dst[k] = I.pass[p].run_dst[k];
-    }
+    for (int k = 0; k <= kMaxTileBits; ++k) a.run[k] = I.pass[p].run[k];
     a.ntiles = I.ntiles;
     a.ry = I.ry;
     a.in_mode = IN_LOAD;
@@ -1704,11 +1820,7 @@ __device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh, OffSt
         o.n = I.n;
         for (int j = 0; j < kMaxTileBits; ++j) o.pos[j] = op.tile.pos[j];
         o.nruns = op.tile.nruns;
-        for (int q = 0; q <= kMaxTileBits; ++q) {
-            o.run_src[q] = op.tile.run_src[q];
-            o.run_w[q] = op.tile.run_w[q];
-            o.run_dst[q] = op.tile.run_dst[q];
-        }
+        for (int q = 0; q <= kMaxTileBits; ++q) o.run[q] = op.tile.run[q];
         o.ntiles = I.ntiles;
         o.cls = I.cls;
         o.c0 = op.c0;
@@ -1823,19 +1935,16 @@ void pass_runs(const int8_t *pos, int K, int n, BatchPass *out)
     fill_runs(fa, pp, K, n);
     for (int j = 0; j < K; ++j) out->pos[j] = pos[j];
     out->nruns = fa.nruns;
-    for (int k = 0; k < fa.nruns; ++k) {
-        out->run_src[k] = fa.run_src[k];
-        out->run_w[k] = fa.run_w[k];
-        out->run_dst[k] = fa.run_dst[k];
-    }
+    for (int k = 0; k < fa.nruns; ++k) out->run[k] = fa.run[k];
 }
 
 
 int fused_grid(int prec, const TilePlan &plan, int n)
 {
-    // persistent blocks: enough to fill 256 CUs several times over
+    // persistent blocks: four rounds of three resident blocks on each of the
+    // 256 CUs, which also balances the kernels that keep four resident
     const u64 ntiles = 1ull << (n - plan.K);
-    const u64 want = prec == GV_C64 ? 1024 : 512;
+    const u64 want = prec == GV_C64 ? 3072 : 512;
     return (int)(ntiles < want ? ntiles : want);
 }
 
@@ -2156,11 +2265,7 @@ hipError_t offdiag_pass(int prec, const void *psi, void *lam, int n, int K, cons
     fill_runs(fa, pp, K, n);
     for (int j = 0; j < K; ++j) a.pos[j] = op.pos[j];
     a.nruns = fa.nruns;
-    for (int k = 0; k < fa.nruns; ++k) {
-        a.run_src[k] = fa.run_src[k];
-        a.run_w[k] = fa.run_w[k];
-        a.run_dst[k] = fa.run_dst[k];
-    }
+    for (int k = 0; k < fa.nruns; ++k) a.run[k] = fa.run[k];
     a.ntiles = 1ull << (n - K);
     a.cls = cls;
     a.c0 = op.c0;

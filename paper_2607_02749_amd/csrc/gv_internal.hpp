@@ -328,7 +328,7 @@ struct BatchPass {
     int8_t pos[kMaxTileBits];
     uint32_t active;
     int nruns;
-    int8_t run_src[kMaxTileBits + 1], run_w[kMaxTileBits + 1], run_dst[kMaxTileBits + 1];
+    uint32_t run[kMaxTileBits + 1];   // source bit | width << 8 | destination bit << 16
 };
 struct BatchOffPass {
     BatchPass tile;
