@@ -302,11 +302,24 @@ __device__ __forceinline__ void rot_pair(cx<R> &x, cx<R> &y, R c, R sn)
     y.im = sn * a.im + c * b.im;
 }
 
+// Whether tile bit j holds an active gate: from the compile-time mask AM
+// when it is set (the kernels compile the two common patterns), else from
+// the pass arguments.  AM with kActRuntime still reads the pass arguments
+// and only lets the chains skip: the reverse bodies keep fewer registers
+// live with the per-gate branches than with straight-line code.
+constexpr uint32_t kActRuntime = 1u << 31;
+template <uint32_t AM>
+__device__ __forceinline__ bool on(const FusedArgs &a, int j)
+{
+    if constexpr (AM != 0 && !(AM & kActRuntime)) return (AM >> j) & 1;
+    else return (a.active >> j) & 1;
+}
+
 // (cos, sin) of the half angles of one rotation layer's RY gates on the K
 // tile qubits, read once per block: inside the tile loop each gate would
 // otherwise wait for its own load.  Only the pass's active qubits are read
 // (the gates the assignments apply); the others hold the identity.
-template <typename R, int K>
+template <typename R, int K, uint32_t AM = 0>
 struct RyC {
     R c[K], s[K];
     __device__ __forceinline__ RyC(const FusedArgs &a, int layer)
@@ -316,7 +329,7 @@ struct RyC {
         for (int j = 0; j < K; ++j) {
             c[j] = R(1);
             s[j] = R(0);
-            if ((a.active >> j) & 1) {
+            if (on<AM>(a, j)) {
                 const cx<R> e = ry[a.pos[j]];
                 c[j] = e.re;
                 s[j] = e.im;
@@ -326,8 +339,9 @@ struct RyC {
 };
 
 // forward rotations of the tile bits that are new in assignment AI
-template <typename R, int K, int LOGR, int AI>
-__device__ __forceinline__ void fwd_assign(cx<R> (&v)[1 << LOGR], const FusedArgs &a, const RyC<R, K> &rc)
+template <typename R, int K, int LOGR, int AI, uint32_t AM>
+__device__ __forceinline__ void fwd_assign(cx<R> (&v)[1 << LOGR], const FusedArgs &a,
+                                           const RyC<R, K, AM> &rc)
 {
     using T = Tile<K, LOGR>;
     constexpr int LO = T::lo(AI);
@@ -335,7 +349,7 @@ __device__ __forceinline__ void fwd_assign(cx<R> (&v)[1 << LOGR], const FusedArg
 #pragma unroll
     for (int k = 0; k < LOGR; ++k) {
         const int j = LO + k;
-        if (!((NEW >> j) & 1) || !((a.active >> j) & 1)) continue;
+        if (!((NEW >> j) & 1) || !on<AM>(a, j)) continue;
         const R c = rc.c[j], sn = rc.s[j];
 #pragma unroll
         for (int r = 0; r < T::NR; ++r)
@@ -346,9 +360,10 @@ __device__ __forceinline__ void fwd_assign(cx<R> (&v)[1 << LOGR], const FusedArg
 // reverse step of the tile bits new in assignment AI: gradient partial of
 // RY (Im<lam|Y_q|phi> = Re(conj(l1) f0) - Re(conj(l0) f1) over the pairs),
 // then RY(-theta) on both vectors
-template <typename R, int K, int LOGR, int AI>
+template <typename R, int K, int LOGR, int AI, uint32_t AM>
 __device__ __forceinline__ void bwd_assign(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
-                                           double (&accY)[K], const FusedArgs &a, const RyC<R, K> &rc)
+                                           double (&accY)[K], const FusedArgs &a,
+                                           const RyC<R, K, AM> &rc)
 {
     using T = Tile<K, LOGR>;
     constexpr int LO = T::lo(AI);
@@ -356,7 +371,7 @@ __device__ __forceinline__ void bwd_assign(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 <
 #pragma unroll
     for (int k = 0; k < LOGR; ++k) {
         const int j = LO + k;
-        if (!((NEW >> j) & 1) || !((a.active >> j) & 1)) continue;
+        if (!((NEW >> j) & 1) || !on<AM>(a, j)) continue;
         const R c = rc.c[j], sn = -rc.s[j];
         R g = 0;
 #pragma unroll
@@ -373,7 +388,7 @@ __device__ __forceinline__ void bwd_assign(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 <
 
 // RY partials of the tile bits new in assignment AI from (phi, lam) taken
 // at the same point, without rotating: Im<lam|Y_q|phi> over the pairs
-template <typename R, int K, int LOGR, int AI>
+template <typename R, int K, int LOGR, int AI, uint32_t AM>
 __device__ __forceinline__ void ygrad_assign(const cx<R> (&f)[1 << LOGR], const cx<R> (&l)[1 << LOGR],
                                              double (&accY)[K], const FusedArgs &a)
 {
@@ -383,7 +398,7 @@ __device__ __forceinline__ void ygrad_assign(const cx<R> (&f)[1 << LOGR], const 
 #pragma unroll
     for (int k = 0; k < LOGR; ++k) {
         const int j = LO + k;
-        if (!((NEW >> j) & 1) || !((a.active >> j) & 1)) continue;
+        if (!((NEW >> j) & 1) || !on<AM>(a, j)) continue;
         R g = 0;
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
@@ -396,8 +411,9 @@ __device__ __forceinline__ void ygrad_assign(const cx<R> (&f)[1 << LOGR], const 
 }
 
 // RY(-theta) of the tile bits new in assignment AI on one vector
-template <typename R, int K, int LOGR, int AI>
-__device__ __forceinline__ void inv_assign(cx<R> (&v)[1 << LOGR], const FusedArgs &a, const RyC<R, K> &rc)
+template <typename R, int K, int LOGR, int AI, uint32_t AM>
+__device__ __forceinline__ void inv_assign(cx<R> (&v)[1 << LOGR], const FusedArgs &a,
+                                           const RyC<R, K, AM> &rc)
 {
     using T = Tile<K, LOGR>;
     constexpr int LO = T::lo(AI);
@@ -405,7 +421,7 @@ __device__ __forceinline__ void inv_assign(cx<R> (&v)[1 << LOGR], const FusedArg
 #pragma unroll
     for (int k = 0; k < LOGR; ++k) {
         const int j = LO + k;
-        if (!((NEW >> j) & 1) || !((a.active >> j) & 1)) continue;
+        if (!((NEW >> j) & 1) || !on<AM>(a, j)) continue;
         const R c = rc.c[j], sn = -rc.s[j];
 #pragma unroll
         for (int r = 0; r < T::NR; ++r)
@@ -434,143 +450,143 @@ __device__ __forceinline__ void exchange(cx<R> (&v)[1 << LOGR], cx<R> *lds, int 
 }
 
 // The chains below run assignments one after the other, each after an
-// exchange into its layout.  SKIP marks assignments in the middle of a chain
-// whose tile bits hold no active gate (in every pass after the first, the
-// kept low bits): they are skipped, the data going straight from the layout
-// it is in (LF) to the next assignment's.  The first and last layouts never
-// change.
+// exchange into its layout.  With a compile-time active mask AM, an
+// assignment in the middle of a chain whose tile bits hold no active gate
+// (in every pass after the first, the kept low bits) is skipped, the data
+// going straight from the layout it is in (LF) to the next assignment's.
+// The first and last layouts never change.
 
-template <typename R, int K, int LOGR, int AI, int SKIP, int LF = Tile<K, LOGR>::lo(AI - 1)>
+template <typename R, int K, int LOGR, int AI, uint32_t AM, int LF = Tile<K, LOGR>::lo(AI - 1)>
 struct FwdChain {
     __device__ static __forceinline__ void run(cx<R> (&v)[1 << LOGR], cx<R> *lds, int t,
-                                               const FusedArgs &a, const RyC<R, K> &rc)
+                                               const FusedArgs &a, const RyC<R, K, AM> &rc)
     {
         using T = Tile<K, LOGR>;
-        if constexpr ((AI + 1 < T::NA) && ((SKIP >> AI) & 1))
-            return FwdChain<R, K, LOGR, AI + 1, SKIP, LF>::run(v, lds, t, a, rc);
+        if constexpr ((AI + 1 < T::NA) && AM != 0 && !(AM & T::newbits(AI)))
+            return FwdChain<R, K, LOGR, AI + 1, AM, LF>::run(v, lds, t, a, rc);
         exchange<R, K, LOGR, LF, T::lo(AI)>(v, lds, t);
-        fwd_assign<R, K, LOGR, AI>(v, a, rc);
-        if constexpr (AI + 1 < T::NA) FwdChain<R, K, LOGR, AI + 1, SKIP>::run(v, lds, t, a, rc);
+        fwd_assign<R, K, LOGR, AI, AM>(v, a, rc);
+        if constexpr (AI + 1 < T::NA) FwdChain<R, K, LOGR, AI + 1, AM>::run(v, lds, t, a, rc);
     }
 };
 
 // forward assignments in the order AI, AI-1, ..., 0 (each after an exchange
 // from AI+1): the second layer of a two-layer pass
-template <typename R, int K, int LOGR, int AI, int SKIP, int LF = Tile<K, LOGR>::lo(AI + 1)>
+template <typename R, int K, int LOGR, int AI, uint32_t AM, int LF = Tile<K, LOGR>::lo(AI + 1)>
 struct FwdChainRev {
     __device__ static __forceinline__ void run(cx<R> (&v)[1 << LOGR], cx<R> *lds, int t,
-                                               const FusedArgs &a, const RyC<R, K> &rc)
+                                               const FusedArgs &a, const RyC<R, K, AM> &rc)
     {
         using T = Tile<K, LOGR>;
-        if constexpr ((AI > 0) && ((SKIP >> AI) & 1))
-            return FwdChainRev<R, K, LOGR, AI - 1, SKIP, LF>::run(v, lds, t, a, rc);
+        if constexpr ((AI > 0) && AM != 0 && !(AM & T::newbits(AI)))
+            return FwdChainRev<R, K, LOGR, AI - 1, AM, LF>::run(v, lds, t, a, rc);
         exchange<R, K, LOGR, LF, T::lo(AI)>(v, lds, t);
-        fwd_assign<R, K, LOGR, AI>(v, a, rc);
-        if constexpr (AI > 0) FwdChainRev<R, K, LOGR, AI - 1, SKIP>::run(v, lds, t, a, rc);
+        fwd_assign<R, K, LOGR, AI, AM>(v, a, rc);
+        if constexpr (AI > 0) FwdChainRev<R, K, LOGR, AI - 1, AM>::run(v, lds, t, a, rc);
     }
 };
 
 // reverse assignments AI = 1 .. NA-1, each after an exchange from AI-1
-template <typename R, int K, int LOGR, int AI, int SKIP, int LF = Tile<K, LOGR>::lo(AI - 1)>
+template <typename R, int K, int LOGR, int AI, uint32_t AM, int LF = Tile<K, LOGR>::lo(AI - 1)>
 struct BwdChain {
     __device__ static __forceinline__ void run(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
                                                double (&accY)[K], cx<R> *lds, int t,
-                                               const FusedArgs &a, const RyC<R, K> &rc)
+                                               const FusedArgs &a, const RyC<R, K, AM> &rc)
     {
         using T = Tile<K, LOGR>;
-        if constexpr ((AI + 1 < T::NA) && ((SKIP >> AI) & 1))
-            return BwdChain<R, K, LOGR, AI + 1, SKIP, LF>::run(f, l, accY, lds, t, a, rc);
+        if constexpr ((AI + 1 < T::NA) && AM != 0 && !(AM & T::newbits(AI)))
+            return BwdChain<R, K, LOGR, AI + 1, AM, LF>::run(f, l, accY, lds, t, a, rc);
         exchange<R, K, LOGR, LF, T::lo(AI)>(f, lds, t);
         exchange<R, K, LOGR, LF, T::lo(AI)>(l, lds, t);
-        bwd_assign<R, K, LOGR, AI>(f, l, accY, a, rc);
+        bwd_assign<R, K, LOGR, AI, AM>(f, l, accY, a, rc);
         if constexpr (AI + 1 < T::NA)
-            BwdChain<R, K, LOGR, AI + 1, SKIP>::run(f, l, accY, lds, t, a, rc);
+            BwdChain<R, K, LOGR, AI + 1, AM>::run(f, l, accY, lds, t, a, rc);
     }
 };
 
 // reverse assignments in the order AI, AI-1, ..., 0 (each after an exchange
 // from AI+1), used where the data ends a forward or reverse part in the last
 // assignment
-template <typename R, int K, int LOGR, int AI, int SKIP, int LF = Tile<K, LOGR>::lo(AI + 1)>
+template <typename R, int K, int LOGR, int AI, uint32_t AM, int LF = Tile<K, LOGR>::lo(AI + 1)>
 struct BwdChainRev {
     __device__ static __forceinline__ void run(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
                                                double (&accY)[K], cx<R> *lds, int t,
-                                               const FusedArgs &a, const RyC<R, K> &rc)
+                                               const FusedArgs &a, const RyC<R, K, AM> &rc)
     {
         using T = Tile<K, LOGR>;
-        if constexpr ((AI > 0) && ((SKIP >> AI) & 1))
-            return BwdChainRev<R, K, LOGR, AI - 1, SKIP, LF>::run(f, l, accY, lds, t, a, rc);
+        if constexpr ((AI > 0) && AM != 0 && !(AM & T::newbits(AI)))
+            return BwdChainRev<R, K, LOGR, AI - 1, AM, LF>::run(f, l, accY, lds, t, a, rc);
         exchange<R, K, LOGR, LF, T::lo(AI)>(f, lds, t);
         exchange<R, K, LOGR, LF, T::lo(AI)>(l, lds, t);
-        bwd_assign<R, K, LOGR, AI>(f, l, accY, a, rc);
-        if constexpr (AI > 0) BwdChainRev<R, K, LOGR, AI - 1, SKIP>::run(f, l, accY, lds, t, a, rc);
+        bwd_assign<R, K, LOGR, AI, AM>(f, l, accY, a, rc);
+        if constexpr (AI > 0) BwdChainRev<R, K, LOGR, AI - 1, AM>::run(f, l, accY, lds, t, a, rc);
     }
 };
 
 // partials of assignments AI .. NA-1, each after an exchange of both vectors
-template <typename R, int K, int LOGR, int AI, int SKIP, int LF = Tile<K, LOGR>::lo(AI - 1)>
+template <typename R, int K, int LOGR, int AI, uint32_t AM, int LF = Tile<K, LOGR>::lo(AI - 1)>
 struct GradChain {
     __device__ static __forceinline__ void run(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
                                                double (&accY)[K], cx<R> *lds, int t,
                                                const FusedArgs &a)
     {
         using T = Tile<K, LOGR>;
-        if constexpr ((AI + 1 < T::NA) && ((SKIP >> AI) & 1))
-            return GradChain<R, K, LOGR, AI + 1, SKIP, LF>::run(f, l, accY, lds, t, a);
+        if constexpr ((AI + 1 < T::NA) && AM != 0 && !(AM & T::newbits(AI)))
+            return GradChain<R, K, LOGR, AI + 1, AM, LF>::run(f, l, accY, lds, t, a);
         exchange<R, K, LOGR, LF, T::lo(AI)>(f, lds, t);
         exchange<R, K, LOGR, LF, T::lo(AI)>(l, lds, t);
-        ygrad_assign<R, K, LOGR, AI>(f, l, accY, a);
-        if constexpr (AI + 1 < T::NA) GradChain<R, K, LOGR, AI + 1, SKIP>::run(f, l, accY, lds, t, a);
+        ygrad_assign<R, K, LOGR, AI, AM>(f, l, accY, a);
+        if constexpr (AI + 1 < T::NA) GradChain<R, K, LOGR, AI + 1, AM>::run(f, l, accY, lds, t, a);
     }
 };
 
 // RY(-theta) of assignments AI, AI-1, .., 0 on one vector, each after an
 // exchange from AI+1
-template <typename R, int K, int LOGR, int AI, int SKIP, int LF = Tile<K, LOGR>::lo(AI + 1)>
+template <typename R, int K, int LOGR, int AI, uint32_t AM, int LF = Tile<K, LOGR>::lo(AI + 1)>
 struct InvChainRev {
     __device__ static __forceinline__ void run(cx<R> (&v)[1 << LOGR], cx<R> *lds, int t,
-                                               const FusedArgs &a, const RyC<R, K> &rc)
+                                               const FusedArgs &a, const RyC<R, K, AM> &rc)
     {
         using T = Tile<K, LOGR>;
-        if constexpr ((AI > 0) && ((SKIP >> AI) & 1))
-            return InvChainRev<R, K, LOGR, AI - 1, SKIP, LF>::run(v, lds, t, a, rc);
+        if constexpr ((AI > 0) && AM != 0 && !(AM & T::newbits(AI)))
+            return InvChainRev<R, K, LOGR, AI - 1, AM, LF>::run(v, lds, t, a, rc);
         exchange<R, K, LOGR, LF, T::lo(AI)>(v, lds, t);
-        inv_assign<R, K, LOGR, AI>(v, a, rc);
-        if constexpr (AI > 0) InvChainRev<R, K, LOGR, AI - 1, SKIP>::run(v, lds, t, a, rc);
+        inv_assign<R, K, LOGR, AI, AM>(v, a, rc);
+        if constexpr (AI > 0) InvChainRev<R, K, LOGR, AI - 1, AM>::run(v, lds, t, a, rc);
     }
 };
 
 // partials of assignments AI, AI-1, .., 0, each after an exchange of both
 // vectors from AI+1
-template <typename R, int K, int LOGR, int AI, int SKIP, int LF = Tile<K, LOGR>::lo(AI + 1)>
+template <typename R, int K, int LOGR, int AI, uint32_t AM, int LF = Tile<K, LOGR>::lo(AI + 1)>
 struct GradChainRev {
     __device__ static __forceinline__ void run(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR],
                                                double (&accY)[K], cx<R> *lds, int t,
                                                const FusedArgs &a)
     {
         using T = Tile<K, LOGR>;
-        if constexpr ((AI > 0) && ((SKIP >> AI) & 1))
-            return GradChainRev<R, K, LOGR, AI - 1, SKIP, LF>::run(f, l, accY, lds, t, a);
+        if constexpr ((AI > 0) && AM != 0 && !(AM & T::newbits(AI)))
+            return GradChainRev<R, K, LOGR, AI - 1, AM, LF>::run(f, l, accY, lds, t, a);
         exchange<R, K, LOGR, LF, T::lo(AI)>(f, lds, t);
         exchange<R, K, LOGR, LF, T::lo(AI)>(l, lds, t);
-        ygrad_assign<R, K, LOGR, AI>(f, l, accY, a);
-        if constexpr (AI > 0) GradChainRev<R, K, LOGR, AI - 1, SKIP>::run(f, l, accY, lds, t, a);
+        ygrad_assign<R, K, LOGR, AI, AM>(f, l, accY, a);
+        if constexpr (AI > 0) GradChainRev<R, K, LOGR, AI - 1, AM>::run(f, l, accY, lds, t, a);
     }
 };
 
 // RY(-theta) of assignments AI .. NA-1 on one vector, each after an exchange
 // from AI-1
-template <typename R, int K, int LOGR, int AI, int SKIP, int LF = Tile<K, LOGR>::lo(AI - 1)>
+template <typename R, int K, int LOGR, int AI, uint32_t AM, int LF = Tile<K, LOGR>::lo(AI - 1)>
 struct InvChain {
     __device__ static __forceinline__ void run(cx<R> (&v)[1 << LOGR], cx<R> *lds, int t,
-                                               const FusedArgs &a, const RyC<R, K> &rc)
+                                               const FusedArgs &a, const RyC<R, K, AM> &rc)
     {
         using T = Tile<K, LOGR>;
-        if constexpr ((AI + 1 < T::NA) && ((SKIP >> AI) & 1))
-            return InvChain<R, K, LOGR, AI + 1, SKIP, LF>::run(v, lds, t, a, rc);
+        if constexpr ((AI + 1 < T::NA) && AM != 0 && !(AM & T::newbits(AI)))
+            return InvChain<R, K, LOGR, AI + 1, AM, LF>::run(v, lds, t, a, rc);
         exchange<R, K, LOGR, LF, T::lo(AI)>(v, lds, t);
-        inv_assign<R, K, LOGR, AI>(v, a, rc);
-        if constexpr (AI + 1 < T::NA) InvChain<R, K, LOGR, AI + 1, SKIP>::run(v, lds, t, a, rc);
+        inv_assign<R, K, LOGR, AI, AM>(v, a, rc);
+        if constexpr (AI + 1 < T::NA) InvChain<R, K, LOGR, AI + 1, AM>::run(v, lds, t, a, rc);
     }
 };
 
@@ -609,18 +625,21 @@ __device__ __forceinline__ void load_tile(cx<R> (&v)[1 << LOGR], const cx<R> *sr
 // of blocks (t0 = blockIdx.x, tstep = gridDim.x) or a single block that owns
 // a whole batch instance (t0 = 0, tstep = 1) can run them; col is the
 // partial-sum column the block writes.
-// The SKIP mask of a pass's chains: assignment 1 when it is a middle one and
-// holds no active gate.  The kernels test it once and run one of two
-// straight-line bodies.
-template <int K, int LOGR>
-__device__ __forceinline__ bool mid_idle(const FusedArgs &a)
+// The two active masks the kernels compile bodies for: pass 0 (every tile
+// bit) and the later passes (all but the kept low bits: 4 for complex64, 3
+// for complex128).  Other masks run the generic body (AM = 0).
+template <int K>
+constexpr uint32_t act_full()
 {
-    using T = Tile<K, LOGR>;
-    if constexpr (T::NA >= 3) return !(a.active & T::newbits(1));
-    else return false;
+    return (1u << K) - 1u;
+}
+template <typename R, int K>
+constexpr uint32_t act_later()
+{
+    return act_full<K>() & ~((1u << (sizeof(R) == 4 ? 4 : 3)) - 1u);
 }
 
-template <typename R, int K, int LOGR, bool CONTIG, bool PL = false, int SKIP = 0>
+template <typename R, int K, int LOGR, bool CONTIG, bool PL = false, uint32_t AM = 0>
 __device__ __forceinline__ void fwd_body(cx<R> *psi, const cx<R> *src, const FusedArgs &a,
                                          u64 t0, u64 tstep, cx<R> *lds)
 {
@@ -633,13 +652,13 @@ __device__ __forceinline__ void fwd_body(cx<R> *psi, const cx<R> *src, const Fus
     mst.init(a.pos + ST);
     P0Diag<R, K, LOGR> pd;
     if (a.in_mode != IN_LOAD) pd.init(a.dt, t);
-    const RyC<R, K> rc(a, a.layer);
+    const RyC<R, K, AM> rc(a, a.layer);
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> v[T::NR];
         load_tile<R, K, LOGR, CONTIG, PL>(v, src, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
-        fwd_assign<R, K, LOGR, 0>(v, a, rc);
-        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1, SKIP>::run(v, lds, t, a, rc);
+        fwd_assign<R, K, LOGR, 0, AM>(v, a, rc);
+        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1, AM>::run(v, lds, t, a, rc);
         cx<R> *pp = psi + fresh(base | toff_st);
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) pp[mst.off(r)] = v[r];
@@ -651,12 +670,14 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_pass(void *psi_, const 
                                                               FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
-    if (mid_idle<K, LOGR>(a))
-        fwd_body<R, K, LOGR, CONTIG, false, 2>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
-                                               gridDim.x, lds);
+    const int b = blockIdx.x, g = gridDim.x;
+    constexpr uint32_t F = act_full<K>(), L = act_later<R, K>();
+    if (a.active == F)
+        fwd_body<R, K, LOGR, CONTIG, false, F>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
+    else if (a.active == L)
+        fwd_body<R, K, LOGR, CONTIG, false, L>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
     else
-        fwd_body<R, K, LOGR, CONTIG, false, 0>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
-                                               gridDim.x, lds);
+        fwd_body<R, K, LOGR, CONTIG, false, 0>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
 }
 
 // the same for a plain load (no diagonal on load, no generated layer)
@@ -665,12 +686,14 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_load_pass(void *psi_, c
                                                                    FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
-    if (mid_idle<K, LOGR>(a))
-        fwd_body<R, K, LOGR, CONTIG, true, 2>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
-                                           gridDim.x, lds);
+    const int b = blockIdx.x, g = gridDim.x;
+    constexpr uint32_t F = act_full<K>(), L = act_later<R, K>();
+    if (a.active == F)
+        fwd_body<R, K, LOGR, CONTIG, true, F>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
+    else if (a.active == L)
+        fwd_body<R, K, LOGR, CONTIG, true, L>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
     else
-        fwd_body<R, K, LOGR, CONTIG, true, 0>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
-                                           gridDim.x, lds);
+        fwd_body<R, K, LOGR, CONTIG, true, 0>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
 }
 
 // Block sums of the gradient partials of the pass's active tile qubits for
@@ -705,7 +728,7 @@ __device__ __forceinline__ void write_partials(const double (&accY)[K], const do
 // RZ partials of the active tile qubits in assignment AI: per register bit
 // the signed sum of Im(conj(lam_i) phi_i), and the thread's total (its sign
 // per thread bit is applied at the block sum)
-template <typename R, int K, int LOGR, int AI>
+template <typename R, int K, int LOGR, int AI, uint32_t AM>
 __device__ __forceinline__ void z_partials(const cx<R> (&f)[1 << LOGR], const cx<R> (&l)[1 << LOGR],
                                            double (&accZr)[LOGR], double &ztot, const FusedArgs &a)
 {
@@ -720,7 +743,7 @@ __device__ __forceinline__ void z_partials(const cx<R> (&f)[1 << LOGR], const cx
     ztot += (double)tsum;
 #pragma unroll
     for (int k = 0; k < LOGR; ++k) {
-        if (!((a.active >> (LZ + k)) & 1)) continue;
+        if (!on<AM>(a, LZ + k)) continue;
         R s = 0;
 #pragma unroll
         for (int r = 0; r < NR; ++r) s += ((r >> k) & 1) ? -tt[r] : tt[r];
@@ -730,7 +753,7 @@ __device__ __forceinline__ void z_partials(const cx<R> (&f)[1 << LOGR], const cx
 
 // LDG: both vectors first lose the diagonal of `layer` in the load layout
 // (a.ld), for the reverse of a two-layer pass.
-template <typename R, int K, int LOGR, bool CONTIG, bool LDG, int SKIP = 0>
+template <typename R, int K, int LOGR, bool CONTIG, bool LDG, uint32_t AM = 0>
 __device__ __forceinline__ void bwd_body(const cx<R> *phi_in, cx<R> *phi, cx<R> *lam,
                                          const FusedArgs &a, u64 t0, u64 tstep, int col,
                                          cx<R> *lds, double *sh)
@@ -753,7 +776,7 @@ __device__ __forceinline__ void bwd_body(const cx<R> *phi_in, cx<R> *phi, cx<R> 
 #pragma unroll
     for (int k = 0; k < LOGR; ++k) accZr[k] = 0.0;
 
-    const RyC<R, K> rc(a, a.layer);
+    const RyC<R, K, AM> rc(a, a.layer);
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> f[T::NR], l[T::NR];
@@ -786,9 +809,9 @@ __device__ __forceinline__ void bwd_body(const cx<R> *phi_in, cx<R> *phi, cx<R> 
             }
         }
         // RZ gradients of the active tile qubits: sum_i z_q(i) Im(conj(lam_i) phi_i)
-        z_partials<R, K, LOGR, 0>(f, l, accZr, ztot, a);
-        bwd_assign<R, K, LOGR, 0>(f, l, accY, a, rc);
-        if constexpr (T::NA > 1) BwdChain<R, K, LOGR, 1, SKIP>::run(f, l, accY, lds, t, a, rc);
+        z_partials<R, K, LOGR, 0, AM>(f, l, accZr, ztot, a);
+        bwd_assign<R, K, LOGR, 0, AM>(f, l, accY, a, rc);
+        if constexpr (T::NA > 1) BwdChain<R, K, LOGR, 1, AM>::run(f, l, accY, lds, t, a, rc);
         const u64 o = fresh(base | toff_st);
         cx<R> *pf = phi + o, *pl = lam + o;
 #pragma unroll
@@ -806,12 +829,14 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const void *phi_in
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
-    if (mid_idle<K, LOGR>(a))
-        bwd_body<R, K, LOGR, CONTIG, false, 2>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_, a,
-                                            blockIdx.x, gridDim.x, blockIdx.x, lds, sh);
+    const int b = blockIdx.x, g = gridDim.x;
+    constexpr uint32_t L = act_later<R, K>() | kActRuntime;
+    if (a.active == (L & ~kActRuntime))
+        bwd_body<R, K, LOGR, CONTIG, false, L>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_,
+                                               a, b, g, b, lds, sh);
     else
-        bwd_body<R, K, LOGR, CONTIG, false, 0>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_, a,
-                                            blockIdx.x, gridDim.x, blockIdx.x, lds, sh);
+        bwd_body<R, K, LOGR, CONTIG, false, 0>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_,
+                                               a, b, g, b, lds, sh);
 }
 
 // the reverse pass that first undoes the layer diagonal given in a.ld
@@ -821,12 +846,14 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_ld_pass(const void *phi
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
-    if (mid_idle<K, LOGR>(a))
-        bwd_body<R, K, LOGR, CONTIG, true, 2>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_, a,
-                                           blockIdx.x, gridDim.x, blockIdx.x, lds, sh);
+    const int b = blockIdx.x, g = gridDim.x;
+    constexpr uint32_t L = act_later<R, K>() | kActRuntime;
+    if (a.active == (L & ~kActRuntime))
+        bwd_body<R, K, LOGR, CONTIG, true, L>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_,
+                                              a, b, g, b, lds, sh);
     else
-        bwd_body<R, K, LOGR, CONTIG, true, 0>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_, a,
-                                           blockIdx.x, gridDim.x, blockIdx.x, lds, sh);
+        bwd_body<R, K, LOGR, CONTIG, true, 0>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_,
+                                              a, b, g, b, lds, sh);
 }
 
 // Reverse pass that does not write phi back: every RY and RZ partial of the
@@ -835,7 +862,7 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_ld_pass(const void *phi
 // which commutes with Y_q), visiting the assignments 0 .. NA-1 with both
 // vectors; then lam alone is rotated back through NA-1 .. 0 and stored in
 // the load layout.  phi dies after the partials.
-template <typename R, int K, int LOGR, bool CONTIG, bool LDG, int SKIP = 0>
+template <typename R, int K, int LOGR, bool CONTIG, bool LDG, uint32_t AM = 0>
 __device__ __forceinline__ void bwd_gf_body(const cx<R> *phi_in, cx<R> *lam, const FusedArgs &a,
                                             u64 t0, u64 tstep, int col, cx<R> *lds, double *sh)
 {
@@ -854,7 +881,7 @@ __device__ __forceinline__ void bwd_gf_body(const cx<R> *phi_in, cx<R> *lam, con
 #pragma unroll
     for (int k = 0; k < LOGR; ++k) accZr[k] = 0.0;
 
-    const RyC<R, K> rc(a, a.layer);
+    const RyC<R, K, AM> rc(a, a.layer);
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         const cx<R> *fp = phi_in + (base | toff_ld);
@@ -879,11 +906,11 @@ __device__ __forceinline__ void bwd_gf_body(const cx<R> *phi_in, cx<R> *lam, con
                 l[r] = cmul_conj(l[r], d);
             }
         }
-        z_partials<R, K, LOGR, 0>(f, l, accZr, ztot, a);
-        ygrad_assign<R, K, LOGR, 0>(f, l, accY, a);
-        if constexpr (T::NA > 1) GradChain<R, K, LOGR, 1, SKIP>::run(f, l, accY, lds, t, a);
-        inv_assign<R, K, LOGR, T::NA - 1>(l, a, rc);
-        if constexpr (T::NA > 1) InvChainRev<R, K, LOGR, T::NA - 2, SKIP>::run(l, lds, t, a, rc);
+        z_partials<R, K, LOGR, 0, AM>(f, l, accZr, ztot, a);
+        ygrad_assign<R, K, LOGR, 0, AM>(f, l, accY, a);
+        if constexpr (T::NA > 1) GradChain<R, K, LOGR, 1, AM>::run(f, l, accY, lds, t, a);
+        inv_assign<R, K, LOGR, T::NA - 1, AM>(l, a, rc);
+        if constexpr (T::NA > 1) InvChainRev<R, K, LOGR, T::NA - 2, AM>::run(l, lds, t, a, rc);
         cx<R> *ls = lam + fresh(base | toff_ld);
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) ls[mld.off(r)] = l[r];
@@ -897,12 +924,14 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_gf_pass(const void *phi
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
-    if (mid_idle<K, LOGR>(a))
-        bwd_gf_body<R, K, LOGR, CONTIG, false, 2>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, blockIdx.x,
-                                               gridDim.x, blockIdx.x, lds, sh);
+    const int b = blockIdx.x, g = gridDim.x;
+    constexpr uint32_t L = act_later<R, K>() | kActRuntime;
+    if (a.active == (L & ~kActRuntime))
+        bwd_gf_body<R, K, LOGR, CONTIG, false, L>((const cx<R> *)phi_in_, (cx<R> *)lam_,
+                                                  a, b, g, b, lds, sh);
     else
-        bwd_gf_body<R, K, LOGR, CONTIG, false, 0>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, blockIdx.x,
-                                               gridDim.x, blockIdx.x, lds, sh);
+        bwd_gf_body<R, K, LOGR, CONTIG, false, 0>((const cx<R> *)phi_in_, (cx<R> *)lam_,
+                                                  a, b, g, b, lds, sh);
 }
 
 template <typename R, int K, int LOGR, bool CONTIG>
@@ -911,12 +940,14 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_gf_ld_pass(const void *
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
-    if (mid_idle<K, LOGR>(a))
-        bwd_gf_body<R, K, LOGR, CONTIG, true, 2>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, blockIdx.x,
-                                              gridDim.x, blockIdx.x, lds, sh);
+    const int b = blockIdx.x, g = gridDim.x;
+    constexpr uint32_t L = act_later<R, K>() | kActRuntime;
+    if (a.active == (L & ~kActRuntime))
+        bwd_gf_body<R, K, LOGR, CONTIG, true, L>((const cx<R> *)phi_in_, (cx<R> *)lam_,
+                                                 a, b, g, b, lds, sh);
     else
-        bwd_gf_body<R, K, LOGR, CONTIG, true, 0>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, blockIdx.x,
-                                              gridDim.x, blockIdx.x, lds, sh);
+        bwd_gf_body<R, K, LOGR, CONTIG, true, 0>((const cx<R> *)phi_in_, (cx<R> *)lam_,
+                                                 a, b, g, b, lds, sh);
 }
 
 // Last forward pass of the last layer + energy + first reverse pass, for a
@@ -929,7 +960,7 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_gf_ld_pass(const void *
 // here: Im(conj(D_i psi_i) psi_i) = 0.  When this is the layer's only pass,
 // the load applies the previous layer's diagonal (or generates the first
 // layer's state).
-template <typename R, int K, int LOGR, bool CONTIG, bool PL, int SKIP = 0>
+template <typename R, int K, int LOGR, bool CONTIG, bool PL, uint32_t AM = 0>
 __device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const FusedArgs &a,
                                           u64 t0, u64 tstep, int col, cx<R> *lds, double *sh)
 {
@@ -947,13 +978,13 @@ __device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const Fu
     for (int j = 0; j < K; ++j) accY[j] = 0.0;
     double eacc = 0.0;
 
-    const RyC<R, K> rc(a, a.layer);
+    const RyC<R, K, AM> rc(a, a.layer);
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> f[T::NR], l[T::NR];
         load_tile<R, K, LOGR, CONTIG, PL>(f, psi, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
-        fwd_assign<R, K, LOGR, 0>(f, a, rc);
-        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1, SKIP>::run(f, lds, t, a, rc);
+        fwd_assign<R, K, LOGR, 0, AM>(f, a, rc);
+        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1, AM>::run(f, lds, t, a, rc);
         // energy and lam in the last assignment's layout
         R et = 0;
 #pragma unroll
@@ -965,10 +996,11 @@ __device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const Fu
             l[r].im = (R)d * f[r].im;
         }
         eacc += (double)et;
-        ygrad_assign<R, K, LOGR, T::NA - 1>(f, l, accY, a);
-        if constexpr (T::NA > 1) GradChainRev<R, K, LOGR, T::NA - 2, SKIP>::run(f, l, accY, lds, t, a);
-        inv_assign<R, K, LOGR, 0>(l, a, rc);
-        if constexpr (T::NA > 1) InvChain<R, K, LOGR, 1, SKIP>::run(l, lds, t, a, rc);
+        ygrad_assign<R, K, LOGR, T::NA - 1, AM>(f, l, accY, a);
+        if constexpr (T::NA > 1)
+            GradChainRev<R, K, LOGR, T::NA - 2, AM>::run(f, l, accY, lds, t, a);
+        inv_assign<R, K, LOGR, 0, AM>(l, a, rc);
+        if constexpr (T::NA > 1) InvChain<R, K, LOGR, 1, AM>::run(l, lds, t, a, rc);
         cx<R> *pl = lam + fresh(base | toff_st);
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) pl[mst.off(r)] = l[r];
@@ -987,12 +1019,17 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_pass(const void *psi_,
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
-    if (mid_idle<K, LOGR>(a))
-        turn_body<R, K, LOGR, CONTIG, false, 2>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x,
-                                             gridDim.x, blockIdx.x, lds, sh);
+    const int b = blockIdx.x, g = gridDim.x;
+    constexpr uint32_t F = act_full<K>(), L = act_later<R, K>();
+    if (a.active == F)
+        turn_body<R, K, LOGR, CONTIG, false, F>((const cx<R> *)psi_, (cx<R> *)lam_,
+                                                a, b, g, b, lds, sh);
+    else if (a.active == L)
+        turn_body<R, K, LOGR, CONTIG, false, L>((const cx<R> *)psi_, (cx<R> *)lam_,
+                                                a, b, g, b, lds, sh);
     else
-        turn_body<R, K, LOGR, CONTIG, false, 0>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x,
-                                             gridDim.x, blockIdx.x, lds, sh);
+        turn_body<R, K, LOGR, CONTIG, false, 0>((const cx<R> *)psi_, (cx<R> *)lam_,
+                                                a, b, g, b, lds, sh);
 }
 
 // Plain-load turnaround for 12-bit tiles, run by 512 threads holding 8
@@ -1003,12 +1040,14 @@ __global__ __launch_bounds__(512) void k_turn_load_pass(const void *psi_, void *
 {
     __shared__ cx<R> lds[Tile<12, 3>::LDS];
     __shared__ double sh[512 / 64 + 1];
-    if (mid_idle<12, 3>(a))
-        turn_body<R, 12, 3, true, true, 2>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x,
-                                           gridDim.x, blockIdx.x, lds, sh);
+    const int b = blockIdx.x, g = gridDim.x;
+    constexpr uint32_t F = act_full<12>(), L = act_later<R, 12>();
+    if (a.active == F)
+        turn_body<R, 12, 3, true, true, F>((const cx<R> *)psi_, (cx<R> *)lam_, a, b, g, b, lds, sh);
+    else if (a.active == L)
+        turn_body<R, 12, 3, true, true, L>((const cx<R> *)psi_, (cx<R> *)lam_, a, b, g, b, lds, sh);
     else
-        turn_body<R, 12, 3, true, true, 0>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x,
-                                           gridDim.x, blockIdx.x, lds, sh);
+        turn_body<R, 12, 3, true, true, 0>((const cx<R> *)psi_, (cx<R> *)lam_, a, b, g, b, lds, sh);
 }
 
 
@@ -1019,7 +1058,7 @@ __global__ __launch_bounds__(512) void k_turn_load_pass(const void *psi_, void *
 // gates through the assignments 0 .. NA-1, the first layer's diagonal in
 // the last assignment, then the second layer's RY gates back through
 // NA-1 .. 0, and the tile is stored in the load layout.
-template <typename R, int K, int LOGR, bool CONTIG, bool PL, int SKIP = 0>
+template <typename R, int K, int LOGR, bool CONTIG, bool PL, uint32_t AM = 0>
 __device__ __forceinline__ void fwd2_body(cx<R> *psi, const cx<R> *src, const FusedArgs &a,
                                           u64 t0, u64 tstep, cx<R> *lds)
 {
@@ -1032,19 +1071,19 @@ __device__ __forceinline__ void fwd2_body(cx<R> *psi, const cx<R> *src, const Fu
     P0Diag<R, K, LOGR> pd;
     if (a.in_mode != IN_LOAD) pd.init(a.dt, t);
     LDiag<R, K, LOGR> dg;
-    const RyC<R, K> rc(a, a.layer);
-    const RyC<R, K> rc2(a, a.layer2);
+    const RyC<R, K, AM> rc(a, a.layer);
+    const RyC<R, K, AM> rc2(a, a.layer2);
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> v[T::NR];
         load_tile<R, K, LOGR, CONTIG, PL>(v, src, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
-        fwd_assign<R, K, LOGR, 0>(v, a, rc);
-        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1, SKIP>::run(v, lds, t, a, rc);
+        fwd_assign<R, K, LOGR, 0, AM>(v, a, rc);
+        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1, AM>::run(v, lds, t, a, rc);
         dg.tile(a.ld, tile, base | toff_st, t);
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) v[r] = cmul(v[r], dg.at(a.ld, r));
-        fwd_assign<R, K, LOGR, T::NA - 1>(v, a, rc2);
-        if constexpr (T::NA > 1) FwdChainRev<R, K, LOGR, T::NA - 2, SKIP>::run(v, lds, t, a, rc2);
+        fwd_assign<R, K, LOGR, T::NA - 1, AM>(v, a, rc2);
+        if constexpr (T::NA > 1) FwdChainRev<R, K, LOGR, T::NA - 2, AM>::run(v, lds, t, a, rc2);
         cx<R> *pp = psi + fresh(base | toff_ld);
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) pp[mld.off(r)] = v[r];
@@ -1056,12 +1095,14 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd2_pass(void *psi_, const
                                                                FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
-    if (mid_idle<K, LOGR>(a))
-        fwd2_body<R, K, LOGR, CONTIG, false, 2>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
-                                             gridDim.x, lds);
+    const int b = blockIdx.x, g = gridDim.x;
+    constexpr uint32_t F = act_full<K>(), L = act_later<R, K>();
+    if (a.active == F)
+        fwd2_body<R, K, LOGR, CONTIG, false, F>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
+    else if (a.active == L)
+        fwd2_body<R, K, LOGR, CONTIG, false, L>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
     else
-        fwd2_body<R, K, LOGR, CONTIG, false, 0>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
-                                             gridDim.x, lds);
+        fwd2_body<R, K, LOGR, CONTIG, false, 0>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
 }
 
 template <typename R, int K, int LOGR, bool CONTIG>
@@ -1069,12 +1110,14 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd2_load_pass(void *psi_, 
                                                                     FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
-    if (mid_idle<K, LOGR>(a))
-        fwd2_body<R, K, LOGR, CONTIG, true, 2>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
-                                            gridDim.x, lds);
+    const int b = blockIdx.x, g = gridDim.x;
+    constexpr uint32_t F = act_full<K>(), L = act_later<R, K>();
+    if (a.active == F)
+        fwd2_body<R, K, LOGR, CONTIG, true, F>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
+    else if (a.active == L)
+        fwd2_body<R, K, LOGR, CONTIG, true, L>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
     else
-        fwd2_body<R, K, LOGR, CONTIG, true, 0>((cx<R> *)psi_, (const cx<R> *)src_, a, blockIdx.x,
-                                            gridDim.x, lds);
+        fwd2_body<R, K, LOGR, CONTIG, true, 0>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
 }
 
 // ------------------------------------------------ first-layer gradients
