@@ -44,7 +44,7 @@ KERNELS = {
     "forward_pass": "k_fwd_load_pass<float,12,4>", "forward_pass2": "k_fwd2_load_pass<float,12,4>",
     "backward_pass": "k_bwd_pass<float,12,4>", "backward_ld": "k_bwd_ld_pass<float,12,4>",
     "backward_gf": "k_bwd_gf_pass<float,12,4>", "backward_gf_ld": "k_bwd_gf_ld_pass<float,12,4>",
-    "turnaround": "k_turn_load_pass<float>", "first_layer": "k_layer0_grad<float,12,4>",
+    "turnaround": "k_turn_load_pass<float,12,4>", "first_layer": "k_layer0_grad<float,12,4>",
     "energy": "k_energy_diag<float>", "offdiag": "k_offdiag_pass<float,12,4>",
 }
 

@@ -1032,24 +1032,25 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_pass(const void *psi_,
                                                 a, b, g, b, lds, sh);
 }
 
-// Plain-load turnaround for 12-bit tiles, run by 512 threads holding 8
-// amplitudes each (4 assignments): fewer registers per thread keeps two
-// waves per SIMD resident without spilling.
-template <typename R>
-__global__ __launch_bounds__(512) void k_turn_load_pass(const void *psi_, void *lam_, FusedArgs a)
+// the same for a plain load (the layer's last pass is not its only one)
+template <typename R, int K, int LOGR, bool CONTIG>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_load_pass(const void *psi_, void *lam_,
+                                                                    FusedArgs a)
 {
-    __shared__ cx<R> lds[Tile<12, 3>::LDS];
-    __shared__ double sh[512 / 64 + 1];
+    __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
+    __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
     const int b = blockIdx.x, g = gridDim.x;
-    constexpr uint32_t F = act_full<12>(), L = act_later<R, 12>();
+    constexpr uint32_t F = act_full<K>(), L = act_later<R, K>();
     if (a.active == F)
-        turn_body<R, 12, 3, true, true, F>((const cx<R> *)psi_, (cx<R> *)lam_, a, b, g, b, lds, sh);
+        turn_body<R, K, LOGR, CONTIG, true, F>((const cx<R> *)psi_, (cx<R> *)lam_,
+                                               a, b, g, b, lds, sh);
     else if (a.active == L)
-        turn_body<R, 12, 3, true, true, L>((const cx<R> *)psi_, (cx<R> *)lam_, a, b, g, b, lds, sh);
+        turn_body<R, K, LOGR, CONTIG, true, L>((const cx<R> *)psi_, (cx<R> *)lam_,
+                                               a, b, g, b, lds, sh);
     else
-        turn_body<R, 12, 3, true, true, 0>((const cx<R> *)psi_, (cx<R> *)lam_, a, b, g, b, lds, sh);
+        turn_body<R, K, LOGR, CONTIG, true, 0>((const cx<R> *)psi_, (cx<R> *)lam_,
+                                               a, b, g, b, lds, sh);
 }
-
 
 // ------------------------------------------------------ two-layer passes
 
@@ -2246,14 +2247,8 @@ hipError_t fused_turnaround(int prec, const void *psi, void *lam, const double *
     a.part = part;
     a.epart = epart;
     a.grid = grid;
-    if (plan.K == 12 && in_mode == IN_LOAD) {
-        if (prec == GV_C64)
-            hipLaunchKernelGGL(k_turn_load_pass<float>, dim3(grid), dim3(512), 0, s, psi, lam, a);
-        else
-            hipLaunchKernelGGL(k_turn_load_pass<double>, dim3(grid), dim3(512), 0, s, psi, lam, a);
-    } else {
-        GV_LAUNCH_K(k_turn_pass, prec, grid, plan.K, psi, lam, a);
-    }
+    if (in_mode == IN_LOAD) GV_LAUNCH_K(k_turn_load_pass, prec, grid, plan.K, psi, lam, a);
+    else GV_LAUNCH_K(k_turn_pass, prec, grid, plan.K, psi, lam, a);
     return hipGetLastError();
 }
 
