@@ -126,8 +126,9 @@ Chunks make_chunks(int n, int K, int LOGR)
     return c;
 }
 
-static const int kEnergyGrid = 1024;  // blocks of the stand-alone energy kernels
+static const int kEnergyGrid = 3072;  // blocks of the energy and off-diagonal kernels
 static const int kPartCols = 4096;    // energy-partial columns the work buffer holds
+static_assert(kEnergyGrid <= kPartCols, "energy partials must fit the work buffer");
 
 static int choose_K(int n) { return n >= 12 ? 12 : (n >= 10 ? 10 : 8); }
 static int choose_logr(int K) { return K == 8 ? 3 : 4; }

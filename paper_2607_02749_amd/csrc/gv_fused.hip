@@ -2311,7 +2311,8 @@ hipError_t offdiag_pass(int prec, const void *psi, void *lam, int n, int K, cons
     a.terms = terms;
     a.epart = epart;
     a.estride = estride;
-    const u64 want = prec == GV_C64 ? 1024 : 512;
+    // three resident blocks per CU, four rounds (as the fused passes)
+    const u64 want = prec == GV_C64 ? 3072 : 512;
     const int grid = (int)(a.ntiles < want ? a.ntiles : want);
     if (grid > estride) return hipErrorInvalidValue;
     switch (K) {
