@@ -191,7 +191,7 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *params_dev,
  * persistent kernel: each block of the grid takes whole instances from an
  * atomic queue (largest first by default) and runs their forward sweep,
  * energy and reverse sweep.  Instances with n >= split_n instead run as
- * whole-GPU tile passes (the path of gv_energy_grad, uncompute mode) on
+ * whole-GPU tile passes (the path of gv_energy_grad, store mode) on
  * side streams forked from and joined back to the batch's stream, alongside
  * the persistent kernel, so one large instance is not left to a single
  * compute unit.  Grid, order and split come from gv_batch_tuning (an

@@ -124,7 +124,7 @@ BatchLayout batch_layout(int count, const gv_instance *inst, gv_precision prec, 
         size_t fw = 0, mk = 0;
         if (a.n >= split) {
             WorkLayout wl;
-            if (work_layout(a, prec, GV_ENGINE_FUSED, GV_GRAD_UNCOMPUTE, &wl) == GV_OK) fw = wl.total;
+            if (work_layout(a, prec, GV_ENGINE_FUSED, GV_GRAD_STORE, &wl) == GV_OK) fw = wl.total;
             mk = (size_t)2 * a.n * R;
         }
         L.fwork.push_back(off);
@@ -160,7 +160,7 @@ gv_status launch_all(gv_batch b, hipStream_t s)
         st.stream = b->side[j % kSideStreams];
         const gv_instance &I = b->large[j];
         if (gv_status r = gv_energy_grad(&st, I.h, I.params_dev, &I.ansatz, b->masks[j],
-                                         GV_GRAD_UNCOMPUTE, I.energy_dev, I.grad_dev))
+                                         GV_GRAD_STORE, I.energy_dev, I.grad_dev))
             return r;
     }
     if (fork) {
