@@ -1943,12 +1943,12 @@ DiagTab make_diagtab(const gv_ansatz &an, const Chunks &ch, const void *tab, boo
         bool dup = false;
         for (int k = 0; k < d.npair; ++k) dup |= d.pb[k] == q;
         if (dup) continue;
-        d.pa[d.npair] = (int8_t)(q - 1);
-        d.pb[d.npair++] = (int8_t)q;
+        d.pa[d.npair] = q - 1;
+        d.pb[d.npair++] = q;
     }
     // the circular pair (n-1, 0) lies inside a chunk only when chunk 0 holds every bit
     if (an.ent == GV_ENT_CZ_CIRCULAR && n > 2 && ch.b[1] < n) {
-        d.pa[d.npair] = (int8_t)(n - 1);
+        d.pa[d.npair] = n - 1;
         d.pb[d.npair++] = 0;
     }
     return d;
@@ -2190,10 +2190,10 @@ hipError_t make_ldiag(int prec, const gv_ansatz &an, const TilePlan &plan, int p
     auto add = [&](int qa, int qb) {
         if (group[qa] == group[qb]) return true;
         if (d.npair >= kMaxLPairs) return false;
-        d.pa[d.npair] = (int8_t)qa;
-        d.pb[d.npair] = (int8_t)qb;
-        d.ka[d.npair] = (int8_t)regbit[qa];
-        d.kb[d.npair] = (int8_t)regbit[qb];
+        d.pa[d.npair] = qa;
+        d.pb[d.npair] = qb;
+        d.ka[d.npair] = regbit[qa];
+        d.kb[d.npair] = regbit[qb];
         ++d.npair;
         return true;
     };

@@ -141,7 +141,7 @@ struct DiagTab {
     int off1, off2, off3;
     u64 m0, m1, m2;
     int npair;
-    int8_t pa[4], pb[4];
+    int pa[4], pb[4];        // 32-bit so the per-tile loop reads them with scalar loads
 };
 
 // Diagonal of one rotation layer (its RZ gates and CZ ladder) in the register
@@ -156,8 +156,10 @@ struct LDiagTab {
     int offR, offB1, offB2;
     int h1;
     int npair;
-    int8_t pa[kMaxLPairs], pb[kMaxLPairs];
-    int8_t ka[kMaxLPairs], kb[kMaxLPairs];
+    // 32-bit entries: the per-tile loop over the pairs then reads them with
+    // scalar loads (byte entries go through vector loads and a wait each)
+    int pa[kMaxLPairs], pb[kMaxLPairs];
+    int ka[kMaxLPairs], kb[kMaxLPairs];
 };
 
 // What the table kernel needs to fill one LDiagTab: the qubit of every
