@@ -59,9 +59,11 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mode", default="store", choices=["uncompute", "checkpoint", "recompute", "store"])
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also time a 2 GiB device-to-device copy (the practical HBM ceiling, and "
-                         "the reference kernel for scaling byte counters)")
+    ap.add_argument("--no-copy-probe", action="store_true",
+                    help="skip the streaming-kernel ceiling (hand-written read / write / copy / "
+                         "read-modify-write kernels over 2 GiB buffers)")
+    ap.add_argument("--stream-sweep", default=None,
+                    help="write every streaming-kernel measurement of a wider sweep to this JSON file")
     return ap.parse_args()
 
 
@@ -182,22 +184,55 @@ def cpu_baseline(inst):
     }
 
 
-def copy_probe(torch):
-    src = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")
-    dst = torch.empty_like(src)
-    src.fill_(1)
-    dst.copy_(src)
-    torch.cuda.synchronize()
+def copy_probe(torch, gv, full=False):
+    """Practical HBM ceiling: hand-written streaming kernels (gv_stream_probe)
+    over 2 GiB buffers, for read, write, copy, read-modify-write (two streams
+    read, one written back: the reverse passes' pattern) and triad, swept over
+    bytes per lane, accesses in flight per lane, non-temporal hints and grid
+    size; plus torch's own device copy.  Returns the best configuration per
+    pattern (and every measurement when full)."""
+    nb = 1 << 31
+    bufs = [torch.empty(nb, dtype=torch.uint8, device="cuda") for _ in range(3)]
+    for b in bufs:
+        b.fill_(0)
+    moved = {"read": 1, "write": 1, "copy": 2, "rmw": 3, "triad": 3}
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(5):
-        dst.copy_(src)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / 5
-    del src, dst
+
+    def timed(fn, reps=3):
+        fn()
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    rows = []
+    widths, unrolls, grids = (8, 16), (1, 2, 4, 8), (0, 1024, 2048, 4096)
+    if not full:
+        widths, unrolls, grids = (8, 16), (2, 4, 8), (0, 2048)
+    for kind in ("read", "write", "copy", "rmw", "triad"):
+        for w in widths:
+            for u in unrolls:
+                for nt in (0, 1):
+                    for g in grids:
+                        ms = timed(lambda: gv.stream_probe(kind, w, u, nt, g, bufs[0], bufs[1],
+                                                           bufs[2], nb))
+                        rows.append({"kind": kind, "width": w, "unroll": u, "nontemporal": nt,
+                                     "grid": g, "ms": ms,
+                                     "GBps": moved[kind] * nb / (ms * 1e-3) / 1e9})
+    best = {}
+    for r in rows:
+        if r["kind"] not in best or r["GBps"] > best[r["kind"]]["GBps"]:
+            best[r["kind"]] = r
+    ms = timed(lambda: bufs[0].copy_(bufs[1]), 5)
+    out = {"bytes_per_buffer": nb, "best": best,
+           "torch_copy": {"ms": ms, "GBps": 2 * nb / (ms * 1e-3) / 1e9}}
+    if full:
+        out["all"] = rows
+    del bufs
     torch.cuda.empty_cache()
-    return {"bytes": 2 * (1 << 31), "ms": ms, "GBps": 2 * (1 << 31) / (ms * 1e-3) / 1e9}
+    return out
 
 
 def bench_n28(args, torch, gv, synth):
@@ -206,7 +241,14 @@ def bench_n28(args, torch, gv, synth):
     m, h = measure(inst, args.mode, args.steps, args.warmup)
     log("timed", args.steps, "steps in", m["wall"], "s")
     roof, breakdown = roofline(m["prof"], args.steps)
-    copy = copy_probe(torch) if args.copy_probe else None
+    copy = None
+    if not args.no_copy_probe:
+        copy = copy_probe(torch, gv, full=args.stream_sweep is not None)
+        if args.stream_sweep:
+            with open(args.stream_sweep, "w") as f:
+                json.dump(copy, f, indent=1)
+            copy.pop("all", None)
+        log("copy probe", {k: round(v["GBps"]) for k, v in copy["best"].items()})
 
     parity = None
     gold_path = os.path.join(ROOT, "tests", "golden", "oracle_n28.json")

@@ -110,14 +110,19 @@ const char *gv_last_error(void);
  * ansatz is invalid. */
 int64_t gv_num_params(const gv_ansatz *ansatz);
 
-/* Buffer sizes for a state that will run `ansatz` in `prec` with gradient
- * mode `mode` on `engine`: state_bytes = 2^n amplitudes; work_bytes = the
- * workspace gv_energy_grad needs (adjoint vector, checkpoints, tables,
- * reduction partials).  Either output pointer may be NULL. */
+/* Buffer sizes for a state that will run `ansatz` (Sec. IV-B, Eq. 8) in
+ * `prec` with gradient mode `mode` on `engine`: state_bytes = 2^n
+ * amplitudes; work_bytes = the workspace gv_energy_grad needs (adjoint
+ * vector, stored states of the mode, tables, reduction partials);
+ * diag_bytes = the FP64 diagonal of a Hamiltonian's Z-only part on n qubits
+ * (2^n doubles; gv_pauli_sum_device_bytes adds the off-diagonal tables of a
+ * given Hamiltonian).  Any output pointer may be NULL. */
 gv_status gv_query_sizes(const gv_ansatz *ansatz, gv_precision prec, gv_engine engine,
-                         gv_grad_mode mode, size_t *state_bytes, size_t *work_bytes);
+                         gv_grad_mode mode, size_t *state_bytes, size_t *work_bytes,
+                         size_t *diag_bytes);
 
-/* Create a state over caller-owned device memory.
+/* Create a state of n qubits (the register the ansatz of Sec. IV-B acts on)
+ * over caller-owned device memory.
  *   amps_dev / amps_bytes: >= 2^n amplitudes of `prec`, 256-byte aligned;
  *   work_dev / work_bytes: workspace (may be NULL/0 when only gv_apply_ansatz
  *                          and gv_energy are used with the PLAIN engine);
@@ -151,7 +156,7 @@ gv_status gv_pauli_sum_info(gv_pauli_sum h, int64_t *n_diag, int64_t *n_offdiag,
  * (2^n doubles) followed by the off-diagonal term tables. */
 gv_status gv_pauli_sum_device_bytes(gv_pauli_sum h, size_t *bytes);
 
-/* Build the device form of H into caller memory `dev` (>= device_bytes,
+/* Build the device form of H (Eq. 6) into caller memory `dev` (>= device_bytes,
  * 256-byte aligned): the diagonal D_i = sum_{k: x_k = 0} c_k (-1)^{|i & z_k|}
  * by an in-place fast Walsh-Hadamard transform, and the off-diagonal terms
  * grouped by flip mask into the tile passes of the state's engine and
@@ -165,7 +170,7 @@ gv_status gv_pauli_sum_prepare(gv_pauli_sum h, gv_state st, void *dev, size_t by
 gv_status gv_pauli_sum_prepare_for(gv_pauli_sum h, gv_precision prec, gv_engine engine,
                                    void *stream, void *dev, size_t bytes);
 
-/* <psi|H|psi> of the state's current psi.  energy_dev: 2 device doubles
+/* E = <psi|H|psi> of the state's current psi (Eq. 4).  energy_dev: 2 device doubles
  * (real part, imaginary part; the latter is rounding noise for real c_k).
  * Needs work memory for reduction partials (FUSED: always; PLAIN: >= 1 MiB). */
 gv_status gv_energy(gv_state st, gv_pauli_sum h, double *energy_dev);
@@ -199,14 +204,21 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *params_dev,
  * Limits: 12 <= n <= 30; CZ or no entangler; every Hamiltonian prepared with
  * gv_pauli_sum_prepare_for(h, prec, GV_ENGINE_FUSED, ...).
  */
+/* One instance: an ansatz, its angles and its Hamiltonian (the Hamiltonian's
+ * FP64 diagonal and off-diagonal tables live in the device buffer it was
+ * prepared into).  The block it updates is its gv_cluster. */
 typedef struct {
     gv_ansatz ansatz;
     const double *params_dev;  /* P = 2 n (layers + final_rotation) device doubles */
     gv_pauli_sum h;            /* prepared for the batch precision, fused engine */
-    uint64_t qubit_mask;       /* gradient for the RY/RZ angles of these qubits */
-    double *energy_dev;        /* out: 2 device doubles (re, im) */
-    double *grad_dev;          /* out: P device doubles, 0 outside qubit_mask */
 } gv_instance;
+
+/* Restricted update of Eq. 11: the gradient is computed for the RY and RZ
+ * angles of these qubits in every layer (2 |B| (layers + final_rotation)
+ * entries) and written as 0 elsewhere. */
+typedef struct {
+    uint64_t qubit_mask;
+} gv_cluster;
 
 typedef struct {
     int32_t blocks_per_cu;     /* persistent blocks per compute unit, 1..8 (default 2) */
@@ -222,20 +234,36 @@ typedef struct gv_batch_s *gv_batch;
  * tuning->split_n; tuning may be NULL for the defaults). */
 gv_status gv_batch_query(int32_t count, const gv_instance *inst, gv_precision prec,
                          const gv_batch_tuning *tuning, size_t *work_bytes);
-/* Plan a batch over caller memory `work` (256-byte aligned, >= query).
+/* Plan a batch over caller memory `work_dev` (256-byte aligned, >= query)
+ * (Sec. IV-D, Eq. 11).
+ *   clusters: count entries, or NULL for unrestricted gradients;
+ *   energies_dev: out, 2 * count device doubles, (re, im) of instance i at 2 i;
+ *   grads_dev: out, sum_i P_i device doubles, instance i's gradient at offset
+ *              sum_{j<i} P_j (0 outside its cluster).
  * tuning may be NULL.  use_graph != 0 records the launches once as a HIP
  * graph that gv_batch_run replays; between runs the caller may rewrite the
- * parameter arrays in place.  The instance array is copied; the pointers in
- * it must stay valid for the batch's lifetime. */
-gv_status gv_batch_create(int32_t count, const gv_instance *inst, gv_precision prec,
-                          const gv_batch_tuning *tuning, void *work_dev, size_t work_bytes,
-                          void *stream, int32_t use_graph, gv_batch *out);
+ * parameter arrays in place.  Waits for the stream (it stages the instance
+ * records into work_dev).  The instance and cluster arrays are copied; the
+ * device pointers, the Hamiltonian handles and their prepared device buffers
+ * must stay valid -- and the Hamiltonians must not be prepared again -- for
+ * the batch's lifetime (gv_batch_run checks the last point and returns
+ * GV_ESTATE). */
+gv_status gv_batch_create(int32_t count, const gv_instance *inst, const gv_cluster *clusters,
+                          gv_precision prec, const gv_batch_tuning *tuning, void *work_dev,
+                          size_t work_bytes, void *stream, int32_t use_graph,
+                          double *energies_dev, double *grads_dev, gv_batch *out);
 /* Enqueue one evaluation of every instance on the batch's stream. */
 gv_status gv_batch_run(gv_batch b);
 gv_status gv_batch_destroy(gv_batch b);
-/* create + run + destroy (no graph). */
-gv_status gv_batch_energy_grad(int32_t count, const gv_instance *inst, gv_precision prec,
-                               void *work_dev, size_t work_bytes, void *stream);
+/* One evaluation of every instance with the default tuning and no graph
+ * (Sec. IV-D, Eq. 11; arguments as gv_batch_create): waits for work already
+ * on `stream` while it stages the instance records, then enqueues the
+ * evaluation on `stream` and returns.  The whole-GPU instances run one after
+ * another on `stream` (no side streams), so nothing the call creates outlives
+ * it. */
+gv_status gv_batch_energy_grad(int32_t count, const gv_instance *inst, const gv_cluster *clusters,
+                               gv_precision prec, void *work_dev, size_t work_bytes, void *stream,
+                               double *energies_dev, double *grads_dev);
 
 /* ------------------------------------------------------------------------
  * Per-kernel-class timing.  While enabled, every launch of the state's
@@ -268,6 +296,31 @@ gv_status gv_profile_reset(gv_state st);
  * the last reset.  Any output pointer may be NULL. */
 gv_status gv_profile_read(gv_state st, int32_t kind, int64_t *launches, double *ms,
                           double *bytes);
+
+/* ------------------------------------------------------------------------
+ * Streaming-bandwidth probe (measurement only; no part of the method).
+ * Runs one perfectly coalesced streaming kernel over `bytes` bytes so the
+ * state-vector passes can be compared with what the device's HBM delivers to
+ * plain streams:
+ *   kind GV_STREAM_READ   reads src0;
+ *        GV_STREAM_WRITE  writes dst;
+ *        GV_STREAM_COPY   dst = src0;
+ *        GV_STREAM_RMW    dst = src0 + dst (two streams read, one written back,
+ *                         the pattern of a reverse pass over phi and lambda);
+ *        GV_STREAM_TRIAD  dst = src0 + src1.
+ *   width: bytes per lane per access, 4, 8 or 16; unroll: accesses in flight
+ *   per lane, 1, 2, 4 or 8; nontemporal != 0 uses non-temporal loads/stores;
+ *   grid: blocks of 256 lanes, 0 = one block per 256 * unroll accesses.
+ * bytes must be a positive multiple of 32 KiB; every buffer the kind uses must
+ * hold `bytes` device bytes (READ writes at most 4 KiB of dst, never in
+ * practice), 256-byte aligned.  Enqueues on `stream` and returns. */
+typedef enum {
+    GV_STREAM_READ = 0, GV_STREAM_WRITE = 1, GV_STREAM_COPY = 2, GV_STREAM_RMW = 3,
+    GV_STREAM_TRIAD = 4
+} gv_stream_kind;
+gv_status gv_stream_probe(int32_t kind, int32_t width, int32_t unroll, int32_t nontemporal,
+                          int32_t grid, void *dst, const void *src0, const void *src1,
+                          size_t bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgv.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["gv_api.cpp", "gv_batch.cpp", "gv_plain.hip", "gv_ham.hip", "gv_fused.hip"]
+# every C++ and HIP source of csrc/ goes into the library
+SOURCES = sorted(f for f in os.listdir(CSRC) if f.endswith((".cpp", ".hip")))
 
 ARCH = "gfx950"
 FLAGS = [
@@ -36,8 +37,13 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str, verbose: bool) -> str:
+def _compile(src: str, verbose: bool, incremental: bool = False) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj):
+        deps = [os.path.join(CSRC, src), os.path.join(CSRC, "gv_internal.hpp"),
+                os.path.join(CSRC, "gv_device.hpp"), os.path.join(ROOT, "include", "gv.h")]
+        if os.path.getmtime(obj) >= max(os.path.getmtime(d) for d in deps):
+            return obj
     cmd = [hipcc(), *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -49,11 +55,12 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libgv.so; returns its path."""
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source and link libgv.so; returns its path.  With
+    incremental, objects newer than their source and headers are kept."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=4) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose, incremental), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -64,4 +71,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="-i" in sys.argv))

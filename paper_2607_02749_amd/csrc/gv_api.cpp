@@ -549,7 +549,8 @@ int64_t gv_num_params(const gv_ansatz *a)
 }
 
 gv_status gv_query_sizes(const gv_ansatz *a, gv_precision prec, gv_engine engine,
-                         gv_grad_mode mode, size_t *state_bytes, size_t *work_bytes)
+                         gv_grad_mode mode, size_t *state_bytes, size_t *work_bytes,
+                         size_t *diag_bytes)
 {
     if (gv_status r = check_ansatz(a)) return r;
     if (prec != GV_C64 && prec != GV_C128) return set_error(GV_EINVAL, "precision");
@@ -559,6 +560,7 @@ gv_status gv_query_sizes(const gv_ansatz *a, gv_precision prec, gv_engine engine
     if (gv_status r = work_layout(*a, prec, engine, mode, &w)) return r;
     if (state_bytes) *state_bytes = ((size_t)1 << a->n) * amp_bytes(prec);
     if (work_bytes) *work_bytes = w.total;
+    if (diag_bytes) *diag_bytes = ((size_t)1 << a->n) * sizeof(double);
     return GV_OK;
 }
 
@@ -820,6 +822,7 @@ static gv_status prepare_impl(gv_pauli_sum h, gv_precision prec, gv_engine engin
     pauli_layout(h, &odiag, &ocls, &oterms, &osz, &osc, &total);
     if (bytes < total) return set_error(GV_ESIZE, "buffer %zu bytes < %zu", bytes, total);
     char *base = (char *)dev;
+    h->prep_gen++;
     h->dev = dev;
     h->dev_bytes = bytes;
     h->diag = (double *)(base + odiag);
@@ -1195,6 +1198,27 @@ gv_status gv_profile_read(gv_state st, int32_t kind, int64_t *launches, double *
     if (ms) *ms = tot;
     if (bytes) *bytes = b;
     return GV_OK;
+}
+
+gv_status gv_stream_probe(int32_t kind, int32_t width, int32_t unroll, int32_t nontemporal,
+                          int32_t grid, void *dst, const void *src0, const void *src1,
+                          size_t bytes, void *stream)
+{
+    if (kind < GV_STREAM_READ || kind > GV_STREAM_TRIAD) return set_error(GV_EINVAL, "kind %d", kind);
+    if (width != 4 && width != 8 && width != 16) return set_error(GV_EINVAL, "width %d", width);
+    if (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8)
+        return set_error(GV_EINVAL, "unroll %d", unroll);
+    if (grid < 0) return set_error(GV_EINVAL, "grid %d", grid);
+    if (bytes == 0 || bytes % 32768 != 0)
+        return set_error(GV_EINVAL, "bytes must be a positive multiple of 32 KiB");
+    if (!dst) return set_error(GV_EINVAL, "dst is NULL");
+    if (kind != GV_STREAM_WRITE && !src0) return set_error(GV_EINVAL, "src0 is NULL");
+    if (kind == GV_STREAM_TRIAD && !src1) return set_error(GV_EINVAL, "src1 is NULL");
+    if (!aligned(dst) || (src0 && !aligned(src0)) || (src1 && !aligned(src1)))
+        return set_error(GV_EINVAL, "buffers must be %zu-byte aligned", kAlign);
+    return check_hip(stream_probe(kind, width, unroll, nontemporal != 0, dst, src0, src1, bytes,
+                                  grid, (hipStream_t)stream),
+                     "stream probe");
 }
 
 }  // extern "C"

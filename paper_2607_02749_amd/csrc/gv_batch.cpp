@@ -28,12 +28,17 @@ struct gv_batch_s {
     hipStream_t capture_stream = nullptr;
     hipGraph_t g = nullptr;
     hipGraphExec_t exec = nullptr;
-    // instances run as whole-GPU passes: their instance records, states (the
-    // batch's psi buffer of the instance and a work region of their own) and
-    // device gradient masks; side streams with fork / join events
+    // instances run as whole-GPU passes: their instance records and output
+    // slots, states (the batch's psi buffer of the instance and a work region
+    // of their own) and device gradient masks; side streams with fork / join
+    // events (or none: then they run one after another on the batch stream)
     std::vector<gv_instance> large;
+    std::vector<double *> large_e, large_g;
     std::vector<gv_state_s> states;
     std::vector<uint8_t *> masks;
+    bool side_streams = true;
+    // every instance's Hamiltonian and its prepare generation at creation
+    std::vector<std::pair<const gv_pauli_s *, uint64_t>> hgen;
     hipStream_t side[kSideStreams] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[kSideStreams] = {};
@@ -75,10 +80,8 @@ gv_status check_instances(int count, const gv_instance *inst, gv_precision prec)
             return set_error(GV_EUNSUPPORTED, "instance %d: no rotation layer", i);
         if (a.ent != GV_ENT_NONE && a.ent != GV_ENT_CZ_LINEAR && a.ent != GV_ENT_CZ_CIRCULAR)
             return set_error(GV_EUNSUPPORTED, "instance %d: batches take CZ or no entangler", i);
-        if (!I.params_dev || !I.energy_dev || !I.grad_dev || !I.h)
+        if (!I.params_dev || !I.h)
             return set_error(GV_EINVAL, "instance %d: NULL pointer", i);
-        if (a.n < 64 && (I.qubit_mask >> a.n))
-            return set_error(GV_EINVAL, "instance %d: qubit mask bit >= n", i);
         const gv_pauli_s *h = I.h;
         if (!h->prepared || h->n != a.n)
             return set_error(GV_ESTATE, "instance %d: Hamiltonian not prepared for n=%d", i, a.n);
@@ -144,7 +147,7 @@ BatchLayout batch_layout(int count, const gv_instance *inst, gv_precision prec, 
 gv_status launch_all(gv_batch b, hipStream_t s)
 {
     hipError_t e = hipSuccess;
-    const bool fork = !b->large.empty();
+    const bool fork = !b->large.empty() && b->side_streams;
     if (fork) {
         e = hipEventRecord(b->fork, s);
         for (int k = 0; k < kSideStreams && e == hipSuccess; ++k)
@@ -157,10 +160,10 @@ gv_status launch_all(gv_batch b, hipStream_t s)
     if (e != hipSuccess) return check_hip(e, "batch launch");
     for (size_t j = 0; j < b->large.size(); ++j) {
         gv_state_s &st = b->states[j];
-        st.stream = b->side[j % kSideStreams];
+        st.stream = fork ? b->side[j % kSideStreams] : s;
         const gv_instance &I = b->large[j];
         if (gv_status r = gv_energy_grad(&st, I.h, I.params_dev, &I.ansatz, b->masks[j],
-                                         GV_GRAD_STORE, I.energy_dev, I.grad_dev))
+                                         GV_GRAD_STORE, b->large_e[j], b->large_g[j]))
             return r;
     }
     if (fork) {
@@ -189,12 +192,28 @@ gv_status gv_batch_query(int32_t count, const gv_instance *inst, gv_precision pr
     return GV_OK;
 }
 
-gv_status gv_batch_create(int32_t count, const gv_instance *inst, gv_precision prec,
-                          const gv_batch_tuning *tuning, void *work, size_t work_bytes,
-                          void *stream, int32_t use_graph, gv_batch *out)
+static gv_status batch_create_impl(int32_t count, const gv_instance *inst,
+                                   const gv_cluster *clusters, gv_precision prec,
+                                   const gv_batch_tuning *tuning, void *work, size_t work_bytes,
+                                   void *stream, int32_t use_graph, double *energies,
+                                   double *grads, bool side_streams, gv_batch *out)
 {
     if (!out) return set_error(GV_EINVAL, "out is NULL");
     if (gv_status r = check_instances(count, inst, prec)) return r;
+    if (count > 0 && (!energies || !grads)) return set_error(GV_EINVAL, "output buffers are NULL");
+    std::vector<uint64_t> qmask(count), goff(count);
+    {
+        uint64_t off = 0;
+        for (int i = 0; i < count; ++i) {
+            const gv_ansatz &a = inst[i].ansatz;
+            const uint64_t all = a.n >= 64 ? ~0ull : ((1ull << a.n) - 1);
+            qmask[i] = clusters ? clusters[i].qubit_mask : all;
+            if (qmask[i] & ~all)
+                return set_error(GV_EINVAL, "cluster %d: qubit mask bit >= n", i);
+            goff[i] = off;
+            off += 2ull * a.n * (a.layers + a.final_rotation);
+        }
+    }
     if (!work || ((uintptr_t)work % kAlign)) return set_error(GV_EINVAL, "work must be 256-byte aligned");
     gv_batch_tuning tu = {2, 0, 0};
     if (tuning) tu = *tuning;
@@ -229,10 +248,10 @@ gv_status gv_batch_create(int32_t count, const gv_instance *inst, gv_precision p
         b.zonly = h->ox.empty();
         b.cz = a.ent == GV_ENT_CZ_LINEAR ? 1 : (a.ent == GV_ENT_CZ_CIRCULAR ? 2 : 0);
         b.ntiles = 1ull << (a.n - kBatchK);
-        b.qmask = I.qubit_mask;
+        b.qmask = qmask[i];
         b.theta = I.params_dev;
-        b.energy = I.energy_dev;
-        b.grad = I.grad_dev;
+        b.energy = energies + 2 * (size_t)i;
+        b.grad = grads + goff[i];
         b.hdiag = h->diag;
         b.cls = h->dev_cls;
         b.terms = h->dev_terms;
@@ -281,6 +300,9 @@ gv_status gv_batch_create(int32_t count, const gv_instance *inst, gv_precision p
     b->dev_order = (int *)(w + L.order);
     b->counter = (unsigned *)(w + L.counter);
     b->nsmall = (int)order.size();
+    b->side_streams = side_streams;
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < count; ++i) b->hgen.push_back({inst[i].h, inst[i].h->prep_gen});
     int cus = 0, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -293,9 +315,10 @@ gv_status gv_batch_create(int32_t count, const gv_instance *inst, gv_precision p
         const gv_ansatz &a = I.ansatz;
         const int64_t P = 2ll * a.n * (a.layers + a.final_rotation);
         std::vector<uint8_t> m((size_t)P);
-        for (int64_t p = 0; p < P; ++p) m[(size_t)p] = (uint8_t)((I.qubit_mask >> (p % a.n)) & 1);
+        for (int64_t p = 0; p < P; ++p) m[(size_t)p] = (uint8_t)((qmask[i] >> (p % a.n)) & 1);
         uint8_t *dm = (uint8_t *)(w + L.mask[i]);
-        if (e == hipSuccess) e = hipMemcpy(dm, m.data(), m.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpyAsync(dm, m.data(), m.size(), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);   // m is about to go
         gv_state_s st;
         st.n = a.n;
         st.prec = prec;
@@ -305,10 +328,12 @@ gv_status gv_batch_create(int32_t count, const gv_instance *inst, gv_precision p
         st.work = w + L.fwork[i];
         st.work_bytes = L.fwork_bytes[i];
         b->large.push_back(I);
+        b->large_e.push_back(energies + 2 * (size_t)i);
+        b->large_g.push_back(grads + goff[i]);
         b->states.push_back(st);
         b->masks.push_back(dm);
     }
-    if (!large.empty()) {
+    if (!large.empty() && side_streams) {
         for (int k = 0; k < kSideStreams && e == hipSuccess; ++k) {
             e = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming);
@@ -316,13 +341,18 @@ gv_status gv_batch_create(int32_t count, const gv_instance *inst, gv_precision p
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
     }
     if (e == hipSuccess && count > 0) {
-        e = hipMemcpy(b->dev_insts, hi.data(), hi.size() * sizeof(BatchInst), hipMemcpyHostToDevice);
+        // stream-ordered behind whatever the caller still runs on the work
+        // buffer; the host arrays live until the synchronisation below
+        e = hipMemcpyAsync(b->dev_insts, hi.data(), hi.size() * sizeof(BatchInst),
+                           hipMemcpyHostToDevice, s);
         if (e == hipSuccess && !order.empty())
-            e = hipMemcpy(b->dev_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice);
+            e = hipMemcpyAsync(b->dev_order, order.data(), order.size() * sizeof(int),
+                               hipMemcpyHostToDevice, s);
         for (int i = 0; i < count && e == hipSuccess; ++i)
             if (!offp[i].empty())
-                e = hipMemcpy(w + L.offp[i], offp[i].data(), offp[i].size() * sizeof(BatchOffPass),
-                              hipMemcpyHostToDevice);
+                e = hipMemcpyAsync(w + L.offp[i], offp[i].data(),
+                                   offp[i].size() * sizeof(BatchOffPass), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
     if (e == hipSuccess && use_graph) {
         e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
@@ -346,9 +376,22 @@ gv_status gv_batch_create(int32_t count, const gv_instance *inst, gv_precision p
     return GV_OK;
 }
 
+gv_status gv_batch_create(int32_t count, const gv_instance *inst, const gv_cluster *clusters,
+                          gv_precision prec, const gv_batch_tuning *tuning, void *work,
+                          size_t work_bytes, void *stream, int32_t use_graph, double *energies,
+                          double *grads, gv_batch *out)
+{
+    return batch_create_impl(count, inst, clusters, prec, tuning, work, work_bytes, stream,
+                             use_graph, energies, grads, true, out);
+}
+
 gv_status gv_batch_run(gv_batch b)
 {
     if (!b) return set_error(GV_EINVAL, "batch is NULL");
+    for (size_t i = 0; i < b->hgen.size(); ++i)
+        if (b->hgen[i].first->prep_gen != b->hgen[i].second || !b->hgen[i].first->prepared)
+            return set_error(GV_ESTATE, "instance %zu: its Hamiltonian was prepared again after "
+                                        "the batch was created", i);
     if (b->graph) return check_hip(hipGraphLaunch(b->exec, b->stream), "graph launch");
     return launch_all(b, b->stream);
 }
@@ -368,13 +411,17 @@ gv_status gv_batch_destroy(gv_batch b)
     return GV_OK;
 }
 
-gv_status gv_batch_energy_grad(int32_t count, const gv_instance *inst, gv_precision prec,
-                               void *work, size_t work_bytes, void *stream)
+gv_status gv_batch_energy_grad(int32_t count, const gv_instance *inst, const gv_cluster *clusters,
+                               gv_precision prec, void *work, size_t work_bytes, void *stream,
+                               double *energies, double *grads)
 {
     gv_batch b = nullptr;
-    if (gv_status r = gv_batch_create(count, inst, prec, nullptr, work, work_bytes, stream, 0, &b))
+    if (gv_status r = batch_create_impl(count, inst, clusters, prec, nullptr, work, work_bytes,
+                                        stream, 0, energies, grads, false, &b))
         return r;
-    gv_status r = gv_batch_run(b);
+    // everything is enqueued on `stream` (no side streams, no graph) and
+    // the launches hold their arguments, so the host handle can go now
+    const gv_status r = gv_batch_run(b);
     gv_batch_destroy(b);
     return r;
 }

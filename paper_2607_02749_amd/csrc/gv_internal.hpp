@@ -75,6 +75,7 @@ struct gv_pauli_s {
     size_t dev_bytes = 0;
     double *diag = nullptr;         // 2^n doubles
     bool prepared = false;
+    uint64_t prep_gen = 0;          // bumped by every prepare (batches check it)
 };
 
 struct gv_prof_record {
@@ -250,6 +251,11 @@ hipError_t reduce_rows(const double *part, int64_t rows, int cols, const uint8_t
 hipError_t reduce_energy(const double *epart, int grid, double *energy, hipStream_t s);
 
 hipError_t copy_vector(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+// streaming-bandwidth probe (gv_stream.hip): kind is a gv_stream_kind
+enum { STREAM_READ = 0, STREAM_WRITE = 1, STREAM_COPY = 2, STREAM_RMW = 3, STREAM_TRIAD = 4 };
+hipError_t stream_probe(int kind, int width, int unroll, int nt, void *dst, const void *s0,
+                        const void *s1, size_t bytes, int grid, hipStream_t s);
 
 // one cover pass of off-diagonal classes: lam += (sum of the classes) psi
 // (lam may be NULL); energy partials epart[b], epart[estride + b] += the

@@ -43,9 +43,11 @@ class _Ansatz(ctypes.Structure):
 
 
 class _Instance(ctypes.Structure):
-    _fields_ = [("ansatz", _Ansatz), ("params_dev", ctypes.c_void_p), ("h", ctypes.c_void_p),
-                ("qubit_mask", ctypes.c_uint64), ("energy_dev", ctypes.c_void_p),
-                ("grad_dev", ctypes.c_void_p)]
+    _fields_ = [("ansatz", _Ansatz), ("params_dev", ctypes.c_void_p), ("h", ctypes.c_void_p)]
+
+
+class _Cluster(ctypes.Structure):
+    _fields_ = [("qubit_mask", ctypes.c_uint64)]
 
 
 class _Tuning(ctypes.Structure):
@@ -70,7 +72,8 @@ def lib():
     L.gv_last_error.restype = ctypes.c_char_p
     L.gv_num_params.argtypes = [AP]
     L.gv_num_params.restype = i64
-    L.gv_query_sizes.argtypes = [AP, i32, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    L.gv_query_sizes.argtypes = [AP, i32, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(sz),
+                                 ctypes.POINTER(sz)]
     L.gv_state_create.argtypes = [i32, i32, i32, vp, sz, vp, sz, vp, ctypes.POINTER(vp)]
     L.gv_state_destroy.argtypes = [vp]
     L.gv_state_set_stream.argtypes = [vp, vp]
@@ -85,12 +88,14 @@ def lib():
     L.gv_energy_grad.argtypes = [vp, vp, vp, AP, vp, i32, vp, vp]
     L.gv_pauli_sum_prepare_for.argtypes = [vp, i32, i32, vp, vp, sz]
     IP = ctypes.POINTER(_Instance)
+    CP = ctypes.POINTER(_Cluster)
     L.gv_batch_query.argtypes = [i32, IP, i32, ctypes.POINTER(_Tuning), ctypes.POINTER(sz)]
-    L.gv_batch_create.argtypes = [i32, IP, i32, ctypes.POINTER(_Tuning), vp, sz, vp, i32,
-                                  ctypes.POINTER(vp)]
+    L.gv_batch_create.argtypes = [i32, IP, CP, i32, ctypes.POINTER(_Tuning), vp, sz, vp, i32,
+                                  vp, vp, ctypes.POINTER(vp)]
     L.gv_batch_run.argtypes = [vp]
     L.gv_batch_destroy.argtypes = [vp]
-    L.gv_batch_energy_grad.argtypes = [i32, IP, i32, vp, sz, vp]
+    L.gv_batch_energy_grad.argtypes = [i32, IP, CP, i32, vp, sz, vp, vp, vp]
+    L.gv_stream_probe.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, sz, vp]
     L.gv_profile_enable.argtypes = [vp, i32]
     L.gv_profile_reset.argtypes = [vp]
     L.gv_profile_read.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
@@ -100,7 +105,8 @@ def lib():
                  "gv_apply_ansatz", "gv_pauli_sum_create", "gv_pauli_sum_destroy",
                  "gv_pauli_sum_info", "gv_pauli_sum_device_bytes", "gv_pauli_sum_prepare",
                  "gv_pauli_sum_prepare_for", "gv_energy", "gv_energy_grad", "gv_batch_query",
-                 "gv_batch_create", "gv_batch_run", "gv_batch_destroy", "gv_batch_energy_grad"):
+                 "gv_batch_create", "gv_batch_run", "gv_batch_destroy", "gv_batch_energy_grad",
+                 "gv_stream_probe"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -145,12 +151,29 @@ class Ansatz:
         return 2 * self.n * (self.layers + self.final_rotation)
 
 
-def query_sizes(ansatz: Ansatz, precision="c64", engine="fused", mode="uncompute") -> Tuple[int, int]:
+def query_sizes(ansatz: Ansatz, precision="c64", engine="fused", mode="uncompute",
+                with_diag=False):
+    """(state bytes, work bytes), and the FP64 diagonal's bytes with_diag."""
     a = ansatz.c()
-    sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    sb, wb, db = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
     _check(lib().gv_query_sizes(ctypes.byref(a), _PREC[precision], _ENGINE[engine], _MODE[mode],
-                                ctypes.byref(sb), ctypes.byref(wb)), "gv_query_sizes")
-    return sb.value, wb.value
+                                ctypes.byref(sb), ctypes.byref(wb), ctypes.byref(db)),
+           "gv_query_sizes")
+    return (sb.value, wb.value, db.value) if with_diag else (sb.value, wb.value)
+
+
+STREAM_KINDS = {"read": 0, "write": 1, "copy": 2, "rmw": 3, "triad": 4}
+
+
+def stream_probe(kind: str, width: int, unroll: int, nontemporal: bool, grid: int,
+                 dst: torch.Tensor, src0: Optional[torch.Tensor] = None,
+                 src1: Optional[torch.Tensor] = None, nbytes: Optional[int] = None):
+    """Enqueue one streaming kernel of the bandwidth probe on the current
+    stream (see gv_stream_probe in include/gv.h)."""
+    nb = dst.numel() * dst.element_size() if nbytes is None else nbytes
+    _check(lib().gv_stream_probe(STREAM_KINDS[kind], width, unroll, int(nontemporal), grid,
+                                 _ptr(dst), _ptr(src0), _ptr(src1), nb,
+                                 _stream_ptr(dst.device)), "gv_stream_probe")
 
 
 class State:
@@ -235,6 +258,12 @@ class PauliSum:
                                          self._c.ctypes.data, ctypes.byref(h)), "gv_pauli_sum_create")
         self.handle = h
         self.device_buffer = None
+        self._batches = 0        # live batches built on this Hamiltonian
+
+    def _may_prepare(self):
+        if self._batches:
+            raise GVError("this PauliSum is used by a live Batch: its device form cannot be "
+                          "rebuilt until the batch is gone")
 
     def info(self) -> Tuple[int, int, int]:
         a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
@@ -243,6 +272,7 @@ class PauliSum:
         return a.value, b.value, c.value
 
     def prepare(self, state: State):
+        self._may_prepare()
         nb = ctypes.c_size_t()
         _check(lib().gv_pauli_sum_device_bytes(self.handle, ctypes.byref(nb)), "device_bytes")
         self._owner, self.device_buffer = _aligned_bytes(nb.value, state.device)
@@ -253,6 +283,7 @@ class PauliSum:
 
     def prepare_for(self, precision="c64", engine="fused", device="cuda"):
         """Device form for states of `precision` on `engine` (and for batches)."""
+        self._may_prepare()
         nb = ctypes.c_size_t()
         _check(lib().gv_pauli_sum_device_bytes(self.handle, ctypes.byref(nb)), "device_bytes")
         dev = torch.device(device)
@@ -341,23 +372,49 @@ def param_mask(n: int, layers: int, qubit_mask: int, final_rotation: int = 0,
     return m.to(device)
 
 
+def _batch_arrays(items, precision, device):
+    """ctypes instance and cluster arrays of (Ansatz, theta, PauliSum,
+    qubit_mask or None) items; prepares any unprepared Hamiltonian."""
+    count = len(items)
+    arr = (_Instance * max(count, 1))()
+    cl = (_Cluster * max(count, 1))()
+    for i, (an, th, h, qmask) in enumerate(items):
+        assert th.dtype == torch.float64 and th.is_contiguous() and th.device == device
+        assert th.numel() == an.num_params
+        if h.device_buffer is None:
+            h.prepare_for(precision, "fused", device)
+        arr[i].ansatz = an.c()
+        arr[i].params_dev = th.data_ptr()
+        arr[i].h = h.handle
+        cl[i].qubit_mask = ((1 << an.n) - 1) if qmask is None else int(qmask)
+    return arr, cl
+
+
+def _device(device):
+    dev = torch.device(device)
+    if dev.type == "cuda" and dev.index is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    return dev
+
+
 class Batch:
     """Many independent energy + restricted-gradient evaluations in one
-    persistent kernel (optionally replayed from a HIP graph).
+    persistent kernel (optionally replayed from a HIP graph) (Sec. IV-D,
+    Eq. 11).
 
     items: sequence of (Ansatz, theta tensor (float64, device), PauliSum,
-    qubit_mask).  Each PauliSum is prepared here for the batch precision.
-    After run(), energies[i] holds (re, im) and grads[i] the gradient of
-    item i (0 outside its qubit block).  Rewriting the theta tensors in place
-    and calling run() again evaluates the new angles.  Instances with
-    n >= split_n run as whole-GPU tile passes beside the persistent kernel
-    (None: the library default)."""
+    qubit_mask or None).  Each PauliSum is prepared here for the batch
+    precision if it is not yet.  After run(), energies[i] holds (re, im) and
+    grads[i] the gradient of item i (0 outside its qubit block): views of one
+    packed buffer, instance i at offset sum_{j<i} P_j.  Rewriting the theta
+    tensors in place and calling run() again evaluates the new angles.
+    Instances with n >= split_n run as whole-GPU tile passes beside the
+    persistent kernel (None: the library default).  While the batch lives,
+    its PauliSums refuse to be prepared again."""
 
     def __init__(self, items, precision="c64", blocks_per_cu=None, order=None, graph=True,
                  device="cuda", split_n=None):
-        dev = torch.device(device)
-        if dev.type == "cuda" and dev.index is None:
-            dev = torch.device("cuda", torch.cuda.current_device())
+        dev = _device(device)
         self.device = dev
         self.precision = _PREC[precision]
         self.items = list(items)
@@ -365,23 +422,15 @@ class Batch:
         total_p = sum(an.num_params for an, _, _, _ in self.items)
         self.energy_buf = torch.zeros(count, 2, dtype=torch.float64, device=dev)
         self.grad_buf = torch.zeros(max(total_p, 1), dtype=torch.float64, device=dev)
-        arr = (_Instance * max(count, 1))()
+        arr, cl = _batch_arrays(self.items, precision, dev)
         self.grads = []
         off = 0
-        for i, (an, th, h, qmask) in enumerate(self.items):
-            assert th.dtype == torch.float64 and th.is_contiguous() and th.device == dev
-            if h.device_buffer is None:
-                h.prepare_for(precision, "fused", dev)
-            g = self.grad_buf[off:off + an.num_params]
+        for an, _, _, _ in self.items:
+            self.grads.append(self.grad_buf[off:off + an.num_params])
             off += an.num_params
-            self.grads.append(g)
-            arr[i].ansatz = an.c()
-            arr[i].params_dev = th.data_ptr()
-            arr[i].h = h.handle
-            arr[i].qubit_mask = int(qmask)
-            arr[i].energy_dev = self.energy_buf[i].data_ptr()
-            arr[i].grad_dev = g.data_ptr()
-        self._arr = arr
+        # the Hamiltonians' device buffers must outlive the batch
+        self._hams = [h for _, _, h, _ in self.items]
+        self._h_buffers = [h._owner for h in self._hams]
         tu = None
         if blocks_per_cu is not None or order is not None or split_n is not None:
             tu = _Tuning(2 if blocks_per_cu is None else blocks_per_cu, 0 if order is None else order,
@@ -393,11 +442,14 @@ class Batch:
                "gv_batch_query")
         self._work_owner, self.work = _aligned_bytes(wb.value, dev)
         b = ctypes.c_void_p()
-        _check(lib().gv_batch_create(count, arr, self.precision,
+        _check(lib().gv_batch_create(count, arr, cl, self.precision,
                                      None if tu is None else ctypes.byref(tu), _ptr(self.work),
-                                     wb.value, _stream_ptr(dev), int(graph), ctypes.byref(b)),
+                                     wb.value, _stream_ptr(dev), int(graph),
+                                     _ptr(self.energy_buf), _ptr(self.grad_buf), ctypes.byref(b)),
                "gv_batch_create")
         self.handle = b
+        for h in self._hams:
+            h._batches += 1
 
     @property
     def energies(self) -> torch.Tensor:
@@ -411,3 +463,30 @@ class Batch:
         if h is not None and _lib is not None:
             _lib.gv_batch_destroy(h)
             self.handle = None
+            for ham in self._hams:
+                ham._batches -= 1
+
+
+def batch_energy_grad(items, precision="c64", device="cuda"):
+    """One-shot batch (gv_batch_energy_grad): energies (count x 2) and the
+    packed gradients (sum of P_i) of (Ansatz, theta, PauliSum, qubit_mask or
+    None) items, enqueued on the current stream."""
+    dev = _device(device)
+    items = list(items)
+    count = len(items)
+    arr, cl = _batch_arrays(items, precision, dev)
+    total_p = sum(an.num_params for an, _, _, _ in items)
+    energies = torch.empty(count, 2, dtype=torch.float64, device=dev)
+    grads = torch.empty(max(total_p, 1), dtype=torch.float64, device=dev)
+    wb = ctypes.c_size_t()
+    _check(lib().gv_batch_query(count, arr, _PREC[precision], None, ctypes.byref(wb)),
+           "gv_batch_query")
+    owner, work = _aligned_bytes(wb.value, dev)
+    _check(lib().gv_batch_energy_grad(count, arr, cl, _PREC[precision], _ptr(work), wb.value,
+                                      _stream_ptr(dev), _ptr(energies), _ptr(grads)),
+           "gv_batch_energy_grad")
+    # `owner` was allocated on the current stream, where the work is queued:
+    # torch's caching allocator hands its memory out again only to later work
+    # on that stream, so dropping it here is safe
+    del owner, work
+    return energies, grads

@@ -20,8 +20,10 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for required in ("gv_state_create", "gv_apply_ansatz", "gv_energy", "gv_energy_grad",
-                     "gv_pauli_sum_create", "gv_pauli_sum_prepare", "gv_last_error"):
+    for required in ("gv_query_sizes", "gv_state_create", "gv_state_destroy", "gv_apply_ansatz",
+                     "gv_energy", "gv_energy_grad", "gv_pauli_sum_create",
+                     "gv_pauli_sum_prepare", "gv_pauli_sum_destroy", "gv_batch_energy_grad",
+                     "gv_last_error"):
         assert required in names
 
 
@@ -59,6 +61,8 @@ def test_query_sizes():
     assert wcn == wcn_ck
     sb128, _ = gv.query_sizes(gv.Ansatz(10, 2), "c128", "plain")
     assert sb128 == 16 << 10
+    _, _, db = gv.query_sizes(gv.Ansatz(28, 6), "c64", "fused", "store", with_diag=True)
+    assert db == 8 << 28                       # FP64 diagonal
     with pytest.raises(gv.GVError):
         gv.query_sizes(gv.Ansatz(35, 1))
     with pytest.raises(gv.GVError):
@@ -110,3 +114,22 @@ def test_pauli_sum_groups_of_generated_workload():
     h = gv.PauliSum(32, w.x, w.z, w.c)
     nd, no, ng = h.info()
     assert no == 2000 and ng <= 64
+
+
+def test_batch_call_validates_before_any_gpu_work():
+    L = gv.lib()
+    fake = ctypes.c_void_p(1 << 20)    # never dereferenced: validation fails first
+    arr = (gv._Instance * 1)()
+    cl = (gv._Cluster * 1)()
+    arr[0].ansatz = gv.Ansatz(12, 2).c()
+    arr[0].params_dev = None
+    arr[0].h = None
+    assert L.gv_batch_energy_grad(1, arr, cl, 0, fake, 1 << 20, None, fake, fake) == 1
+    h = gv.PauliSum(12, [0], [1], [1.0])
+    arr[0].params_dev = 1 << 20
+    arr[0].h = h.handle
+    # Hamiltonian not prepared
+    assert L.gv_batch_energy_grad(1, arr, cl, 0, fake, 1 << 20, None, fake, fake) == 4
+    arr[0].ansatz = gv.Ansatz(8, 2).c()
+    assert L.gv_batch_energy_grad(1, arr, cl, 0, fake, 1 << 20, None, fake, fake) == 3
+    assert L.gv_batch_energy_grad(-1, arr, cl, 0, fake, 1 << 20, None, fake, fake) == 1

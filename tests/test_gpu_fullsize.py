@@ -43,6 +43,24 @@ def evaluate(inst, precision, mode):
     return out
 
 
+def test_n28_diagonal_entries_against_stored_oracle():
+    # 16 seeded entries of the FP64 diagonal, each a direct sum over the
+    # 20,000 Z-strings in the oracle (tests/golden/make_golden.py)
+    gold = json.load(open(os.path.join(HERE, "golden", "oracle_n28.json")))
+    inst = synth.workload_n28()
+    h = gv.PauliSum(inst.n, inst.x, inst.z, inst.c).prepare_for("c64", "fused")
+    d = h.diagonal()
+    idx = torch.tensor(gold["diag_index"], dtype=torch.int64, device=d.device)
+    got = d[idx].cpu().numpy()
+    want = np.array(gold["diag_value"])
+    scale = np.abs(inst.c).sum()
+    print("n=28 diagonal entries: max abs err / sum|c|", np.abs(got - want).max() / scale,
+          flush=True)
+    assert np.abs(got - want).max() <= 1e-12 * scale
+    del h, d
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("mode", ["uncompute", "store"])
 def test_n28_against_stored_oracle(mode):
     gold = json.load(open(os.path.join(HERE, "golden", "oracle_n28.json")))

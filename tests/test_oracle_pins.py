@@ -242,3 +242,46 @@ def test_adjoint_gate_steps_match_full_sweep():
     oracle.adjoint_gates(n, L, ent, inst.theta, phi, lam, gg, ng // 2, ng - ng // 2)
     oracle.adjoint_gates(n, L, ent, inst.theta, phi, lam, gg, 0, ng // 2)
     assert np.abs(gg - g).max() < 1e-13
+
+
+@pytest.mark.parametrize("final_rotation", [0, 1])
+def test_param_mask_is_support_of_block_gradient(final_rotation):
+    # Block parameters (Sec. IV-D, Eq. 11): with no entangler the state is a
+    # product state, so when every term acts on the block's qubits only, the
+    # closed-form gradient (Bloch vectors, product rule) is nonzero exactly at
+    # the RY and RZ angles of the block's qubits in every layer.  param_mask
+    # must select that support, and the masked oracle gradient must equal
+    # the closed form entry by entry.
+    rng = np.random.default_rng(31 + final_rotation)
+    n, layers = 9, 3
+    p = oracle.num_params(n, layers, final_rotation)
+    for block in (0b000010110, 0b110000001, 0b000111000, 0b000000001):
+        qs = [q for q in range(n) if (block >> q) & 1]
+        x, z = [], []
+        for q in qs:                                   # X, Y, Z on every block qubit
+            for xb, zb in ((1, 0), (1, 1), (0, 1)):
+                x.append(xb << q)
+                z.append(zb << q)
+        for _ in range(12):                            # random strings over the block
+            sub = [q for q in qs if rng.random() < 0.6] or qs[:1]
+            xm = zm = 0
+            for q in sub:
+                letter = int(rng.integers(3))          # X, Y, Z
+                xm |= (letter <= 1) << q
+                zm |= (letter >= 1) << q
+            x.append(xm)
+            z.append(zm)
+        x = np.array(x, np.uint64)
+        z = np.array(z, np.uint64)
+        c = rng.normal(size=len(x))
+        theta = rng.uniform(-np.pi, np.pi, p)
+        e_cf, g_cf = cf.product_energy_grad(n, layers + final_rotation, theta, x, z, c)
+        support = np.abs(g_cf) > 1e-9
+        assert np.all(g_cf[~support] == 0.0)
+        m = oracle.param_mask(n, layers, block, final_rotation)
+        assert m.shape == (p,)
+        assert np.array_equal(m.astype(bool), support), (bin(block), m, support)
+        e, gm = oracle.energy_grad(n, layers, synth.ENT_NONE, theta, x, z, c, mask=m,
+                                   final_rotation=final_rotation)
+        assert abs(e.real - e_cf) < 1e-12
+        assert np.abs(gm - g_cf).max() < 1e-12
