@@ -225,11 +225,25 @@ def copy_probe(torch, gv, full=False):
     for r in rows:
         if r["kind"] not in best or r["GBps"] > best[r["kind"]]["GBps"]:
             best[r["kind"]] = r
+    # the tile-pass layout: one amplitude (8 B) per lane, 16 in flight, runs of
+    # 16 amplitudes 2^s apart (s = 12, 20: the second and third passes at n = 28)
+    tiled = []
+    if full:
+        for kind in ("copy", "rmw"):
+            for shift in (0, 12, 20):
+                for g in (0, 3072):
+                    for u in (4, 16):
+                        ms = timed(lambda: gv.stream_probe(kind, 8, u, 0, g, bufs[0], bufs[1],
+                                                           bufs[2], nb, tile_shift=shift))
+                        tiled.append({"kind": kind, "width": 8, "unroll": u, "grid": g,
+                                      "tile_shift": shift, "ms": ms,
+                                      "GBps": moved[kind] * nb / (ms * 1e-3) / 1e9})
     ms = timed(lambda: bufs[0].copy_(bufs[1]), 5)
     out = {"bytes_per_buffer": nb, "best": best,
            "torch_copy": {"ms": ms, "GBps": 2 * nb / (ms * 1e-3) / 1e9}}
     if full:
         out["all"] = rows
+        out["tiled"] = tiled
     del bufs
     torch.cuda.empty_cache()
     return out

@@ -152,6 +152,15 @@ gv_status gv_pauli_sum_destroy(gv_pauli_sum h);
 gv_status gv_pauli_sum_info(gv_pauli_sum h, int64_t *n_diag, int64_t *n_offdiag,
                             int64_t *n_groups);
 
+/* How the off-diagonal terms (Eq. 6) would be applied to a state of n_state
+ * qubits in `prec` on `engine` (host-side planning only, no device work):
+ * the number of cover passes (each one sweep over psi and lambda), the most
+ * terms one pass holds, and the terms applied one by one (flip masks too wide
+ * for a tile; every term on the plain engine).  Any output pointer may be
+ * NULL. */
+gv_status gv_pauli_sum_plan(gv_pauli_sum h, int32_t n_state, gv_precision prec, gv_engine engine,
+                            int64_t *passes, int64_t *max_pass_terms, int64_t *loose_terms);
+
 /* Device bytes the Hamiltonian needs: the FP64 diagonal of its Z-only part
  * (2^n doubles) followed by the off-diagonal term tables. */
 gv_status gv_pauli_sum_device_bytes(gv_pauli_sum h, size_t *bytes);
@@ -215,7 +224,9 @@ typedef struct {
 
 /* Restricted update of Eq. 11: the gradient is computed for the RY and RZ
  * angles of these qubits in every layer (2 |B| (layers + final_rotation)
- * entries) and written as 0 elsewhere. */
+ * entries) and written as 0 elsewhere.  An empty block (qubit_mask = 0)
+ * asks for the energy alone: no reverse sweep runs and the gradient is all
+ * zeros (the shifted evaluations of the parameter-shift rule, Eq. 13). */
 typedef struct {
     uint64_t qubit_mask;
 } gv_cluster;
@@ -310,17 +321,22 @@ gv_status gv_profile_read(gv_state st, int32_t kind, int64_t *launches, double *
  *        GV_STREAM_TRIAD  dst = src0 + src1.
  *   width: bytes per lane per access, 4, 8 or 16; unroll: accesses in flight
  *   per lane, 1, 2, 4 or 8; nontemporal != 0 uses non-temporal loads/stores;
- *   grid: blocks of 256 lanes, 0 = one block per 256 * unroll accesses.
- * bytes must be a positive multiple of 32 KiB; every buffer the kind uses must
- * hold `bytes` device bytes (READ writes at most 4 KiB of dst, never in
- * practice), 256-byte aligned.  Enqueues on `stream` and returns. */
+ *   grid: blocks of 256 lanes, 0 = one block per 256 * unroll accesses;
+ *   tile_shift: 0 = linear order; s in 4..40 = the layout of a state-vector
+ *   tile pass: bits 0..3 of an access's index stay, bits 4..11 move to bits
+ *   s..s+7 and the other bits fill the rest in order (runs of 16 accesses lie
+ *   2^s accesses apart); then bytes / width must be a power of two >= 2^(s+8).
+ * unroll may also be 16.  bytes must be a positive multiple of 64 KiB; every
+ * buffer the kind uses must hold `bytes` device bytes (READ writes at most
+ * 4 KiB of dst, never in practice), 256-byte aligned.  Enqueues on `stream`
+ * and returns. */
 typedef enum {
     GV_STREAM_READ = 0, GV_STREAM_WRITE = 1, GV_STREAM_COPY = 2, GV_STREAM_RMW = 3,
     GV_STREAM_TRIAD = 4
 } gv_stream_kind;
 gv_status gv_stream_probe(int32_t kind, int32_t width, int32_t unroll, int32_t nontemporal,
-                          int32_t grid, void *dst, const void *src0, const void *src1,
-                          size_t bytes, void *stream);
+                          int32_t grid, int32_t tile_shift, void *dst, const void *src0,
+                          const void *src1, size_t bytes, void *stream);
 
 #ifdef __cplusplus
 }

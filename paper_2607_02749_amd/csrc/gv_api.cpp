@@ -198,16 +198,19 @@ gv_status work_layout(const gv_ansatz &a, gv_precision prec, gv_engine eng, gv_g
     const int64_t P = nparams(a);
     const int R = rot_layers(a);
     size_t off = 0;
-    w.epart = off;
-    off += align_up(2 * kPartCols * sizeof(double));
+    TilePlan plan;
     if (fused_ok(eng, a.n)) {
-        TilePlan plan;
         if (!make_tile_plan(a.n, choose_K(a.n), choose_C(prec, choose_K(a.n)), &plan))
             return set_error(GV_EUNSUPPORTED, "no tile plan for n=%d", a.n);
         w.grid = fused_grid(prec, plan, a.n);
-        // the energy partials (2 x kPartCols) also take one column per block
-        if (w.grid > kPartCols)
-            return set_error(GV_EUNSUPPORTED, "grid %d exceeds the energy partials", w.grid);
+    } else {
+        w.grid = kPlainGrid;
+    }
+    // energy partials: 2 rows of max(kPartCols, grid) columns (the fused
+    // turnaround writes one column per block)
+    w.epart = off;
+    off += align_up(2 * (size_t)std::max(kPartCols, w.grid) * sizeof(double));
+    if (fused_ok(eng, a.n)) {
         const int K = choose_K(a.n);
         const Chunks ch = make_chunks(a.n, K, choose_logr(K));
         w.dtab_stride = align_up((size_t)ch.off[4] * s);
@@ -222,8 +225,6 @@ gv_status work_layout(const gv_ansatz &a, gv_precision prec, gv_engine eng, gv_g
         w.ldtab_stride = align_up((size_t)ldiag_entries(a.n, K, choose_logr(K)) * s);
         w.ldtab = off;
         off += w.ldtab_stride * (size_t)(R > 0 ? 2 * R : 1);
-    } else {
-        w.grid = kPlainGrid;
     }
     w.part = off;
     off += align_up((size_t)P * w.grid * sizeof(double) + 8);
@@ -239,8 +240,6 @@ gv_status work_layout(const gv_ansatz &a, gv_precision prec, gv_engine eng, gv_g
         off += align_up(A * s) * (size_t)(R - 2);
     }
     if (mode == GV_GRAD_STORE && fused_ok(eng, a.n)) {
-        TilePlan plan;
-        make_tile_plan(a.n, choose_K(a.n), choose_C(prec, choose_K(a.n)), &plan);
         w.ckpt = off;  // the output of every pass but the last
         off += align_up(A * s) * (size_t)store_slots(a, plan.npass);
     }
@@ -733,11 +732,51 @@ static void pauli_layout(const gv_pauli_s *h, size_t *diag, size_t *cls, size_t 
     *total = off;
 }
 
-// Group the off-diagonal terms by flip mask and cover the classes with tiles
-// of K index bits that keep bits 0..C-1: a class joins a tile when its flip
-// bits fit; every class sits in exactly one tile.  Classes whose flip bits
+// Bits of the tile a cover pass should take next: grown from `seed` one bit
+// at a time, each time the bit that completes the most pending classes
+// (weighted by their terms), ties broken by the number of pending classes
+// the bit could still complete with the free slots left, then by the bit.
+static uint64_t grow_tile(uint64_t tile, int K, int n, const std::vector<uint64_t> &hx,
+                          const std::vector<int64_t> &wt, const std::vector<char> &done)
+{
+    while (__builtin_popcountll(tile) < K) {
+        const int free_after = K - __builtin_popcountll(tile) - 1;
+        int best_q = -1;
+        int64_t best_gain = -1, best_part = -1;
+        for (int q = 0; q < n; ++q) {
+            const uint64_t b = 1ull << q;
+            if (tile & b) continue;
+            int64_t gain = 0, part = 0;
+            for (size_t c = 0; c < hx.size(); ++c) {
+                if (done[c] || !(hx[c] & b)) continue;
+                const uint64_t miss = hx[c] & ~(tile | b);
+                if (!miss) gain += wt[c];
+                else if (__builtin_popcountll(miss) <= free_after) part += 1;
+            }
+            if (gain > best_gain || (gain == best_gain && part > best_part)) {
+                best_q = q;
+                best_gain = gain;
+                best_part = part;
+            }
+        }
+        if (best_q < 0) break;
+        tile |= 1ull << best_q;
+    }
+    return tile;
+}
+
+// Group the off-diagonal terms by flip mask (classes) and cover the classes
+// with tiles of K index bits that keep bits 0..C-1: a class goes to a tile
+// that holds its flip bits, and every class sits in exactly one tile.  The
+// tiles are chosen greedily to cover as many pending terms as possible
+// (several seeds per pass, the best kept), with at most kOffPassTerms terms
+// per pass so the pass stages all of them in LDS.  Within a class the terms
+// are ordered by (real / imaginary phase, z restricted to the register bits
+// of the pass's load layout), and the last term of each such group is
+// flagged: the kernel sums a group's signed coefficients per thread and
+// applies the group's register sign pattern once.  Classes whose flip bits
 // cannot fit any tile are applied term by term.
-static void build_cover(gv_pauli_s *h, int K, int C)
+static void build_cover(gv_pauli_s *h, int K, int C, int logr)
 {
     h->classes.clear();
     h->class_terms.clear();
@@ -749,25 +788,54 @@ static void build_cover(gv_pauli_s *h, int K, int C)
     std::map<uint64_t, std::vector<int64_t>> by_x;
     for (size_t k = 0; k < h->ox.size(); ++k) by_x[h->ox[k]].push_back((int64_t)k);
     const uint64_t low = (C >= 64) ? ~0ull : ((1ull << C) - 1);
-    std::vector<uint64_t> pending;
+    // classes, a class of more than kOffPassTerms terms split into several
+    // with the same flip mask (their factors add on the same pairs)
+    std::vector<uint64_t> xs, hx;
+    std::vector<int64_t> wt;
+    std::vector<std::vector<int64_t>> cterms;
     for (const auto &kv : by_x) {
         if (__builtin_popcountll(kv.first & ~low) > K - C) {
             for (int64_t k : kv.second) h->loose_terms.push_back(k);
-        } else {
-            pending.push_back(kv.first);
+            continue;
+        }
+        for (size_t i0 = 0; i0 < kv.second.size(); i0 += kOffPassTerms) {
+            const size_t i1 = std::min(kv.second.size(), i0 + (size_t)kOffPassTerms);
+            xs.push_back(kv.first);
+            hx.push_back(kv.first & ~low);
+            wt.push_back((int64_t)(i1 - i0));
+            cterms.emplace_back(kv.second.begin() + i0, kv.second.begin() + i1);
         }
     }
-    while (!pending.empty()) {
-        uint64_t tile = low;
-        std::vector<uint64_t> chosen, rest;
-        for (uint64_t x : pending) {
-            if (__builtin_popcountll(tile | x) <= K) {
-                tile |= x;
-                chosen.push_back(x);
-            } else {
-                rest.push_back(x);
+    std::vector<char> done(xs.size(), 0);
+    size_t left = xs.size();
+    while (left > 0) {
+        // seeds: the low bits alone, and the low bits plus each flip bit of
+        // the pending classes with the most terms
+        std::vector<uint64_t> seeds{low};
+        {
+            std::vector<size_t> idx;
+            for (size_t c = 0; c < xs.size(); ++c)
+                if (!done[c]) idx.push_back(c);
+            std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return wt[a] > wt[b]; });
+            for (size_t i = 0; i < idx.size() && seeds.size() < 9; ++i)
+                if (__builtin_popcountll(low | hx[idx[i]]) <= K) seeds.push_back(low | hx[idx[i]]);
+        }
+        uint64_t best_tile = 0;
+        int64_t best_cov = -1;
+        for (uint64_t seed : seeds) {
+            const uint64_t t = grow_tile(seed, K, n, hx, wt, done);
+            int64_t cov = 0, nt = 0;
+            for (size_t c = 0; c < xs.size(); ++c)
+                if (!done[c] && !(hx[c] & ~t) && nt + wt[c] <= kOffPassTerms) {
+                    cov += wt[c];
+                    nt += wt[c];
+                }
+            if (cov > best_cov) {
+                best_cov = cov;
+                best_tile = t;
             }
         }
+        uint64_t tile = best_tile;
         for (int q = 0; q < n && __builtin_popcountll(tile) < K; ++q) tile |= 1ull << q;
         OffPass op;
         int j = 0;
@@ -777,20 +845,36 @@ static void build_cover(gv_pauli_s *h, int K, int C)
                 where[q] = (int8_t)j;
                 op.pos[j++] = (int8_t)q;
             }
+        // register bits of the load layout: tile bits K - logr .. K - 1
+        uint64_t regmask = 0;
+        for (int r = K - logr; r < K; ++r) regmask |= 1ull << op.pos[r];
         op.c0 = (int)h->classes.size();
-        for (uint64_t x : chosen) {
+        int64_t nt = 0;
+        for (size_t c = 0; c < xs.size(); ++c) {
+            if (done[c] || (hx[c] & ~tile) || nt + wt[c] > kOffPassTerms) continue;
+            done[c] = 1;
+            --left;
+            nt += wt[c];
+            const uint64_t x = xs[c];
             OffClass cl;
             cl.x = x;
             cl.xu = 0;
             for (int q = 0; q < n; ++q)
                 if ((x >> q) & 1) cl.xu |= 1u << where[q];
             cl.t0 = (int32_t)h->class_terms.size();
-            for (int64_t k : by_x[x]) {
+            std::vector<int64_t> ks = cterms[c];
+            auto key = [&](int64_t k) {
+                const int imag = __builtin_popcountll(h->ox[k] & h->oz[k]) & 1;
+                return std::make_pair(imag, h->oz[k] & regmask);
+            };
+            std::stable_sort(ks.begin(), ks.end(), [&](int64_t a, int64_t b) { return key(a) < key(b); });
+            for (size_t i = 0; i < ks.size(); ++i) {
+                const int64_t k = ks[i];
                 OffTerm tm;
                 tm.z = h->oz[k];
                 tm.c = h->oc[k];
                 tm.ph = __builtin_popcountll(h->ox[k] & h->oz[k]) & 3;
-                tm.pad = 0;
+                tm.pad = (i + 1 == ks.size() || key(ks[i + 1]) != key(k)) ? kOffGroupEnd : 0;
                 h->class_terms.push_back(tm);
             }
             cl.t1 = (int32_t)h->class_terms.size();
@@ -798,9 +882,46 @@ static void build_cover(gv_pauli_s *h, int K, int C)
             h->classes.push_back(cl);
         }
         op.c1 = (int)h->classes.size();
+        // every pass takes a class: the seeded tiles each cover the class
+        // they were seeded with, which holds at most kOffPassTerms terms
+        if (op.c1 == op.c0) {   // (defensive) apply what is left term by term
+            for (size_t c = 0; c < xs.size(); ++c)
+                if (!done[c]) {
+                    done[c] = 1;
+                    --left;
+                    for (int64_t k : cterms[c]) h->loose_terms.push_back(k);
+                }
+            break;
+        }
         h->off_passes.push_back(op);
-        pending.swap(rest);
     }
+}
+
+gv_status gv_pauli_sum_plan(gv_pauli_sum h, int32_t n_state, gv_precision prec, gv_engine engine,
+                            int64_t *passes, int64_t *max_pass_terms, int64_t *loose_terms)
+{
+    if (!h) return set_error(GV_EINVAL, "pauli sum is NULL");
+    if (prec != GV_C64 && prec != GV_C128) return set_error(GV_EINVAL, "precision %d", prec);
+    if (engine != GV_ENGINE_FUSED && engine != GV_ENGINE_PLAIN) return set_error(GV_EINVAL, "engine");
+    if (n_state != h->n) return set_error(GV_ESTATE, "pauli sum n=%d but n=%d", h->n, n_state);
+    gv_pauli_s tmp;
+    tmp.n = h->n;
+    tmp.ox = h->ox;
+    tmp.oz = h->oz;
+    tmp.oc = h->oc;
+    int64_t np = 0, mx = 0, lo = (int64_t)h->ox.size();
+    if (fused_ok(engine, h->n)) {
+        const int K = choose_K(h->n);
+        build_cover(&tmp, K, choose_C(prec, K), choose_logr(K));
+        np = (int64_t)tmp.off_passes.size();
+        for (const OffPass &op : tmp.off_passes)
+            mx = std::max<int64_t>(mx, tmp.classes[op.c1 - 1].t1 - tmp.classes[op.c0].t0);
+        lo = (int64_t)tmp.loose_terms.size();
+    }
+    if (passes) *passes = np;
+    if (max_pass_terms) *max_pass_terms = mx;
+    if (loose_terms) *loose_terms = lo;
+    return GV_OK;
 }
 
 gv_status gv_pauli_sum_device_bytes(gv_pauli_sum h, size_t *bytes)
@@ -832,7 +953,7 @@ static gv_status prepare_impl(gv_pauli_sum h, gv_precision prec, gv_engine engin
     const int n = h->n;
     if (fused_ok(engine, n)) {
         const int K = choose_K(n);
-        build_cover(h, K, choose_C(prec, K));
+        build_cover(h, K, choose_C(prec, K), choose_logr(K));
     } else {
         h->classes.clear();
         h->class_terms.clear();
@@ -1201,23 +1322,30 @@ gv_status gv_profile_read(gv_state st, int32_t kind, int64_t *launches, double *
 }
 
 gv_status gv_stream_probe(int32_t kind, int32_t width, int32_t unroll, int32_t nontemporal,
-                          int32_t grid, void *dst, const void *src0, const void *src1,
-                          size_t bytes, void *stream)
+                          int32_t grid, int32_t tile_shift, void *dst, const void *src0,
+                          const void *src1, size_t bytes, void *stream)
 {
     if (kind < GV_STREAM_READ || kind > GV_STREAM_TRIAD) return set_error(GV_EINVAL, "kind %d", kind);
     if (width != 4 && width != 8 && width != 16) return set_error(GV_EINVAL, "width %d", width);
-    if (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8)
+    if (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8 && unroll != 16)
         return set_error(GV_EINVAL, "unroll %d", unroll);
     if (grid < 0) return set_error(GV_EINVAL, "grid %d", grid);
-    if (bytes == 0 || bytes % 32768 != 0)
-        return set_error(GV_EINVAL, "bytes must be a positive multiple of 32 KiB");
+    if (bytes == 0 || bytes % 65536 != 0)
+        return set_error(GV_EINVAL, "bytes must be a positive multiple of 64 KiB");
+    if (tile_shift != 0) {
+        const size_t nvec = bytes / (size_t)width;
+        if (tile_shift < 4 || tile_shift > 40 || (nvec & (nvec - 1)) != 0 ||
+            nvec < ((size_t)1 << (tile_shift + 8)))
+            return set_error(GV_EINVAL, "tile_shift %d needs a power-of-two count >= 2^%d",
+                             tile_shift, tile_shift + 8);
+    }
     if (!dst) return set_error(GV_EINVAL, "dst is NULL");
     if (kind != GV_STREAM_WRITE && !src0) return set_error(GV_EINVAL, "src0 is NULL");
     if (kind == GV_STREAM_TRIAD && !src1) return set_error(GV_EINVAL, "src1 is NULL");
     if (!aligned(dst) || (src0 && !aligned(src0)) || (src1 && !aligned(src1)))
         return set_error(GV_EINVAL, "buffers must be %zu-byte aligned", kAlign);
     return check_hip(stream_probe(kind, width, unroll, nontemporal != 0, dst, src0, src1, bytes,
-                                  grid, (hipStream_t)stream),
+                                  grid, tile_shift, (hipStream_t)stream),
                      "stream probe");
 }
 

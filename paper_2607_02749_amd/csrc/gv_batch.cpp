@@ -34,6 +34,7 @@ struct gv_batch_s {
     // events (or none: then they run one after another on the batch stream)
     std::vector<gv_instance> large;
     std::vector<double *> large_e, large_g;
+    std::vector<uint64_t> large_q;   // their qubit blocks (0: energy only)
     std::vector<gv_state_s> states;
     std::vector<uint8_t *> masks;
     bool side_streams = true;
@@ -162,6 +163,14 @@ gv_status launch_all(gv_batch b, hipStream_t s)
         gv_state_s &st = b->states[j];
         st.stream = fork ? b->side[j % kSideStreams] : s;
         const gv_instance &I = b->large[j];
+        if (b->large_q[j] == 0) {   // empty block: the energy alone
+            if (gv_status r = gv_apply_ansatz(&st, I.params_dev, &I.ansatz)) return r;
+            if (gv_status r = gv_energy(&st, I.h, b->large_e[j])) return r;
+            const int64_t P = 2ll * I.ansatz.n * (I.ansatz.layers + I.ansatz.final_rotation);
+            if (gv_status r = check_hip(fill_zero_f64(b->large_g[j], (u64)P, st.stream), "zero grad"))
+                return r;
+            continue;
+        }
         if (gv_status r = gv_energy_grad(&st, I.h, I.params_dev, &I.ansatz, b->masks[j],
                                          GV_GRAD_STORE, b->large_e[j], b->large_g[j]))
             return r;
@@ -328,6 +337,7 @@ static gv_status batch_create_impl(int32_t count, const gv_instance *inst,
         st.work = w + L.fwork[i];
         st.work_bytes = L.fwork_bytes[i];
         b->large.push_back(I);
+        b->large_q.push_back(qmask[i]);
         b->large_e.push_back(energies + 2 * (size_t)i);
         b->large_g.push_back(grads + goff[i]);
         b->states.push_back(st);

@@ -1305,14 +1305,33 @@ struct OffArgs {
 // A term of a cover pass as the inner loop uses it: z, its coefficient
 // with the fixed signs folded in (c, times -1 for ph & 2 and for the parity
 // of x & z), and per register r the sign of the register bits' share of
-// (i ^ x) & z (bit r of `regsign`) plus the real / imaginary choice (ph odd).
+// (i ^ x) & z (bit r of `regsign`) plus the real / imaginary choice (ph odd)
+// and whether it ends a group of terms with the same register signs and
+// phase parity (the host orders a class's terms that way).
 struct OffStaged {
     u64 z;
     double cf;
-    uint32_t regsign_imag;   // bits 0..15: register signs; bit 31: i^ph is imaginary
+    uint32_t regsign_imag;   // bits 0..15: register signs; bit 30: group end;
+                             // bit 31: i^ph is imaginary
     uint32_t pad;
 };
-constexpr int kOffStage = 512;  // terms staged in LDS per pass (the rest read in place)
+constexpr int kOffStage = kOffPassTerms;  // terms staged in LDS per pass (the rest read in place)
+
+template <int LOGR>
+__device__ __forceinline__ OffStaged stage_term(const OffTerm &tm, u64 x,
+                                                const RegMap<LOGR, false> &m)
+{
+    constexpr int NR = 1 << LOGR;
+    uint32_t pat = 0;
+    for (int r = 0; r < NR; ++r)
+        if (__popcll(m.off(r) & tm.z) & 1) pat |= 1u << r;
+    double cf = tm.c;
+    if ((tm.ph & 2) ^ ((__popcll(x & tm.z) & 1) << 1)) cf = -cf;
+    return OffStaged{tm.z, cf,
+                     pat | ((uint32_t)(tm.pad & kOffGroupEnd) << 30) |
+                         ((uint32_t)(tm.ph & 1) << 31),
+                     0u};
+}
 
 // One cover pass: the psi tile sits in LDS, so for every class (flip mask x
 // inside the tile) each amplitude reads its partner psi_{i^x} there and adds
@@ -1340,13 +1359,7 @@ __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const Off
         const OffClass C = a.cls[c];
         for (int k = C.t0 + t; k < C.t1; k += blockDim.x) {
             if (k - k0 >= nst) break;
-            const OffTerm tm = a.terms[k];
-            uint32_t pat = 0;
-            for (int r = 0; r < T::NR; ++r)
-                if (__popcll(m.off(r) & tm.z) & 1) pat |= 1u << r;
-            double cf = tm.c;
-            if ((tm.ph & 2) ^ ((__popcll(C.x & tm.z) & 1) << 1)) cf = -cf;
-            stg[k - k0] = OffStaged{tm.z, cf, pat | ((uint32_t)(tm.ph & 1) << 31), 0u};
+            stg[k - k0] = stage_term<LOGR>(a.terms[k], C.x, m);
         }
     }
     __syncthreads();
@@ -1369,20 +1382,15 @@ __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const Off
             R A[T::NR], B[T::NR];
 #pragma unroll
             for (int r = 0; r < T::NR; ++r) A[r] = B[r] = R(0);
+            // a group's terms share their register signs: sum their signed
+            // coefficients for this thread, then spread the sum over the
+            // registers once (the group-end flag is the same in every lane)
+            R w = 0;
             for (int k = C.t0; k < C.t1; ++k) {
-                OffStaged q;
-                if (k - k0 < nst) {
-                    q = stg[k - k0];
-                } else {   // beyond the staging buffer: build the entry in place
-                    const OffTerm tm = a.terms[k];
-                    uint32_t pat = 0;
-                    for (int r = 0; r < T::NR; ++r)
-                        if (__popcll(m.off(r) & tm.z) & 1) pat |= 1u << r;
-                    double cf = tm.c;
-                    if ((tm.ph & 2) ^ ((__popcll(C.x & tm.z) & 1) << 1)) cf = -cf;
-                    q = OffStaged{tm.z, cf, pat | ((uint32_t)(tm.ph & 1) << 31), 0u};
-                }
-                const R w = (__popcll(bt & q.z) & 1) ? -(R)q.cf : (R)q.cf;
+                const OffStaged q = k - k0 < nst ? stg[k - k0]
+                                                 : stage_term<LOGR>(a.terms[k], C.x, m);
+                w += (__popcll(bt & q.z) & 1) ? -(R)q.cf : (R)q.cf;
+                if (!((q.regsign_imag >> 30) & 1)) continue;
                 if (q.regsign_imag >> 31) {
 #pragma unroll
                     for (int r = 0; r < T::NR; ++r) B[r] += ((q.regsign_imag >> r) & 1) ? -w : w;
@@ -1390,6 +1398,7 @@ __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const Off
 #pragma unroll
                     for (int r = 0; r < T::NR; ++r) A[r] += ((q.regsign_imag >> r) & 1) ? -w : w;
                 }
+                w = 0;
             }
 #pragma unroll
             for (int r = 0; r < T::NR; ++r) {
@@ -1839,6 +1848,9 @@ __device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh, OffSt
         for (u64 i = t; i < dim; i += nt) psi[i] = cmul(psi[i], diag_entry<R>(i, d));
         __syncthreads();
     }
+    // an empty qubit block asks for the energy alone: no lam, no reverse
+    // sweep, a zero gradient
+    const bool eonly = I.qmask == 0;
     // energy: diagonal part with lam = D psi, then the off-diagonal cover passes
     {
         double e = 0.0;
@@ -1846,6 +1858,7 @@ __device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh, OffSt
             const cx<R> v = psi[i];
             const double d = I.hdiag[i];
             e += d * ((double)v.re * v.re + (double)v.im * v.im);
+            if (eonly) continue;
             cx<R> o;
             o.re = (R)d * v.re;
             o.im = (R)d * v.im;
@@ -1872,8 +1885,12 @@ __device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh, OffSt
         o.terms = I.terms;
         o.epart = I.energy;
         o.estride = 1;
-        off_body<R, K, LOGR>(psi, lam, o, 0, 1, 0, lds, sh, stg);
+        off_body<R, K, LOGR>(psi, eonly ? nullptr : lam, o, 0, 1, 0, lds, sh, stg);
         __syncthreads();
+    }
+    if (eonly) {
+        for (int64_t p = t; p < 2ll * I.n * R_; p += nt) I.grad[p] = 0.0;
+        return;
     }
     // reverse sweep
     bool post = !I.zonly;

@@ -42,8 +42,10 @@ struct OffTerm {
     u64 z;
     double c;
     int32_t ph;     // popcount(x & z) mod 4: the i^ph factor of P(x, z)
-    int32_t pad;
+    int32_t pad;    // kOffGroupEnd: last term of its (phase parity, register-bit z) group
 };
+constexpr int32_t kOffGroupEnd = 1;
+constexpr int kOffPassTerms = 512;   // terms one cover pass stages in LDS
 // A cover pass: a tile whose bits hold every flip bit of its classes.
 struct OffPass {
     int8_t pos[kMaxTileBits];
@@ -255,7 +257,7 @@ hipError_t copy_vector(void *dst, const void *src, size_t bytes, hipStream_t s);
 // streaming-bandwidth probe (gv_stream.hip): kind is a gv_stream_kind
 enum { STREAM_READ = 0, STREAM_WRITE = 1, STREAM_COPY = 2, STREAM_RMW = 3, STREAM_TRIAD = 4 };
 hipError_t stream_probe(int kind, int width, int unroll, int nt, void *dst, const void *s0,
-                        const void *s1, size_t bytes, int grid, hipStream_t s);
+                        const void *s1, size_t bytes, int grid, int shift, hipStream_t s);
 
 // one cover pass of off-diagonal classes: lam += (sum of the classes) psi
 // (lam may be NULL); energy partials epart[b], epart[estride + b] += the

@@ -83,6 +83,8 @@ def lib():
     L.gv_pauli_sum_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                     ctypes.POINTER(i64)]
     L.gv_pauli_sum_device_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.gv_pauli_sum_plan.argtypes = [vp, i32, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                    ctypes.POINTER(i64)]
     L.gv_pauli_sum_prepare.argtypes = [vp, vp, vp, sz]
     L.gv_energy.argtypes = [vp, vp, vp]
     L.gv_energy_grad.argtypes = [vp, vp, vp, AP, vp, i32, vp, vp]
@@ -95,7 +97,7 @@ def lib():
     L.gv_batch_run.argtypes = [vp]
     L.gv_batch_destroy.argtypes = [vp]
     L.gv_batch_energy_grad.argtypes = [i32, IP, CP, i32, vp, sz, vp, vp, vp]
-    L.gv_stream_probe.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, sz, vp]
+    L.gv_stream_probe.argtypes = [i32, i32, i32, i32, i32, i32, vp, vp, vp, sz, vp]
     L.gv_profile_enable.argtypes = [vp, i32]
     L.gv_profile_reset.argtypes = [vp]
     L.gv_profile_read.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
@@ -106,7 +108,7 @@ def lib():
                  "gv_pauli_sum_info", "gv_pauli_sum_device_bytes", "gv_pauli_sum_prepare",
                  "gv_pauli_sum_prepare_for", "gv_energy", "gv_energy_grad", "gv_batch_query",
                  "gv_batch_create", "gv_batch_run", "gv_batch_destroy", "gv_batch_energy_grad",
-                 "gv_stream_probe"):
+                 "gv_stream_probe", "gv_pauli_sum_plan"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -167,12 +169,13 @@ STREAM_KINDS = {"read": 0, "write": 1, "copy": 2, "rmw": 3, "triad": 4}
 
 def stream_probe(kind: str, width: int, unroll: int, nontemporal: bool, grid: int,
                  dst: torch.Tensor, src0: Optional[torch.Tensor] = None,
-                 src1: Optional[torch.Tensor] = None, nbytes: Optional[int] = None):
+                 src1: Optional[torch.Tensor] = None, nbytes: Optional[int] = None,
+                 tile_shift: int = 0):
     """Enqueue one streaming kernel of the bandwidth probe on the current
     stream (see gv_stream_probe in include/gv.h)."""
     nb = dst.numel() * dst.element_size() if nbytes is None else nbytes
     _check(lib().gv_stream_probe(STREAM_KINDS[kind], width, unroll, int(nontemporal), grid,
-                                 _ptr(dst), _ptr(src0), _ptr(src1), nb,
+                                 tile_shift, _ptr(dst), _ptr(src0), _ptr(src1), nb,
                                  _stream_ptr(dst.device)), "gv_stream_probe")
 
 
@@ -269,6 +272,15 @@ class PauliSum:
         a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib().gv_pauli_sum_info(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
                "gv_pauli_sum_info")
+        return a.value, b.value, c.value
+
+    def plan(self, precision="c64", engine="fused") -> Tuple[int, int, int]:
+        """(cover passes, most terms in one pass, terms applied one by one)
+        for the off-diagonal part on a state of this size (host planning)."""
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().gv_pauli_sum_plan(self.handle, self.n, _PREC[precision], _ENGINE[engine],
+                                       ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+               "gv_pauli_sum_plan")
         return a.value, b.value, c.value
 
     def prepare(self, state: State):
@@ -490,3 +502,35 @@ def batch_energy_grad(items, precision="c64", device="cuda"):
     # on that stream, so dropping it here is safe
     del owner, work
     return energies, grads
+
+
+class ParamShift:
+    """The parameter-shift gradient of Eq. 13 as one batched launch:
+    dE/dtheta_j = (E(theta + pi/2 e_j) - E(theta - pi/2 e_j)) / 2 for every
+    j in `indices` (all parameters by default, or a block's P_B of them),
+    i.e. 2 |indices| energy-only instances (empty qubit blocks) of one
+    ansatz and Hamiltonian, replayed from a HIP graph.  ``__call__(theta)``
+    returns (gradient entries at `indices`, the 2 |indices| shifted
+    energies)."""
+
+    def __init__(self, ansatz: Ansatz, h: PauliSum, indices=None, precision="c64",
+                 device="cuda", graph=True):
+        dev = _device(device)
+        self.device = dev
+        p = ansatz.num_params
+        self.indices = np.arange(p) if indices is None else np.asarray(indices, dtype=np.int64)
+        m = len(self.indices)
+        shift = torch.zeros(2 * m, p, dtype=torch.float64)
+        rows = torch.arange(m)
+        shift[2 * rows, torch.as_tensor(self.indices)] = np.pi / 2
+        shift[2 * rows + 1, torch.as_tensor(self.indices)] = -np.pi / 2
+        self.shift = shift.to(dev)
+        self.thetas = torch.zeros(2 * m, p, dtype=torch.float64, device=dev)
+        items = [(ansatz, self.thetas[i], h, 0) for i in range(2 * m)]
+        self.batch = Batch(items, precision, graph=graph, device=dev)
+
+    def __call__(self, theta: torch.Tensor):
+        self.thetas.copy_(theta.to(self.device).reshape(1, -1) + self.shift)
+        self.batch.run()
+        e = self.batch.energies[:, 0]
+        return 0.5 * (e[0::2] - e[1::2]), e

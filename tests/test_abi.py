@@ -133,3 +133,21 @@ def test_batch_call_validates_before_any_gpu_work():
     arr[0].ansatz = gv.Ansatz(8, 2).c()
     assert L.gv_batch_energy_grad(1, arr, cl, 0, fake, 1 << 20, None, fake, fake) == 3
     assert L.gv_batch_energy_grad(-1, arr, cl, 0, fake, 1 << 20, None, fake, fake) == 1
+
+
+def test_cover_plan_of_n32_workload():
+    # 2,000 two-qubit XX/YY/XZ/ZY terms on 32 qubits: tiles of 12 index bits
+    # keep the 4 low bits, so each pass holds 8 more; the planner must cover
+    # every term, stage at most 512 per pass, and use far fewer passes than
+    # one per pair of qubits
+    from paper_2607_02749_amd import synth
+    w = synth.workload_n32()
+    h = gv.PauliSum(32, w.x, w.z, w.c)
+    passes, most, loose = h.plan("c64")
+    print("n=32 cover passes", passes, "most terms in a pass", most, "loose", loose)
+    assert loose == 0
+    assert most <= 512
+    assert passes <= 24
+    # tiny registers run on the plain engine: every term one by one
+    h2 = gv.PauliSum(6, [3, 5], [0, 1], [1.0, 0.5])
+    assert h2.plan("c128") == (0, 0, 2)
