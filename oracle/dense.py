@@ -68,6 +68,22 @@ def circuit(n: int, layers: int, ent: int, final_rotation: int = 0) -> List[Tupl
             if ent == 4 and n > 2:
                 out.append(("cnot", n - 1, 0))
             out += [("cnot", q, q + 1) for q in range(n - 1)]
+        elif ent == 5:      # full: every pair, first qubit outer
+            out += [("cnot", i, j) for i in range(n) for j in range(i + 1, n)]
+        elif ent == 6:      # reverse linear
+            out += [("cnot", q, q + 1) for q in reversed(range(n - 1))]
+        elif ent == 7:      # pairwise: even pairs, then odd pairs
+            out += [("cnot", q, q + 1) for q in range(0, n - 1, 2)]
+            out += [("cnot", q, q + 1) for q in range(1, n - 1, 2)]
+        elif ent == 8:      # shifted circular alternating
+            ring = ([(n - 1, 0)] + [(q, q + 1) for q in range(n - 1)]) if n > 2 else \
+                [(q, q + 1) for q in range(n - 1)]
+            if n > 2:
+                s = l % len(ring)
+                ring = ring[len(ring) - s:] + ring[:len(ring) - s]
+            if l % 2:
+                ring = [(b, a) for a, b in ring]
+            out += [("cnot", a, b) for a, b in ring]
         elif ent != 0:
             raise ValueError("unknown entangler")
     return out

@@ -23,8 +23,19 @@
  *   - RY(t) = [[cos t/2, -sin t/2], [sin t/2, cos t/2]],
  *     RZ(t) = diag(exp(-i t/2), exp(+i t/2))            (Eq. 7);
  *   - entanglers: CZ on (q, q+1) for q = 0..n-2 (circular adds (n-1, 0));
- *     CNOT with control q, target q+1, applied for q = 0, 1, ..., n-2 in that
- *     order (circular applies CNOT(n-1 -> 0) first);
+ *     CNOT networks (Sec. IV-B names linear, circular and full patterns;
+ *     Sec. V-A also uses reverse-linear, pairwise and shifted-circular-
+ *     alternating ones), each a list of CNOT(control -> target) applied in
+ *     order:
+ *       linear          (q, q+1) for q = 0, 1, ..., n-2
+ *       circular        (n-1, 0) first (n > 2), then linear
+ *       full            (i, j) for i = 0..n-2, j = i+1..n-1, i outer
+ *       reverse linear  (q, q+1) for q = n-2 down to 0
+ *       pairwise        (q, q+1) for even q, then for odd q
+ *       sca             in layer l the circular list [(n-1, 0), (0, 1), ...,
+ *                       (n-2, n-1)] rotated right by l mod n, with control
+ *                       and target exchanged in the odd layers (for n <= 2
+ *                       the linear list);
  *   - Pauli string P(x, z) = i^{|x & z|} X^x Z^z over bit masks x, z, so that
  *     (P psi)_i = i^{|x & z|} (-1)^{popcount((i ^ x) & z)} psi_{i ^ x}.
  *
@@ -46,7 +57,8 @@ typedef double complex cplx;
 
 enum { G_RY = 0, G_RZ = 1, G_CZ = 2, G_CNOT = 3 };
 enum { ENT_NONE = 0, ENT_CZ_LINEAR = 1, ENT_CZ_CIRCULAR = 2,
-       ENT_CNOT_LINEAR = 3, ENT_CNOT_CIRCULAR = 4 };
+       ENT_CNOT_LINEAR = 3, ENT_CNOT_CIRCULAR = 4, ENT_CNOT_FULL = 5,
+       ENT_CNOT_REVERSE_LINEAR = 6, ENT_CNOT_PAIRWISE = 7, ENT_CNOT_SCA = 8 };
 
 typedef struct {
     int kind;
@@ -62,7 +74,7 @@ int gvo_num_params(int n, int layers, int final_rotation)
 /* Upper bound on the number of gates of the circuit. */
 static int64_t max_gates(int n, int layers, int final_rotation)
 {
-    return (int64_t)(layers + final_rotation) * (3 * (int64_t)n + 1);
+    return (int64_t)(layers + final_rotation) * (2 * (int64_t)n + (int64_t)n * n + 1);
 }
 
 /* Gate list of the circuit in application order. Returns the count, or -1. */
@@ -105,6 +117,43 @@ static int64_t build_circuit(int n, int layers, int ent, int final_rotation, gat
                 g[k++] = t;
             }
             break;
+        case ENT_CNOT_FULL:
+            for (int i = 0; i + 1 < n; ++i)
+                for (int j = i + 1; j < n; ++j) {
+                    gate_t t = { G_CNOT, i, j, -1 };
+                    g[k++] = t;
+                }
+            break;
+        case ENT_CNOT_REVERSE_LINEAR:
+            for (int q = n - 2; q >= 0; --q) {
+                gate_t t = { G_CNOT, q, q + 1, -1 };
+                g[k++] = t;
+            }
+            break;
+        case ENT_CNOT_PAIRWISE:
+            for (int start = 0; start < 2; ++start)
+                for (int q = start; q + 1 < n; q += 2) {
+                    gate_t t = { G_CNOT, q, q + 1, -1 };
+                    g[k++] = t;
+                }
+            break;
+        case ENT_CNOT_SCA: {
+            /* circular list: entry 0 is (n-1, 0), entry e >= 1 is (e-1, e) */
+            const int m = n > 2 ? n : n - 1;
+            for (int e = 0; e < m; ++e) {
+                int src = n > 2 ? ((e - l) % m + m) % m : e;
+                int c = n > 2 ? (src == 0 ? n - 1 : src - 1) : src;
+                int t = n > 2 ? (src == 0 ? 0 : src) : src + 1;
+                if (l & 1) {
+                    int tmp = c;
+                    c = t;
+                    t = tmp;
+                }
+                gate_t gt = { G_CNOT, c, t, -1 };
+                g[k++] = gt;
+            }
+            break;
+        }
         default:
             return -1;
         }

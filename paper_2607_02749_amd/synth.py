@@ -44,6 +44,10 @@ ENT_CZ_LINEAR = 1
 ENT_CZ_CIRCULAR = 2
 ENT_CNOT_LINEAR = 3
 ENT_CNOT_CIRCULAR = 4
+ENT_CNOT_FULL = 5
+ENT_CNOT_REVERSE_LINEAR = 6
+ENT_CNOT_PAIRWISE = 7
+ENT_CNOT_SCA = 8
 
 P_IN = 0.6
 P_OUT = 0.05

@@ -13,7 +13,8 @@ from oracle import dense
 from paper_2607_02749_amd import synth
 
 ENTS = [synth.ENT_NONE, synth.ENT_CZ_LINEAR, synth.ENT_CZ_CIRCULAR,
-        synth.ENT_CNOT_LINEAR, synth.ENT_CNOT_CIRCULAR]
+        synth.ENT_CNOT_LINEAR, synth.ENT_CNOT_CIRCULAR, synth.ENT_CNOT_FULL,
+        synth.ENT_CNOT_REVERSE_LINEAR, synth.ENT_CNOT_PAIRWISE, synth.ENT_CNOT_SCA]
 
 
 def rand_terms(rng, n, m, offdiag=True):
@@ -285,3 +286,77 @@ def test_param_mask_is_support_of_block_gradient(final_rotation):
                                    final_rotation=final_rotation)
         assert abs(e.real - e_cf) < 1e-12
         assert np.abs(gm - g_cf).max() < 1e-12
+
+
+def _bits(v, n):
+    return [(v >> q) & 1 for q in range(n)]
+
+
+def _val(b):
+    return sum(bit << q for q, bit in enumerate(b))
+
+
+def _basis_image(ent, n, b):
+    """Where one layer of each CNOT network sends the basis state |b>,
+    written out by hand per pattern (Sec. IV-B / Sec. V-A)."""
+    x = _bits(b, n)
+    if ent == synth.ENT_CNOT_LINEAR:                  # prefix XOR
+        return _val([sum(x[:j + 1]) % 2 for j in range(n)])
+    if ent in (synth.ENT_CNOT_REVERSE_LINEAR, synth.ENT_CNOT_FULL):
+        return _val([x[0]] + [x[j] ^ x[j - 1] for j in range(1, n)])
+    if ent == synth.ENT_CNOT_PAIRWISE:
+        out = [x[0]]
+        for j in range(1, n):
+            out.append(x[j] ^ x[j - 1] if j % 2 else x[j] ^ x[j - 1] ^ x[j - 2])
+        return _val(out)
+    if ent in (synth.ENT_CNOT_CIRCULAR, synth.ENT_CNOT_SCA):   # SCA's layer 0 is circular
+        x0 = x[0] ^ x[n - 1]
+        y = [x0] + x[1:]
+        return _val([sum(y[:j + 1]) % 2 for j in range(n)])
+    raise ValueError(ent)
+
+
+@pytest.mark.parametrize("ent", [synth.ENT_CNOT_LINEAR, synth.ENT_CNOT_CIRCULAR,
+                                 synth.ENT_CNOT_FULL, synth.ENT_CNOT_REVERSE_LINEAR,
+                                 synth.ENT_CNOT_PAIRWISE, synth.ENT_CNOT_SCA])
+def test_cnot_networks_map_basis_states(ent):
+    # RY(pi) on the set qubits of layer 1 prepares |b>; one CNOT network
+    # sends it to |M b>, M given by hand for every pattern
+    rng = np.random.default_rng(ent)
+    for n in (3, 5, 8, 11):
+        for b in list(rng.integers(0, 1 << n, size=5)) + [1, (1 << n) - 1]:
+            b = int(b)
+            th = cf.basis_theta(n, 1, b)
+            psi = oracle.prepare(n, 1, ent, th)
+            want = np.zeros(1 << n, complex)
+            want[_basis_image(ent, n, b)] = 1.0
+            assert np.abs(psi - want).max() < 1e-14, (ent, n, b)
+
+
+def test_sca_second_layer_by_hand():
+    # layer 1 of SCA: the circular list rotated right by one, control and
+    # target exchanged: (n-1 -> n-2), (0 -> n-1), (1 -> 0), (2 -> 1), ...,
+    # (n-2 -> n-3), applied in that order
+    for n in (4, 6, 9):
+        rng = np.random.default_rng(n)
+        for b in rng.integers(0, 1 << n, size=6):
+            b = int(b)
+            x = _bits(_basis_image(synth.ENT_CNOT_SCA, n, b), n)   # after layer 0
+            x[n - 2] ^= x[n - 1]
+            x[n - 1] ^= x[0]
+            for t in range(0, n - 2):
+                x[t] ^= x[t + 1]
+            th = cf.basis_theta(n, 2, b)
+            psi = oracle.prepare(n, 2, synth.ENT_CNOT_SCA, th)
+            assert abs(abs(psi[_val(x)]) - 1.0) < 1e-14, (n, b)
+
+
+def test_reverse_linear_equals_full_cnot_network():
+    # known identity: the full CNOT network and the reverse-linear ladder are
+    # the same unitary (both send b_j to b_j ^ b_{j-1})
+    for n in (3, 4, 6):
+        th = np.random.default_rng(n).uniform(-np.pi, np.pi, 2 * n * 2)
+        a = dense.state(n, 2, synth.ENT_CNOT_FULL, th)
+        b = dense.state(n, 2, synth.ENT_CNOT_REVERSE_LINEAR, th)
+        assert np.abs(a - b).max() < 1e-13
+        assert oracle.num_gates(n, 1, synth.ENT_CNOT_FULL) == 2 * n + n * (n - 1) // 2
