@@ -230,13 +230,15 @@ def copy_probe(torch, gv, full=False):
     tiled = []
     if full:
         for kind in ("copy", "rmw"):
-            for shift in (0, 12, 20):
-                for g in (0, 3072):
-                    for u in (4, 16):
-                        ms = timed(lambda: gv.stream_probe(kind, 8, u, 0, g, bufs[0], bufs[1],
+            for w in (8, 16):
+                for shift in (0, 8, 10, 12, 14, 16, 17, 18, 19, 20, 21):
+                    if shift and (nb // w) < (1 << (shift + 8)):
+                        continue
+                    for u, nt in ((16, 0), (16, 1), (4, 1)):
+                        ms = timed(lambda: gv.stream_probe(kind, w, u, nt, 0, bufs[0], bufs[1],
                                                            bufs[2], nb, tile_shift=shift))
-                        tiled.append({"kind": kind, "width": 8, "unroll": u, "grid": g,
-                                      "tile_shift": shift, "ms": ms,
+                        tiled.append({"kind": kind, "width": w, "unroll": u, "grid": 0,
+                                      "nontemporal": nt, "tile_shift": shift, "ms": ms,
                                       "GBps": moved[kind] * nb / (ms * 1e-3) / 1e9})
     ms = timed(lambda: bufs[0].copy_(bufs[1]), 5)
     out = {"bytes_per_buffer": nb, "best": best,

@@ -63,13 +63,22 @@ typedef enum {
 
 typedef enum { GV_C64 = 0, GV_C128 = 1 } gv_precision;
 
-/* Entangler of each repeated layer (Sec. IV-B lists linear, circular, full). */
+/* Entangler of each repeated layer (Sec. IV-B lists linear, circular and
+ * full patterns; Sec. V-A also runs reverse-linear, pairwise and
+ * shifted-circular-alternating ones).  CNOT networks apply their gates in
+ * the order listed. */
 typedef enum {
     GV_ENT_NONE = 0,
     GV_ENT_CZ_LINEAR = 1,     /* CZ(q, q+1), q = 0..n-2 (all commute) */
     GV_ENT_CZ_CIRCULAR = 2,   /* linear plus CZ(n-1, 0) when n > 2 */
     GV_ENT_CNOT_LINEAR = 3,   /* CNOT(q -> q+1) applied for q = 0, 1, ..., n-2 */
-    GV_ENT_CNOT_CIRCULAR = 4  /* CNOT(n-1 -> 0) first (n > 2), then the linear ladder */
+    GV_ENT_CNOT_CIRCULAR = 4, /* CNOT(n-1 -> 0) first (n > 2), then the linear ladder */
+    GV_ENT_CNOT_FULL = 5,     /* CNOT(i -> j) for every i < j, i the outer loop */
+    GV_ENT_CNOT_REVERSE_LINEAR = 6, /* CNOT(q -> q+1) for q = n-2 down to 0 */
+    GV_ENT_CNOT_PAIRWISE = 7, /* CNOT(q -> q+1) for even q, then for odd q */
+    GV_ENT_CNOT_SCA = 8       /* layer l: the circular list (n-1 -> 0), (0 -> 1), ...,
+                                 (n-2 -> n-1) rotated right by l mod n, control and
+                                 target exchanged in odd layers (n <= 2: linear) */
 } gv_entangler;
 
 /* How the reverse sweep recovers the forward states at large n. */

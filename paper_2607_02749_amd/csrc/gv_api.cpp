@@ -181,7 +181,7 @@ static std::vector<FwdOp> snake_ops(int np, int upto, bool keep_last_single, boo
 // buffers the STORE mode needs: one per pass output except the last
 static int store_slots(const gv_ansatz &a, int np)
 {
-    const bool cnot = a.ent == GV_ENT_CNOT_LINEAR || a.ent == GV_ENT_CNOT_CIRCULAR;
+    const bool cnot = ent_is_cnot(a.ent);
     const int R = rot_layers(a);
     if (cnot || R < 2) return std::max(0, R - 2);
     const size_t m = std::max(snake_ops(np, R - 1, false, false).size(),
@@ -230,7 +230,7 @@ gv_status work_layout(const gv_ansatz &a, gv_precision prec, gv_engine eng, gv_g
     off += align_up((size_t)P * w.grid * sizeof(double) + 8);
     w.lam = off;
     off += align_up(A * s);
-    const bool cnot = a.ent == GV_ENT_CNOT_LINEAR || a.ent == GV_ENT_CNOT_CIRCULAR;
+    const bool cnot = ent_is_cnot(a.ent);
     if (fused_ok(eng, a.n) && cnot) {
         w.scratch = off;
         off += align_up(A * s);
@@ -258,7 +258,7 @@ static gv_status check_ansatz(const gv_ansatz *a)
     if (a->layers < 0 || a->layers > 4096) return set_error(GV_EINVAL, "layers=%d", a->layers);
     if (a->final_rotation != 0 && a->final_rotation != 1)
         return set_error(GV_EINVAL, "final_rotation must be 0 or 1");
-    if (a->ent < GV_ENT_NONE || a->ent > GV_ENT_CNOT_CIRCULAR)
+    if (a->ent < GV_ENT_NONE || a->ent > GV_ENT_CNOT_SCA)
         return set_error(GV_EINVAL, "unknown entangler %d", a->ent);
     return GV_OK;
 }
@@ -284,9 +284,8 @@ static std::vector<Gate> gate_list(const gv_ansatz &an)
         if (an.ent == GV_ENT_CZ_LINEAR || an.ent == GV_ENT_CZ_CIRCULAR) {
             for (int q = 0; q + 1 < n; ++q) g.push_back({2, q, q + 1, -1});
             if (an.ent == GV_ENT_CZ_CIRCULAR && n > 2) g.push_back({2, n - 1, 0, -1});
-        } else if (an.ent == GV_ENT_CNOT_LINEAR || an.ent == GV_ENT_CNOT_CIRCULAR) {
-            if (an.ent == GV_ENT_CNOT_CIRCULAR && n > 2) g.push_back({3, n - 1, 0, -1});
-            for (int q = 0; q + 1 < n; ++q) g.push_back({3, q, q + 1, -1});
+        } else if (ent_is_cnot(an.ent)) {
+            for (const auto &ct : cnot_network(n, an.ent, l)) g.push_back({3, ct.first, ct.second, -1});
         }
     }
     return g;
@@ -325,10 +324,67 @@ struct FusedCtx {
     std::vector<LDiagTab> ld0;       // ... and in the load assignment of the same pass
 };
 
-static bool is_cnot(const gv_ansatz &a)
+static bool is_cnot(const gv_ansatz &a) { return ent_is_cnot(a.ent); }
+
+}  // namespace gv
+
+std::vector<std::pair<int, int>> gv::cnot_network(int n, int ent, int layer)
 {
-    return a.ent == GV_ENT_CNOT_LINEAR || a.ent == GV_ENT_CNOT_CIRCULAR;
+    std::vector<std::pair<int, int>> g;
+    switch (ent) {
+    case GV_ENT_CNOT_LINEAR:
+    case GV_ENT_CNOT_CIRCULAR:
+        if (ent == GV_ENT_CNOT_CIRCULAR && n > 2) g.push_back({n - 1, 0});
+        for (int q = 0; q + 1 < n; ++q) g.push_back({q, q + 1});
+        break;
+    case GV_ENT_CNOT_FULL:
+        for (int i = 0; i + 1 < n; ++i)
+            for (int j = i + 1; j < n; ++j) g.push_back({i, j});
+        break;
+    case GV_ENT_CNOT_REVERSE_LINEAR:
+        for (int q = n - 2; q >= 0; --q) g.push_back({q, q + 1});
+        break;
+    case GV_ENT_CNOT_PAIRWISE:
+        for (int start = 0; start < 2; ++start)
+            for (int q = start; q + 1 < n; q += 2) g.push_back({q, q + 1});
+        break;
+    case GV_ENT_CNOT_SCA: {
+        // the circular list, entry 0 = (n-1, 0) and entry e = (e-1, e), rotated
+        // right by the layer index; odd layers exchange control and target
+        std::vector<std::pair<int, int>> ring;
+        if (n > 2) ring.push_back({n - 1, 0});
+        for (int q = 0; q + 1 < n; ++q) ring.push_back({q, q + 1});
+        const int m = (int)ring.size();
+        for (int e = 0; e < m; ++e) {
+            std::pair<int, int> ct = n > 2 ? ring[(size_t)(((e - layer) % m + m) % m)] : ring[(size_t)e];
+            if (layer & 1) std::swap(ct.first, ct.second);
+            g.push_back(ct);
+        }
+        break;
+    }
+    default:
+        break;
+    }
+    return g;
 }
+
+gv::LinMap gv::cnot_linmap(int n, int ent, int layer, bool inverse)
+{
+    LinMap m;
+    memset(&m, 0, sizeof(m));
+    m.n = n;
+    for (int q = 0; q < n; ++q) m.col[q] = 1ull << q;
+    // CNOT(c -> t) sends v to v ^ (bit c of v) << t; the map of the whole
+    // network is the product of the gates (applied to every column), in
+    // order for the network and in reverse order for its inverse
+    std::vector<std::pair<int, int>> g = cnot_network(n, ent, layer);
+    if (inverse) std::reverse(g.begin(), g.end());
+    for (const auto &ct : g)
+        for (int q = 0; q < n; ++q) m.col[q] ^= ((m.col[q] >> ct.first) & 1ull) << ct.second;
+    return m;
+}
+
+namespace gv {
 
 static gv_status fused_setup(gv_state st, const gv_ansatz &an, const double *theta,
                              gv_grad_mode mode, FusedCtx *c)

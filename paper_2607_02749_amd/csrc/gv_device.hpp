@@ -21,6 +21,25 @@ __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b)
     return o;
 }
 
+// State-vector loads and stores of the sweeps: every amplitude is read and
+// written once per pass, so they carry the non-temporal (streaming) hint.
+template <typename R>
+__device__ __forceinline__ cx<R> ld_amp(const cx<R> *p)
+{
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    const v2 v = __builtin_nontemporal_load((const v2 *)p);
+    return cx<R>{v.x, v.y};
+}
+template <typename R>
+__device__ __forceinline__ void st_amp(cx<R> *p, cx<R> a)
+{
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    v2 v;
+    v.x = a.re;
+    v.y = a.im;
+    __builtin_nontemporal_store(v, (v2 *)p);
+}
+
 // k with a zero bit inserted at position q
 __device__ __forceinline__ u64 insert_zero(u64 k, int q)
 {

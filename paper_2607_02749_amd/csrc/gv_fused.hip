@@ -604,7 +604,7 @@ __device__ __forceinline__ void load_tile(cx<R> (&v)[1 << LOGR], const cx<R> *sr
     const cx<R> *sp = src + (base | toff);
     if constexpr (PL) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) v[r] = sp[m.off(r)];
+        for (int r = 0; r < NR; ++r) v[r] = ld_amp(sp + m.off(r));
         return;
     }
     if (mode != IN_LOAD) pd.tile(d, base, t);
@@ -613,7 +613,7 @@ __device__ __forceinline__ void load_tile(cx<R> (&v)[1 << LOGR], const cx<R> *sr
         for (int r = 0; r < NR; ++r) v[r] = pd.at(d, r);
     } else {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) v[r] = sp[m.off(r)];
+        for (int r = 0; r < NR; ++r) v[r] = ld_amp(sp + m.off(r));
         if (mode == IN_LOAD_DIAG) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) v[r] = cmul(v[r], pd.at(d, r));
@@ -661,7 +661,7 @@ __device__ __forceinline__ void fwd_body(cx<R> *psi, const cx<R> *src, const Fus
         if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1, AM>::run(v, lds, t, a, rc);
         cx<R> *pp = psi + fresh(base | toff_st);
 #pragma unroll
-        for (int r = 0; r < T::NR; ++r) pp[mst.off(r)] = v[r];
+        for (int r = 0; r < T::NR; ++r) st_amp(pp + mst.off(r), v[r]);
     }
 }
 
@@ -786,10 +786,10 @@ __device__ __forceinline__ void bwd_body(const cx<R> *phi_in, cx<R> *phi, cx<R> 
             for (int r = 0; r < T::NR; ++r) f[r] = pg.at(a.gt, r);
         } else {
 #pragma unroll
-            for (int r = 0; r < T::NR; ++r) f[r] = (phi_in + (base | toff_ld))[mld.off(r)];
+            for (int r = 0; r < T::NR; ++r) f[r] = ld_amp(phi_in + (base | toff_ld) + mld.off(r));
         }
 #pragma unroll
-        for (int r = 0; r < T::NR; ++r) l[r] = (lam + (base | toff_ld))[mld.off(r)];
+        for (int r = 0; r < T::NR; ++r) l[r] = ld_amp(lam + (base | toff_ld) + mld.off(r));
         if (any_diag) {
             pd.tile(a.dt, base, t);
 #pragma unroll
@@ -816,8 +816,8 @@ __device__ __forceinline__ void bwd_body(const cx<R> *phi_in, cx<R> *phi, cx<R> 
         cx<R> *pf = phi + o, *pl = lam + o;
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
-            if (a.store_phi) pf[mst.off(r)] = f[r];
-            if (a.store_lam) pl[mst.off(r)] = l[r];
+            if (a.store_phi) st_amp(pf + mst.off(r), f[r]);
+            if (a.store_lam) st_amp(pl + mst.off(r), l[r]);
         }
     }
     write_partials<R, K, LOGR, 0, true>(accY, accZr, ztot, sh, a, a.layer, col);
@@ -889,8 +889,8 @@ __device__ __forceinline__ void bwd_gf_body(const cx<R> *phi_in, cx<R> *lam, con
         cx<R> f[T::NR], l[T::NR];
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
-            f[r] = fp[mld.off(r)];
-            l[r] = lp[mld.off(r)];
+            f[r] = ld_amp(fp + mld.off(r));
+            l[r] = ld_amp(lp + mld.off(r));
         }
         if (a.diag_lam) {
             pd.tile(a.dt, base, t);
@@ -913,7 +913,7 @@ __device__ __forceinline__ void bwd_gf_body(const cx<R> *phi_in, cx<R> *lam, con
         if constexpr (T::NA > 1) InvChainRev<R, K, LOGR, T::NA - 2, AM>::run(l, lds, t, a, rc);
         cx<R> *ls = lam + fresh(base | toff_ld);
 #pragma unroll
-        for (int r = 0; r < T::NR; ++r) ls[mld.off(r)] = l[r];
+        for (int r = 0; r < T::NR; ++r) st_amp(ls + mld.off(r), l[r]);
     }
     write_partials<R, K, LOGR, 0, true>(accY, accZr, ztot, sh, a, a.layer, col);
 }
@@ -989,7 +989,7 @@ __device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const Fu
         R et = 0;
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
-            const double d = (a.hdiag + (base | toff_st))[mst.off(r)];
+            const double d = __builtin_nontemporal_load(a.hdiag + (base | toff_st) + mst.off(r));
             const R p = f[r].re * f[r].re + f[r].im * f[r].im;
             et += (R)d * p;
             l[r].re = (R)d * f[r].re;
@@ -1003,7 +1003,7 @@ __device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const Fu
         if constexpr (T::NA > 1) InvChain<R, K, LOGR, 1, AM>::run(l, lds, t, a, rc);
         cx<R> *pl = lam + fresh(base | toff_st);
 #pragma unroll
-        for (int r = 0; r < T::NR; ++r) pl[mst.off(r)] = l[r];
+        for (int r = 0; r < T::NR; ++r) st_amp(pl + mst.off(r), l[r]);
     }
     write_partials<R, K, LOGR, 0, false>(accY, accZr, 0.0, sh, a, a.layer, col);
     const double e = block_sum(eacc, sh);
@@ -1087,7 +1087,7 @@ __device__ __forceinline__ void fwd2_body(cx<R> *psi, const cx<R> *src, const Fu
         if constexpr (T::NA > 1) FwdChainRev<R, K, LOGR, T::NA - 2, AM>::run(v, lds, t, a, rc2);
         cx<R> *pp = psi + fresh(base | toff_ld);
 #pragma unroll
-        for (int r = 0; r < T::NR; ++r) pp[mld.off(r)] = v[r];
+        for (int r = 0; r < T::NR; ++r) st_amp(pp + mld.off(r), v[r]);
     }
 }
 
@@ -1372,7 +1372,7 @@ __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const Off
         const cx<R> *pt = psi + bt;
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
-            v[r] = pt[m.off(r)];
+            v[r] = ld_amp(pt + m.off(r));
             lds[T::pad(T::u_of(t, r, LD))] = v[r];
             acc[r].re = acc[r].im = R(0);
         }
@@ -1413,10 +1413,10 @@ __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const Off
             er += (double)v[r].re * acc[r].re + (double)v[r].im * acc[r].im;
             ei += (double)v[r].re * acc[r].im - (double)v[r].im * acc[r].re;
             if (lt) {
-                cx<R> o = lt[m.off(r)];
+                cx<R> o = ld_amp(lt + m.off(r));
                 o.re += acc[r].re;
                 o.im += acc[r].im;
-                lt[m.off(r)] = o;
+                st_amp(lt + m.off(r), o);
             }
         }
     }
@@ -1570,31 +1570,35 @@ __global__ void k_diag_apply(cx<R> *v0, cx<R> *v1, DiagTab d, u64 dim, int conj)
 }
 
 // CNOT ladder as an index permutation, fused with the layer diagonal.
-// Forward ladder F = f o g with f = prefix XOR of the index bits (CNOT(q ->
-// q+1) for q = 0, 1, ...) and g = CNOT(n-1 -> 0) for the circular form.
-// forward:  dst[j] = D(s) src[s], s = g(f^-1(j))  (the state CNOT D psi~)
-// inverse:  dst[i] = conj(D(i)) src[f(g(i))]       (undoes both)
+// A CNOT network layer as an index gather.  The network sends basis index
+// b to M b (M linear over GF(2), given by its columns), so
+//   forward:  dst[o] = D(s) src[s], s = M^-1 o   (the state CNOT D psi~)
+//   inverse:  dst[i] = conj(D(i)) src[M i]       (undoes both)
+// with `map` holding the columns of M^-1 (forward) or M (inverse).  The
+// map of an index is the XOR of five byte-table entries built in LDS.
 template <typename R>
-__global__ void k_cnot_gather(const cx<R> *src, cx<R> *dst, int n, int circular, int inverse,
-                              DiagTab d, int with_diag)
+__global__ __launch_bounds__(256) void k_linmap_gather(const cx<R> *src, cx<R> *dst, LinMap map,
+                                                       int inverse, DiagTab d, int with_diag)
 {
-    const u64 dim = 1ull << n, mask = dim - 1;
+    __shared__ u64 tab[5][256];
+    for (int e = threadIdx.x; e < 5 * 256; e += blockDim.x) {
+        const int k = e >> 8, v = e & 255;
+        u64 acc = 0;
+        for (int b = 0; b < 8; ++b) {
+            const int q = 8 * k + b;
+            if (((v >> b) & 1) && q < map.n) acc ^= map.col[q];
+        }
+        tab[k][v] = acc;
+    }
+    __syncthreads();
+    const u64 dim = 1ull << map.n;
     for (u64 o = blockIdx.x * (u64)blockDim.x + threadIdx.x; o < dim;
          o += (u64)gridDim.x * blockDim.x) {
-        if (!inverse) {
-            u64 i = o ^ ((o << 1) & mask);
-            if (circular) i ^= (i >> (n - 1)) & 1;
-            cx<R> v = src[i];
-            if (with_diag) v = cmul(v, diag_entry<R>(i, d));
-            dst[o] = v;
-        } else {
-            u64 v = o;
-            if (circular) v ^= (v >> (n - 1)) & 1;
-            for (int sh = 1; sh < 64; sh <<= 1) v ^= v << sh;
-            cx<R> x = src[v & mask];
-            if (with_diag) x = cmul_conj(x, diag_entry<R>(o, d));
-            dst[o] = x;
-        }
+        const u64 s = tab[0][o & 255] ^ tab[1][(o >> 8) & 255] ^ tab[2][(o >> 16) & 255] ^
+                      tab[3][(o >> 24) & 255] ^ tab[4][(o >> 32) & 255];
+        cx<R> v = src[s];
+        if (with_diag) v = inverse ? cmul_conj(v, diag_entry<R>(o, d)) : cmul(v, diag_entry<R>(s, d));
+        dst[o] = v;
     }
 }
 
@@ -2288,20 +2292,19 @@ hipError_t cnot_ladder_gather(int prec, const void *src, void *dst, const gv_ans
                               hipStream_t s)
 {
     const int n = an.n;
-    const int circular = an.ent == GV_ENT_CNOT_CIRCULAR && n > 2;
+    if (n > 40) return hipErrorInvalidValue;
+    const LinMap map = cnot_linmap(n, an.ent, layer, !inverse);
     DiagTab d;
     memset(&d, 0, sizeof(d));
     const int with_diag = t != nullptr;
     if (t) d = layer_tab(an, ch, *t, layer);
     const u64 dim = 1ull << n;
     if (prec == GV_C64)
-        hipLaunchKernelGGL(k_cnot_gather<float>, dim3(elem_grid(dim)), dim3(256), 0, s,
-                           (const cx<float> *)src, (cx<float> *)dst, n, circular, inverse, d,
-                           with_diag);
+        hipLaunchKernelGGL(k_linmap_gather<float>, dim3(elem_grid(dim)), dim3(256), 0, s,
+                           (const cx<float> *)src, (cx<float> *)dst, map, inverse, d, with_diag);
     else
-        hipLaunchKernelGGL(k_cnot_gather<double>, dim3(elem_grid(dim)), dim3(256), 0, s,
-                           (const cx<double> *)src, (cx<double> *)dst, n, circular, inverse, d,
-                           with_diag);
+        hipLaunchKernelGGL(k_linmap_gather<double>, dim3(elem_grid(dim)), dim3(256), 0, s,
+                           (const cx<double> *)src, (cx<double> *)dst, map, inverse, d, with_diag);
     return hipGetLastError();
 }
 

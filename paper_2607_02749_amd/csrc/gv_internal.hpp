@@ -218,6 +218,21 @@ gv_status work_layout(const gv_ansatz &a, gv_precision prec, gv_engine eng, gv_g
 int rot_layers(const gv_ansatz &a);
 int64_t nparams(const gv_ansatz &a);
 
+// CNOT networks: whether the entangler is one, and the (control, target)
+// list of its layer `layer` in application order
+inline bool ent_is_cnot(int ent) { return ent >= GV_ENT_CNOT_LINEAR && ent <= GV_ENT_CNOT_SCA; }
+std::vector<std::pair<int, int>> cnot_network(int n, int ent, int layer);
+
+// A CNOT network as a GF(2)-linear map of the amplitude index: col[q] is
+// the image of the index with only bit q set; index i goes to the XOR of the
+// columns of its set bits.
+struct LinMap {
+    u64 col[40];
+    int n;
+};
+// the map of layer `layer`'s network (inverse = its inverse)
+LinMap cnot_linmap(int n, int ent, int layer, bool inverse);
+
 // ------------------------------------------------------------------ launchers
 // All launchers enqueue on `s` and return the launch status.
 

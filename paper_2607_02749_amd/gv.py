@@ -22,6 +22,7 @@ C64, C128 = 0, 1
 ENGINE_FUSED, ENGINE_PLAIN = 0, 1
 GRAD_UNCOMPUTE, GRAD_CHECKPOINT, GRAD_RECOMPUTE, GRAD_STORE = 0, 1, 2, 3
 ENT_NONE, ENT_CZ_LINEAR, ENT_CZ_CIRCULAR, ENT_CNOT_LINEAR, ENT_CNOT_CIRCULAR = 0, 1, 2, 3, 4
+ENT_CNOT_FULL, ENT_CNOT_REVERSE_LINEAR, ENT_CNOT_PAIRWISE, ENT_CNOT_SCA = 5, 6, 7, 8
 
 _PREC = {"c64": C64, "complex64": C64, C64: C64, "c128": C128, "complex128": C128, C128: C128}
 _ENGINE = {"fused": ENGINE_FUSED, "plain": ENGINE_PLAIN, ENGINE_FUSED: ENGINE_FUSED,

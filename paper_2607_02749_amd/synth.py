@@ -121,6 +121,9 @@ def _diag_terms(rng, n, adj, m, w_max):
     seen = set()
     out = []
     w_hi = min(w_max, n)
+    from math import comb
+    if m > sum(comb(n, w) for w in range(1, w_hi + 1)):
+        raise ValueError(f"{m} distinct Z-strings of weight 1..{w_hi} do not exist on {n} qubits")
     while len(out) < m:
         w = int(rng.integers(1, w_hi + 1))
         sup = _grow_support(rng, n, adj, w)

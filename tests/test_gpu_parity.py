@@ -62,9 +62,13 @@ def test_small_workload(engine, precision):
     check(e, g, *oracle_eg(inst), precision, f"n=10 {engine}")
 
 
+ALL_ENTS = [synth.ENT_CZ_LINEAR, synth.ENT_CZ_CIRCULAR, synth.ENT_CNOT_LINEAR,
+            synth.ENT_CNOT_CIRCULAR, synth.ENT_NONE, synth.ENT_CNOT_FULL,
+            synth.ENT_CNOT_REVERSE_LINEAR, synth.ENT_CNOT_PAIRWISE, synth.ENT_CNOT_SCA]
+
+
 @pytest.mark.parametrize("n", [8, 9, 11, 12, 13, 15, 17])
-@pytest.mark.parametrize("ent", [synth.ENT_CZ_LINEAR, synth.ENT_CZ_CIRCULAR, synth.ENT_CNOT_LINEAR,
-                                 synth.ENT_CNOT_CIRCULAR, synth.ENT_NONE])
+@pytest.mark.parametrize("ent", ALL_ENTS)
 def test_sizes_and_entanglers_c128(n, ent):
     inst = synth.make_instance(n, 2, 12 * n, 4, 3, seed=n * 10 + ent, m_off=2 * n,
                                off_types=("XX", "YY", "XZ", "ZY"), ent=ent,
@@ -266,8 +270,7 @@ def test_tiny_registers(n, precision, engine):
     # below the fused engine's smallest tile the request runs the plain
     # kernels; every entangler and arbitrary Pauli strings (Y phases, wide flips)
     rng = np.random.default_rng(300 + n)
-    for ent in (synth.ENT_CZ_LINEAR, synth.ENT_CZ_CIRCULAR, synth.ENT_CNOT_LINEAR,
-                synth.ENT_CNOT_CIRCULAR, synth.ENT_NONE):
+    for ent in ALL_ENTS:
         m = 3 * n + 2
         x = rng.integers(0, 1 << n, size=m, dtype=np.uint64)
         x[: m // 3] = 0
@@ -284,7 +287,7 @@ def test_tiny_registers(n, precision, engine):
 @pytest.mark.parametrize("n", [5, 10, 14])
 def test_rotation_layer_only(n, precision):
     # layers = 0 with the final rotation layer: one RY, RZ layer and no entangler
-    inst = synth.make_instance(n, 0, 10 * n, 4, 2, seed=40 + n, m_off=n,
+    inst = synth.make_instance(n, 0, 5 * n, 4, 2, seed=40 + n, m_off=n,
                                off_types=("XX", "YY", "XZ"), final_rotation=1)
     e, g, _, _ = run_gpu(inst, precision)
     assert g.shape == (2 * n,)
@@ -321,3 +324,16 @@ def test_duplicate_zero_and_identity_terms(n, precision):
         e, g, _, _ = run_gpu(inst, precision, engine)
         check(e, g, *oracle_eg(inst), precision, f"dup/zero/identity n={n} {engine}",
               e_scale=np.abs(c).sum())
+
+
+@pytest.mark.parametrize("ent", [synth.ENT_CNOT_FULL, synth.ENT_CNOT_REVERSE_LINEAR,
+                                 synth.ENT_CNOT_PAIRWISE, synth.ENT_CNOT_SCA])
+@pytest.mark.parametrize("mode", ["uncompute", "checkpoint", "store"])
+def test_cnot_networks_c64(ent, mode):
+    # the CNOT networks are index gathers between the fused tile passes;
+    # SCA changes its network every layer
+    inst = synth.make_instance(16, 4, 160, 4, 3, seed=600 + ent, m_off=16,
+                               off_types=("XX", "YY", "XZ"), ent=ent, final_rotation=1)
+    e_ref, g_ref = oracle_eg(inst)
+    e, g, _, _ = run_gpu(inst, "c64", mode=mode)
+    check(e, g, e_ref, g_ref, "c64", f"ent={ent} {mode}")

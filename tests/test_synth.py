@@ -2,6 +2,7 @@
 workload recipe promises (distinct terms, weights, community coefficients,
 qubit-wise-commuting group bound)."""
 import numpy as np
+import pytest
 
 from paper_2607_02749_amd import synth
 
@@ -72,3 +73,10 @@ def test_batch_workload():
         assert inst.num_terms == 55 * inst.n
         assert inst.cluster_mask != 0
         assert 2 <= len(inst.communities) <= 4
+
+
+def test_impossible_term_counts_raise():
+    # 5 qubits hold only 30 distinct Z-strings of weight 1..4
+    with pytest.raises(ValueError):
+        synth.make_instance(5, 1, 31, 4, 2, seed=0)
+    synth.make_instance(5, 1, 30, 4, 2, seed=0)
