@@ -347,6 +347,27 @@ gv_status gv_stream_probe(int32_t kind, int32_t width, int32_t unroll, int32_t n
                           int32_t grid, int32_t tile_shift, void *dst, const void *src0,
                           const void *src1, size_t bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: energy and
+ * gradient like gv_energy_grad in GV_GRAD_UNCOMPUTE mode, without a state or
+ * a caller workspace.  The state vector, the adjoint vector and every table
+ * and partial sum live in one library-owned static device array of
+ * gv_noalloc_scratch_bytes() (64 MiB) per GPU, held from the library's load
+ * until the process ends: n <= 21 in GV_C64, n <= 20 in GV_C128 (larger
+ * requests return GV_ESIZE before any work).  The call allocates nothing
+ * (no hipMalloc, no allocating library routine); it enqueues on `stream` and
+ * returns.  Arguments as gv_energy_grad; h must be prepared for `prec` on the
+ * fused engine (gv_pauli_sum_prepare_for).  Every call on one GPU shares the
+ * array: calls that overlap on one GPU (other streams, other threads) race.
+ * Nothing has to be cleared between calls (every scratch entry a call reads
+ * it has written first). */
+gv_status gv_energy_grad_noalloc(int32_t n, gv_precision prec, gv_pauli_sum h,
+                                 const double *params_dev, const gv_ansatz *ansatz,
+                                 const uint8_t *grad_mask_dev, double *energy_dev,
+                                 double *grad_dev, void *stream);
+size_t gv_noalloc_scratch_bytes(void);
+
 #ifdef __cplusplus
 }
 #endif
