@@ -66,6 +66,10 @@ def _load():
     L.gvo_energy_grad.restype = i32
     L.gvo_adjoint_gates.argtypes = [i32, i32, i32, i32, p, i64, i64, p, p, p]
     L.gvo_adjoint_gates.restype = i64
+    L.gvo_max_threads.argtypes = []
+    L.gvo_max_threads.restype = i32
+    L.gvo_set_threads.argtypes = [i32]
+    L.gvo_set_threads.restype = None
     _lib = L
     return L
 
@@ -81,6 +85,16 @@ def _terms(x, z, c):
     if not (x.shape == z.shape == c.shape):
         raise ValueError("x, z, c must have the same length")
     return x, z, c
+
+
+def max_threads() -> int:
+    """Host threads the oracle's parallel loops use."""
+    return int(_load().gvo_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads for the oracle's parallel loops from now on."""
+    _load().gvo_set_threads(int(n))
 
 
 def num_params(n: int, layers: int, final_rotation: int = 0) -> int:

@@ -49,6 +49,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
 
@@ -444,4 +447,24 @@ int64_t gvo_adjoint_gates(int n, int layers, int ent, int final_rotation,
     }
     free(g);
     return count;
+}
+
+/* Threads the OpenMP loops use (1 without OpenMP), and a way to change it
+ * (for timing the oracle on a given number of host cores). */
+int gvo_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void gvo_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
