@@ -25,7 +25,10 @@ import numpy as np
 
 
 def born_sample(psi: np.ndarray, u: np.ndarray) -> np.ndarray:
-    p = np.abs(np.asarray(psi)) ** 2
+    """Probabilities and their running sum in FP64, whatever the amplitudes'
+    precision."""
+    v = np.asarray(psi).astype(np.complex128)
+    p = v.real * v.real + v.imag * v.imag
     cdf = np.cumsum(p)
     target = np.asarray(u, dtype=np.float64) * cdf[-1]
     idx = np.searchsorted(cdf, target, side="right")
@@ -33,7 +36,8 @@ def born_sample(psi: np.ndarray, u: np.ndarray) -> np.ndarray:
 
 
 def argmax(psi: np.ndarray) -> int:
-    return int(np.argmax(np.abs(np.asarray(psi)) ** 2))
+    v = np.asarray(psi).astype(np.complex128)
+    return int(np.argmax(v.real * v.real + v.imag * v.imag))
 
 
 def merge_terms(x, z, c):
@@ -83,9 +87,28 @@ def qwc_groups(x, z, c) -> List[Tuple[int, int, int, List[Tuple[int, int, float]
     return out
 
 
-def basis_rotate(psi: np.ndarray, n: int, xmask: int, ymask: int) -> np.ndarray:
+def basis_rotate(psi: np.ndarray, n: int, xmask: int, ymask: int,
+                 single: bool = False) -> np.ndarray:
     """H on the X qubits, H S^dagger on the Y qubits, as 2x2 matrices on the
-    qubit's axis of the state tensor (qubit q = bit q of the index)."""
+    qubit's axis of the state tensor (qubit q = bit q of the index).
+
+    single: the complex64 arithmetic of a complex64 state, qubit by qubit in
+    ascending order: b <- -i b (Y only), then (h (a + b), h (a - b)) with
+    h = 1/sqrt(2) rounded to float32 -- the precision in which a complex64
+    engine decides which basis states the draws land on."""
+    if single:
+        h32 = np.float32(1.0 / np.sqrt(2.0))
+        t = np.asarray(psi).astype(np.complex64).reshape([2] * n)
+        for q in range(n):
+            if not ((xmask | ymask) >> q) & 1:
+                continue
+            ax = n - 1 - q
+            a = np.take(t, 0, axis=ax)
+            b = np.take(t, 1, axis=ax)
+            if (ymask >> q) & 1:
+                b = (b.imag - 1j * b.real).astype(np.complex64)
+            t = np.stack([h32 * (a + b), h32 * (a - b)], axis=ax).astype(np.complex64)
+        return t.reshape(-1)
     h = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2.0)
     sdg = np.array([[1, 0], [0, -1j]], dtype=np.complex128)
     t = np.asarray(psi, dtype=np.complex128).reshape([2] * n)   # axis 0 = qubit n-1
@@ -101,9 +124,11 @@ def basis_rotate(psi: np.ndarray, n: int, xmask: int, ymask: int) -> np.ndarray:
     return t.reshape(-1)
 
 
-def energy_shots(n: int, psi: np.ndarray, x, z, c, u: np.ndarray, shots: int) -> float:
+def energy_shots(n: int, psi: np.ndarray, x, z, c, u: np.ndarray, shots: int,
+                 single: bool = False) -> float:
     """The finite-shot estimate; u holds (1 + groups) * shots uniforms: the
-    first block for the Z-only part, then one block per group in order."""
+    first block for the Z-only part, then one block per group in order
+    (single: the basis changes in complex64 arithmetic)."""
     terms = merge_terms(x, z, c)
     idx = np.arange(1 << n, dtype=np.uint64)
     d = np.zeros(1 << n)
@@ -114,7 +139,7 @@ def energy_shots(n: int, psi: np.ndarray, x, z, c, u: np.ndarray, shots: int) ->
     b = born_sample(psi, u[:shots])
     est = float(np.mean(d[b.astype(np.int64)]))
     for g, (xm, ym, _, gterms) in enumerate(qwc_groups(x, z, c)):
-        rot = basis_rotate(psi, n, xm, ym)
+        rot = basis_rotate(psi, n, xm, ym, single)
         b = born_sample(rot, u[(g + 1) * shots:(g + 2) * shots])
         for xk, zk, ck in gterms:
             sup = np.uint64(xk | zk)
