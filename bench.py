@@ -46,6 +46,7 @@ KERNELS = {
     "backward_gf": "k_bwd_gf_pass<float,12,4>", "backward_gf_ld": "k_bwd_gf_ld_pass<float,12,4>",
     "turnaround": "k_turn_load_pass<float,12,4>", "first_layer": "k_layer0_grad<float,12,4>",
     "energy": "k_energy_diag<float>", "offdiag": "k_offdiag_pass<float,12,4>",
+    "backward2": "k_bwd2_pass<float,12,4>",
 }
 
 
@@ -54,7 +55,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="n28", choices=["n28", "n32", "batch"])
+    ap.add_argument("--workload", default="n28", choices=["n28", "n32", "batch", "pshift"])
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -94,10 +95,20 @@ def measure(inst, mode, steps, warmup, h=None):
     st = gv.State(inst.n, "c64", "fused", an, mode)
     diag_ms = None
     if h is None:
-        t0 = time.perf_counter()
-        h = gv.PauliSum(inst.n, inst.x, inst.z, inst.c).prepare(st)
+        # host: merge, split and group the terms; device: the FWHT diagonal
+        # and the term tables (prepare waits for its stream)
         torch.cuda.synchronize()
-        diag_ms = (time.perf_counter() - t0) * 1e3
+        t0 = time.perf_counter()
+        h = gv.PauliSum(inst.n, inst.x, inst.z, inst.c)
+        t1 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        h.prepare(st)
+        e1.record()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        diag_ms = {"host_ingest_ms": (t1 - t0) * 1e3, "prepare_wall_ms": (t2 - t1) * 1e3,
+                   "prepare_stream_ms": e0.elapsed_time(e1)}
     theta = torch.tensor(inst.theta, dtype=torch.float64, device=st.device, requires_grad=True)
     last = {}
 
@@ -147,18 +158,31 @@ def roofline(prof, steps):
     return roof, breakdown
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(inst):
     """The oracle on host cores, on a bounded sample of one evaluation: one
     whole layer of the n=28 circuit forward (every RY, RZ and CZ gate), the
     reverse-sweep steps of the same layer, and the lambda = D psi product,
-    each timed once; one evaluation runs L such layers each way (the
-    theta-independent diagonal excluded, as on the GPU)."""
+    each timed once with every host thread; one evaluation runs L such layers
+    each way (the theta-independent diagonal excluded, as on the GPU).  Then
+    the first 4 gates forward and back on one thread, scaled by the gate
+    count of an evaluation."""
     import oracle
     n, L, ent = inst.n, inst.layers, inst.ent
     ng = oracle.num_gates(n, L, ent)
     per_layer = ng // L
     assert ng == L * per_layer
     dim = 1 << n
+    threads = oracle.max_threads()
     phi = np.zeros(dim, np.complex128)
     phi[0] = 1.0
     grad = np.zeros(inst.num_params)
@@ -174,13 +198,30 @@ def cpu_baseline(inst):
     oracle.adjoint_gates(n, L, ent, inst.theta, phi, lam, grad, 0, per_layer)
     t_b = time.perf_counter() - t0
     est = L * (t_f + t_b) + t_h
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # one thread: 4 gates forward and their 4 reverse steps
+    k = 4
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.apply_gates(n, L, ent, inst.theta, phi, 0, k)
+        t_f1 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.adjoint_gates(n, L, ent, inst.theta, phi, lam, grad, 0, k)
+        t_b1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    est1 = ng * (t_f1 + t_b1) / k
     return {
         "value": 1.0 / est, "unit": "evals/s", "cores": threads, "kind": "oracle",
-        "sample": (f"complex128 oracle at n={n}: one full layer forward ({per_layer} gates, "
-                   f"{t_f:.1f} s), its {per_layer} reverse-sweep steps ({t_b:.1f} s) and one "
-                   f"lambda=D*psi product ({t_h:.1f} s), scaled to the {L} layers of one "
-                   f"evaluation: est. {est:.1f} s/eval; diagonal build excluded"),
+        "cpu_model": cpu_model(),
+        "sample": (f"complex128 oracle at n={n}, {threads} threads: one full layer forward "
+                   f"({per_layer} gates, {t_f:.1f} s), its {per_layer} reverse-sweep steps "
+                   f"({t_b:.1f} s) and one lambda=D*psi product ({t_h:.1f} s), scaled to the {L} "
+                   f"layers of one evaluation: est. {est:.1f} s/eval; diagonal build excluded"),
+        "one_thread": {"value": 1.0 / est1, "unit": "evals/s", "cores": 1,
+                       "sample": (f"the first {k} gates forward ({t_f1:.1f} s) and back "
+                                  f"({t_b1:.1f} s) on one thread, scaled to the {ng} gates "
+                                  f"of an evaluation: est. {est1:.0f} s/eval")},
     }
 
 
@@ -432,6 +473,51 @@ def bench_batch(args, torch, gv, synth):
     }
 
 
+def bench_pshift(args, torch, gv, synth):
+    """The paper's own gradient (Eq. 13): 2P shifted energy-only evaluations
+    of one instance in one batched graph launch, beside the adjoint gradient
+    (one reverse sweep) on the same instance; n = 16, L = 4 (P = 128),
+    800 Z-strings + 80 XX/YY terms on a 3-community graph, complex64."""
+    inst = synth.make_instance(16, 4, 800, 4, 3, seed=0, m_off=80, off_types=("XX", "YY"))
+    an = gv.Ansatz(inst.n, inst.layers, inst.ent)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    th = torch.tensor(inst.theta, dtype=torch.float64, device=dev)
+    ps = gv.ParamShift(an, gv.PauliSum(inst.n, inst.x, inst.z, inst.c), precision="c64")
+    for _ in range(args.warmup):
+        ps(th)
+    wall_ps, ev_ps = time_steps(lambda: ps(th), args.steps, torch)
+    g_ps, _ = ps(th)
+    st = gv.State(inst.n, "c64", "fused", an, "store")
+    h = gv.PauliSum(inst.n, inst.x, inst.z, inst.c).prepare(st)
+    out = {}
+
+    def adj():
+        out["e"], out["g"] = gv.energy_grad(st, h, th, an, None, "store")
+
+    for _ in range(args.warmup):
+        adj()
+    wall_a, ev_a = time_steps(adj, args.steps, torch)
+    g_ps = g_ps.cpu().numpy()
+    g_a = out["g"].cpu().numpy()
+    P = an.num_params
+    return {
+        "metric": "gradient evals/s: batched parameter shift (Eq. 13, 2P shifted circuits) vs adjoint",
+        "value": args.steps / wall_ps, "unit": "gradients/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall_ps / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "pshift_n16_L4_800z_80offdiag", "n": inst.n, "layers": inst.layers,
+                   "params": P, "shifted_circuits": 2 * P},
+        "parameter_shift": {"gradients_per_s": args.steps / wall_ps,
+                            "shifted_evals_per_s": 2 * P * args.steps / wall_ps,
+                            "ms_per_gradient": ev_ps / args.steps * 1e3},
+        "adjoint": {"gradients_per_s": args.steps / wall_a,
+                    "ms_per_gradient": ev_a / args.steps * 1e3},
+        "grad_rel_l2_shift_vs_adjoint": float(np.linalg.norm(g_ps - g_a) / np.linalg.norm(g_a)),
+        "cpu_baseline": None,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -440,7 +526,8 @@ def main():
         sys.exit(2)
     import torch
     from paper_2607_02749_amd import gv, synth
-    run = {"n28": bench_n28, "n32": bench_n32, "batch": bench_batch}[args.workload]
+    run = {"n28": bench_n28, "n32": bench_n32, "batch": bench_batch,
+           "pshift": bench_pshift}[args.workload]
     out = run(args, torch, gv, synth)
     print(json.dumps(out))
 

@@ -307,7 +307,8 @@ typedef enum {
     GV_PROF_BACKWARD_GF = 10,   /* reverse pass rotating lambda alone (phi not kept) */
     GV_PROF_BACKWARD_GF_LD = 11,/* the same, undoing a layer diagonal on load */
     GV_PROF_TURNAROUND = 12,    /* last forward pass + energy + first reverse pass */
-    GV_PROF_KINDS = 13
+    GV_PROF_BACKWARD2 = 13,     /* reverse of a two-layer pass in one sweep (STORE mode) */
+    GV_PROF_KINDS = 14
 } gv_prof_kind;
 
 gv_status gv_profile_enable(gv_state st, int32_t enable);
@@ -316,6 +317,43 @@ gv_status gv_profile_reset(gv_state st);
  * the last reset.  Any output pointer may be NULL. */
 gv_status gv_profile_read(gv_state st, int32_t kind, int64_t *launches, double *ms,
                           double *bytes);
+
+/* ------------------------------------------------------------------------
+ * Measurement (Sec. IV-F, Sec. V-A).  The paper estimates energies from 8192
+ * shots and decodes the most probable bitstring; these calls do both on a
+ * state vector in device memory (amps_dev: 2^n amplitudes of `prec`, e.g. a
+ * state's buffer after gv_apply_ansatz), enqueued on `stream`.  Random
+ * numbers are the caller's: u_dev holds uniform draws in [0, 1).
+ *
+ * gv_sample: shots indices drawn from the Born distribution |psi_i|^2 by
+ *   inverse-CDF sampling (out_dev[j] = the i with cdf(i-1) <= u_j * total <
+ *   cdf(i), cumulative sums in FP64).  work_dev: gv_sample_work_bytes(n).
+ * gv_argmax: the index of the largest |psi_i|^2 (ties: the smallest index)
+ *   and that probability (prob_dev may be NULL).  Same work size.
+ * gv_energy_shots: the finite-shot estimate of <psi|H|psi> for a prepared
+ *   Hamiltonian: the Z-only part as the mean of the FP64 diagonal D(b) over
+ *   `shots` samples of psi (draws u_dev[0 .. shots)), each qubit-wise-
+ *   commuting group g (gv_pauli_sum_group order) from `shots` samples of psi
+ *   in the group's eigenbasis (H on X qubits, H S^dagger on Y qubits; draws
+ *   u_dev[(g+1) shots ..)), term k contributing c_k times the mean of
+ *   (-1)^{popcount(b & support_k)}.  u_dev: (1 + groups) * shots doubles;
+ *   energy_dev: 2 doubles (estimate, 0); work_dev:
+ *   gv_energy_shots_work_bytes(h, prec, shots). */
+size_t gv_sample_work_bytes(int32_t n);
+gv_status gv_sample(int32_t n, gv_precision prec, const void *amps_dev, const double *u_dev,
+                    int64_t shots, void *work_dev, size_t work_bytes, uint64_t *out_dev,
+                    void *stream);
+gv_status gv_argmax(int32_t n, gv_precision prec, const void *amps_dev, void *work_dev,
+                    size_t work_bytes, uint64_t *index_dev, double *prob_dev, void *stream);
+/* Group g of the Hamiltonian's qubit-wise-commuting grouping of its
+ * off-diagonal terms (greedy first fit over the merged terms in (x, z)
+ * order): the qubits carrying X, Y and Z in the group, and its term count. */
+gv_status gv_pauli_sum_group(gv_pauli_sum h, int64_t g, uint64_t *xmask, uint64_t *ymask,
+                             uint64_t *zmask, int64_t *nterms);
+size_t gv_energy_shots_work_bytes(gv_pauli_sum h, gv_precision prec, int64_t shots);
+gv_status gv_energy_shots(gv_pauli_sum h, int32_t n, gv_precision prec, const void *amps_dev,
+                          const double *u_dev, int64_t shots, void *work_dev, size_t work_bytes,
+                          double *energy_dev, void *stream);
 
 /* ------------------------------------------------------------------------
  * Streaming-bandwidth probe (measurement only; no part of the method).

@@ -772,7 +772,8 @@ gv_status gv_pauli_sum_info(gv_pauli_sum h, int64_t *n_diag, int64_t *n_offdiag,
 }
 
 static void pauli_layout(const gv_pauli_s *h, size_t *diag, size_t *cls, size_t *terms,
-                         size_t *sz, size_t *sc, size_t *total)
+                         size_t *sz, size_t *sc, size_t *total, size_t *gmask = nullptr,
+                         size_t *gcoef = nullptr)
 {
     size_t off = 0;
     *diag = off;
@@ -785,6 +786,10 @@ static void pauli_layout(const gv_pauli_s *h, size_t *diag, size_t *cls, size_t 
     off += align_up(h->dz.size() * 8 + 8);
     *sc = off;
     off += align_up(h->dc.size() * 8 + 8);
+    if (gmask) *gmask = off;
+    off += align_up(h->ox.size() * 8 + 8);
+    if (gcoef) *gcoef = off;
+    off += align_up(h->ox.size() * 8 + 8);
     *total = off;
 }
 
@@ -995,10 +1000,12 @@ static gv_status prepare_impl(gv_pauli_sum h, gv_precision prec, gv_engine engin
     if (prec != GV_C64 && prec != GV_C128) return set_error(GV_EINVAL, "precision %d", prec);
     if (engine != GV_ENGINE_FUSED && engine != GV_ENGINE_PLAIN) return set_error(GV_EINVAL, "engine");
     if (!aligned(dev)) return set_error(GV_EINVAL, "buffer must be %zu-byte aligned", kAlign);
-    size_t odiag, ocls, oterms, osz, osc, total;
-    pauli_layout(h, &odiag, &ocls, &oterms, &osz, &osc, &total);
+    size_t odiag, ocls, oterms, osz, osc, total, ogm, ogc;
+    pauli_layout(h, &odiag, &ocls, &oterms, &osz, &osc, &total, &ogm, &ogc);
     if (bytes < total) return set_error(GV_ESIZE, "buffer %zu bytes < %zu", bytes, total);
     char *base = (char *)dev;
+    h->dev_gmask = (uint64_t *)(base + ogm);
+    h->dev_gcoef = (double *)(base + ogc);
     h->prep_gen++;
     h->dev = dev;
     h->dev_bytes = bytes;
@@ -1025,6 +1032,22 @@ static gv_status prepare_impl(gv_pauli_sum h, gv_precision prec, gv_engine engin
             return r;
         if (gv_status r = check_hip(hipMemcpyAsync(h->dev_terms, h->class_terms.data(),
                                                    h->class_terms.size() * sizeof(OffTerm),
+                                                   hipMemcpyHostToDevice, s), "copy"))
+            return r;
+    }
+    // off-diagonal terms in group order: support masks and coefficients
+    std::vector<uint64_t> gm;
+    std::vector<double> gc;
+    for (const QwcGroup &g : h->groups)
+        for (int64_t k : g.terms) {
+            gm.push_back(h->ox[(size_t)k] | h->oz[(size_t)k]);
+            gc.push_back(h->oc[(size_t)k]);
+        }
+    if (!gm.empty()) {
+        if (gv_status r = check_hip(hipMemcpyAsync(h->dev_gmask, gm.data(), gm.size() * 8,
+                                                   hipMemcpyHostToDevice, s), "copy"))
+            return r;
+        if (gv_status r = check_hip(hipMemcpyAsync(h->dev_gcoef, gc.data(), gc.size() * 8,
                                                    hipMemcpyHostToDevice, s), "copy"))
             return r;
     }
@@ -1214,8 +1237,20 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
             fl.store_phi = k >= 1 && !prev_fresh;
             fl.store_lam = 1;
             fl.grad_first = !fl.store_phi && !fl.diag_phi;
-            // a two-layer pass is undone by two reverse passes: layer lb's RY
-            // gates, then layer la's diagonal (on load) and RY gates
+            // STORE keeps the two-layer pass's input: one sweep from there
+            // undoes both layers (3 A s instead of 7)
+            if (op.lb >= 0 && store && k >= 1 && !fl.diag_lam) {
+                ProfScope ps(st, GV_PROF_BACKWARD2, 3.0 * vb);
+                if (gv_status r = check_hip(
+                        fused_backward2_pass(st->prec, store_out(c, k - 1, psi, ck, vb), lam, *a,
+                                             c.plan, op.g, op.la, op.in_mode, c.ch, c.ld[op.la],
+                                             c.ld0[op.la], c.tabs, part, c.w.grid, s),
+                        "two-layer backward pass"))
+                    return r;
+                continue;
+            }
+            // otherwise a two-layer pass is undone by two reverse passes: layer
+            // lb's RY gates, then layer la's diagonal (on load) and RY gates
             if (op.lb >= 0) {
                 BwdFlags fa = fl;
                 fa.store_phi = 1;
@@ -1375,6 +1410,110 @@ gv_status gv_profile_read(gv_state st, int32_t kind, int64_t *launches, double *
     if (ms) *ms = tot;
     if (bytes) *bytes = b;
     return GV_OK;
+}
+
+size_t gv_sample_work_bytes(int32_t n)
+{
+    if (n < 1 || n > kMaxQubits) return 0;
+    return sample_work_bytes(n);
+}
+
+static gv_status check_amps(int32_t n, gv_precision prec, const void *amps, void *work,
+                            size_t work_bytes, size_t need)
+{
+    if (n < 1 || n > kMaxQubits) return set_error(GV_EINVAL, "n=%d outside 1..%d", n, kMaxQubits);
+    if (prec != GV_C64 && prec != GV_C128) return set_error(GV_EINVAL, "precision %d", prec);
+    if (!amps || !work) return set_error(GV_EINVAL, "NULL buffer");
+    if (!aligned(amps) || !aligned(work))
+        return set_error(GV_EINVAL, "buffers must be %zu-byte aligned", kAlign);
+    if (work_bytes < need) return set_error(GV_ESIZE, "work buffer %zu bytes < %zu", work_bytes, need);
+    return GV_OK;
+}
+
+gv_status gv_sample(int32_t n, gv_precision prec, const void *amps, const double *u,
+                    int64_t shots, void *work, size_t work_bytes, uint64_t *out, void *stream)
+{
+    if (gv_status r = check_amps(n, prec, amps, work, work_bytes, sample_work_bytes(n))) return r;
+    if (shots < 0) return set_error(GV_EINVAL, "shots < 0");
+    if (shots > 0 && (!u || !out)) return set_error(GV_EINVAL, "NULL draws or output");
+    return check_hip(sample_born(prec, amps, n, u, shots, work, out, (hipStream_t)stream),
+                     "sample");
+}
+
+gv_status gv_argmax(int32_t n, gv_precision prec, const void *amps, void *work, size_t work_bytes,
+                    uint64_t *index, double *prob, void *stream)
+{
+    if (gv_status r = check_amps(n, prec, amps, work, work_bytes, sample_work_bytes(n))) return r;
+    if (!index) return set_error(GV_EINVAL, "index is NULL");
+    return check_hip(argmax_prob(prec, amps, n, work, index, prob, (hipStream_t)stream), "argmax");
+}
+
+static size_t shots_work_bytes(const gv_pauli_s *h, gv_precision prec, int64_t shots)
+{
+    const size_t A = (size_t)1 << h->n;
+    return sample_work_bytes(h->n) + align_up(A * amp_bytes(prec)) +
+           align_up((size_t)shots * 8 + 8) + align_up((h->ox.size() + 1) * 8);
+}
+
+size_t gv_energy_shots_work_bytes(gv_pauli_sum h, gv_precision prec, int64_t shots)
+{
+    if (!h || shots < 0 || (prec != GV_C64 && prec != GV_C128)) return 0;
+    return shots_work_bytes(h, prec, shots);
+}
+
+gv_status gv_pauli_sum_group(gv_pauli_sum h, int64_t g, uint64_t *xmask, uint64_t *ymask,
+                             uint64_t *zmask, int64_t *nterms)
+{
+    if (!h) return set_error(GV_EINVAL, "pauli sum is NULL");
+    if (g < 0 || g >= (int64_t)h->groups.size()) return set_error(GV_EINVAL, "group %lld", (long long)g);
+    const QwcGroup &q = h->groups[(size_t)g];
+    if (xmask) *xmask = q.xmask;
+    if (ymask) *ymask = q.ymask;
+    if (zmask) *zmask = q.zmask;
+    if (nterms) *nterms = (int64_t)q.terms.size();
+    return GV_OK;
+}
+
+gv_status gv_energy_shots(gv_pauli_sum h, int32_t n, gv_precision prec, const void *amps,
+                          const double *u, int64_t shots, void *work, size_t work_bytes,
+                          double *energy, void *stream)
+{
+    if (!h || !energy) return set_error(GV_EINVAL, "NULL argument");
+    if (!h->prepared) return set_error(GV_ESTATE, "pauli sum not prepared");
+    if (h->n != n) return set_error(GV_ESTATE, "pauli sum n=%d but n=%d", h->n, n);
+    if (shots < 1 || !u) return set_error(GV_EINVAL, "need shots >= 1 and the draws");
+    if (gv_status r = check_amps(n, prec, amps, work, work_bytes, shots_work_bytes(h, prec, shots)))
+        return r;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t A = (size_t)1 << n;
+    char *w = (char *)work;
+    void *swork = w;
+    void *rot = w + sample_work_bytes(n);
+    uint64_t *idx = (uint64_t *)((char *)rot + align_up(A * amp_bytes(prec)));
+    double *vals = (double *)((char *)idx + align_up((size_t)shots * 8 + 8));
+    double *dpart = vals + h->ox.size();
+    // the Z-only terms (and the identity) from shots of psi: mean of D(b)
+    if (gv_status r = check_hip(sample_born(prec, amps, n, u, shots, swork, idx, s), "sample"))
+        return r;
+    if (gv_status r = check_hip(diag_mean(idx, shots, h->diag, dpart, s), "diagonal mean")) return r;
+    // every qubit-wise-commuting group from shots of psi in its eigenbasis
+    int64_t t0 = 0;
+    for (size_t g = 0; g < h->groups.size(); ++g) {
+        const QwcGroup &q = h->groups[g];
+        const int64_t m = (int64_t)q.terms.size();
+        if (gv_status r = check_hip(basis_rotate(prec, amps, rot, n, q.xmask, q.ymask, s), "basis"))
+            return r;
+        if (gv_status r = check_hip(sample_born(prec, rot, n, u + (size_t)(g + 1) * shots, shots,
+                                                swork, idx, s),
+                                    "sample"))
+            return r;
+        if (gv_status r = check_hip(parity_means(idx, shots, h->dev_gmask + t0, h->dev_gcoef + t0,
+                                                 m, vals + t0, s),
+                                    "parity means"))
+            return r;
+        t0 += m;
+    }
+    return check_hip(sum_terms(vals, (int64_t)h->ox.size(), dpart, energy, s), "sum");
 }
 
 gv_status gv_stream_probe(int32_t kind, int32_t width, int32_t unroll, int32_t nontemporal,

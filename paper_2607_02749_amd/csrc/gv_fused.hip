@@ -74,6 +74,7 @@ struct FusedArgs {
     u64 qmask;               // qubits whose gradient rows are written (others get 0)
     int layer2;              // two-layer passes: the second rotation layer
     LDiagTab ld;             // two-layer passes: diagonal of `layer` in the last assignment
+    LDiagTab ld2;            // fused two-layer reverse: the same diagonal in the load assignment
 };
 
 template <int K, int LOGR>
@@ -950,6 +951,102 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_gf_ld_pass(const void *
                                                  a, b, g, b, lds, sh);
 }
 
+// Reverse of a two-layer pass (rotation layers la = a.layer and lb =
+// a.layer2 on the same tile qubits) in one sweep, from the state the pass
+// started from (phi_in, kept by the STORE mode): per tile, phi_in is carried
+// forward in registers to phi_a = RY_la phi_in (kept in a second LDS buffer)
+// and phi_out = RY_lb D_la phi_a; the partials of lb's RZ and RY gates come
+// from (phi_out, lam) at the pass's end point, lam is rotated back through
+// RY_lb and D_la, then the partials of la's RZ and RY gates come from
+// (phi_a, lam) and lam is rotated back through RY_la.  It reads phi_in and
+// lam and writes lam (3 A s) where the two single-layer reverse passes move
+// 7 A s.
+template <typename R, int K, int LOGR, bool CONTIG, uint32_t AM = 0>
+__device__ __forceinline__ void bwd2_body(const cx<R> *phi_in, cx<R> *lam, const FusedArgs &a,
+                                          u64 t0, u64 tstep, int col, cx<R> *lds, cx<R> *ldsa,
+                                          double *sh)
+{
+    using T = Tile<K, LOGR>;
+    const int t = threadIdx.x;
+    constexpr int LD = T::lo(0), ST = T::lo(T::NA - 1);
+    const u64 toff_ld = thread_off<K, LOGR>(t, LD, a), toff_st = thread_off<K, LOGR>(t, ST, a);
+    RegMap<LOGR, CONTIG> mld;
+    mld.init(a.pos + LD);
+    LDiag<R, K, LOGR> dg;
+    P0Diag<R, K, LOGR> pd;   // the previous layer's diagonal when the pass applied it on load
+    if (a.in_mode != IN_LOAD) pd.init(a.dt, t);
+    double accYa[K], accYb[K], accZa[LOGR], accZb[LOGR], zta = 0.0, ztb = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) accYa[j] = accYb[j] = 0.0;
+#pragma unroll
+    for (int k = 0; k < LOGR; ++k) accZa[k] = accZb[k] = 0.0;
+
+    const RyC<R, K, AM> rca(a, a.layer), rcb(a, a.layer2);
+    for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
+        const u64 base = tile_base(tile, a);
+        cx<R> f[T::NR], l[T::NR];
+        load_tile<R, K, LOGR, CONTIG>(f, phi_in, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
+        {
+            const cx<R> *lp = lam + (base | toff_ld);
+#pragma unroll
+            for (int r = 0; r < T::NR; ++r) l[r] = ld_amp(lp + mld.off(r));
+        }
+        // phi_a = RY_la phi_in, kept in the second buffer (last layout)
+        fwd_assign<R, K, LOGR, 0, AM>(f, a, rca);
+        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1, AM>::run(f, lds, t, a, rca);
+#pragma unroll
+        for (int r = 0; r < T::NR; ++r) ldsa[T::lds_index(t, r, ST)] = f[r];
+        // phi_out = RY_lb D_la phi_a
+        dg.tile(a.ld, tile, base | toff_st, t);
+#pragma unroll
+        for (int r = 0; r < T::NR; ++r) f[r] = cmul(f[r], dg.at(a.ld, r));
+        fwd_assign<R, K, LOGR, T::NA - 1, AM>(f, a, rcb);
+        if constexpr (T::NA > 1) FwdChainRev<R, K, LOGR, T::NA - 2, AM>::run(f, lds, t, a, rcb);
+        // layer lb at the pass's end point, then lam back through RY_lb
+        z_partials<R, K, LOGR, 0, AM>(f, l, accZb, ztb, a);
+        ygrad_assign<R, K, LOGR, 0, AM>(f, l, accYb, a);
+        if constexpr (T::NA > 1) GradChain<R, K, LOGR, 1, AM>::run(f, l, accYb, lds, t, a);
+        inv_assign<R, K, LOGR, T::NA - 1, AM>(l, a, rcb);
+        if constexpr (T::NA > 1) InvChainRev<R, K, LOGR, T::NA - 2, AM>::run(l, lds, t, a, rcb);
+        // lam back through D_la; phi_a from the second buffer (load layout)
+        __syncthreads();
+        dg.tile(a.ld2, tile, base | toff_ld, t);
+#pragma unroll
+        for (int r = 0; r < T::NR; ++r) {
+            l[r] = cmul_conj(l[r], dg.at(a.ld2, r));
+            f[r] = ldsa[T::lds_index(t, r, LD)];
+        }
+        // layer la, then lam back through RY_la
+        z_partials<R, K, LOGR, 0, AM>(f, l, accZa, zta, a);
+        ygrad_assign<R, K, LOGR, 0, AM>(f, l, accYa, a);
+        if constexpr (T::NA > 1) GradChain<R, K, LOGR, 1, AM>::run(f, l, accYa, lds, t, a);
+        inv_assign<R, K, LOGR, T::NA - 1, AM>(l, a, rca);
+        if constexpr (T::NA > 1) InvChainRev<R, K, LOGR, T::NA - 2, AM>::run(l, lds, t, a, rca);
+        cx<R> *ls = lam + fresh(base | toff_ld);
+#pragma unroll
+        for (int r = 0; r < T::NR; ++r) st_amp(ls + mld.off(r), l[r]);
+    }
+    write_partials<R, K, LOGR, 0, true>(accYb, accZb, ztb, sh, a, a.layer2, col);
+    write_partials<R, K, LOGR, 0, true>(accYa, accZa, zta, sh, a, a.layer, col);
+}
+
+template <typename R, int K, int LOGR, bool CONTIG>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd2_pass(const void *phi_in_, void *lam_,
+                                                               FusedArgs a)
+{
+    __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
+    __shared__ cx<R> ldsa[Tile<K, LOGR>::LDS];
+    __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
+    const int b = blockIdx.x, g = gridDim.x;
+    constexpr uint32_t L = act_later<R, K>() | kActRuntime;
+    if (a.active == (L & ~kActRuntime))
+        bwd2_body<R, K, LOGR, CONTIG, L>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, b, g, b, lds,
+                                         ldsa, sh);
+    else
+        bwd2_body<R, K, LOGR, CONTIG, 0>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, b, g, b, lds,
+                                         ldsa, sh);
+}
+
 // Last forward pass of the last layer + energy + first reverse pass, for a
 // Z-only Hamiltonian with diagonal D: in each tile psi gets the pass's RY
 // gates (assignments 0 .. NA-1), E += sum D_i |psi_i|^2 and lam = D psi;
@@ -986,16 +1083,15 @@ __device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const Fu
         fwd_assign<R, K, LOGR, 0, AM>(f, a, rc);
         if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1, AM>::run(f, lds, t, a, rc);
         // energy and lam in the last assignment's layout
-        R et = 0;
+        // E in FP64 from the FP64 diagonal: D_i |psi_i|^2 per amplitude
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
             const double d = __builtin_nontemporal_load(a.hdiag + (base | toff_st) + mst.off(r));
-            const R p = f[r].re * f[r].re + f[r].im * f[r].im;
-            et += (R)d * p;
+            const double fr = (double)f[r].re, fi = (double)f[r].im;
+            eacc += d * (fr * fr + fi * fi);
             l[r].re = (R)d * f[r].re;
             l[r].im = (R)d * f[r].im;
         }
-        eacc += (double)et;
         ygrad_assign<R, K, LOGR, T::NA - 1, AM>(f, l, accY, a);
         if constexpr (T::NA > 1)
             GradChainRev<R, K, LOGR, T::NA - 2, AM>::run(f, l, accY, lds, t, a);
@@ -1382,6 +1478,7 @@ __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const Off
             R A[T::NR], B[T::NR];
 #pragma unroll
             for (int r = 0; r < T::NR; ++r) A[r] = B[r] = R(0);
+
             // a group's terms share their register signs: sum their signed
             // coefficients for this thread, then spread the sum over the
             // registers once (the group-end flag is the same in every lane)
@@ -2102,6 +2199,26 @@ hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *la
     } else {
         GV_LAUNCH_K(k_bwd_pass, prec, grid, plan.K, phi_in, phi, lam, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t fused_backward2_pass(int prec, const void *phi_in, void *lam, const gv_ansatz &an,
+                                const TilePlan &plan, int pass, int layer, int in_mode,
+                                const Chunks &ch, const LDiagTab &ld_last,
+                                const LDiagTab &ld_load, const FusedTables &t, double *part,
+                                int grid, hipStream_t s)
+{
+    if (in_mode == IN_GENERATE || (in_mode == IN_LOAD_DIAG && (pass != 0 || layer < 1)))
+        return hipErrorInvalidValue;
+    FusedArgs a = base_args(an, plan, pass, layer, t);
+    a.in_mode = in_mode;
+    if (in_mode == IN_LOAD_DIAG) a.dt = layer_tab(an, ch, t, layer - 1);
+    a.layer2 = layer + 1;
+    a.ld = ld_last;
+    a.ld2 = ld_load;
+    a.part = part;
+    a.grid = grid;
+    GV_LAUNCH_K(k_bwd2_pass, prec, grid, plan.K, phi_in, lam, a);
     return hipGetLastError();
 }
 

@@ -72,6 +72,10 @@ struct gv_pauli_s {
     int cover_K = 0, cover_C = 0;
     gv::OffClass *dev_cls = nullptr;
     gv::OffTerm *dev_terms = nullptr;
+    // the off-diagonal terms in qubit-wise-commuting group order: support
+    // masks and coefficients (for the finite-shot estimate)
+    uint64_t *dev_gmask = nullptr;
+    double *dev_gcoef = nullptr;
     // device form (borrowed caller memory)
     void *dev = nullptr;
     size_t dev_bytes = 0;
@@ -269,6 +273,22 @@ hipError_t reduce_energy(const double *epart, int grid, double *energy, hipStrea
 
 hipError_t copy_vector(void *dst, const void *src, size_t bytes, hipStream_t s);
 
+// measurement (gv_sample.hip): Born-rule samples, the most probable index,
+// the basis change of a qubit-wise-commuting group, shot averages
+size_t sample_work_bytes(int n);
+hipError_t sample_born(int prec, const void *psi, int n, const double *u, int64_t shots,
+                       void *work, uint64_t *out, hipStream_t s);
+hipError_t argmax_prob(int prec, const void *psi, int n, void *work, uint64_t *idx, double *p,
+                       hipStream_t s);
+hipError_t basis_rotate(int prec, const void *src, void *dst, int n, u64 xmask, u64 ymask,
+                        hipStream_t s);
+hipError_t parity_means(const uint64_t *b, int64_t shots, const uint64_t *mask, const double *c,
+                        int64_t m, double *term_out, hipStream_t s);
+hipError_t diag_mean(const uint64_t *b, int64_t shots, const double *diag, double *out,
+                     hipStream_t s);
+hipError_t sum_terms(const double *term, int64_t m, const double *diag_part, double *out,
+                     hipStream_t s);
+
 // streaming-bandwidth probe (gv_stream.hip): kind is a gv_stream_kind
 enum { STREAM_READ = 0, STREAM_WRITE = 1, STREAM_COPY = 2, STREAM_RMW = 3, STREAM_TRIAD = 4 };
 hipError_t stream_probe(int kind, int width, int unroll, int nt, void *dst, const void *s0,
@@ -335,6 +355,18 @@ hipError_t fused_forward2_pass(int prec, void *psi, const gv_ansatz &an, const T
                                int pass, int layer, int in_mode, const Chunks &ch,
                                const FusedTables &t, const LDiagTab &ld, hipStream_t s,
                                const void *src = nullptr);
+// Reverse of a two-layer pass (layers `layer` and layer + 1 on plan pass
+// `pass`) in one sweep from the state stored before it (phi_in): lam is read
+// and rewritten, the partials of both layers written.  in_mode: how the
+// forward pass loaded phi_in (FWD_LOAD, or FWD_LOAD_DIAG in pass 0: times
+// the previous layer's diagonal); lam is left at the point after that load.
+// ld_last / ld_load: `layer`'s diagonal in the pass's last and load
+// assignments.
+hipError_t fused_backward2_pass(int prec, const void *phi_in, void *lam, const gv_ansatz &an,
+                                const TilePlan &plan, int pass, int layer, int in_mode,
+                                const Chunks &ch, const LDiagTab &ld_last,
+                                const LDiagTab &ld_load, const FusedTables &t, double *part,
+                                int grid, hipStream_t s);
 hipError_t fused_turnaround(int prec, const void *psi, void *lam, const double *hdiag,
                             const gv_ansatz &a, const TilePlan &plan, int pass, int layer,
                             int in_mode, const Chunks &ch, const FusedTables &t, double *part,

@@ -99,6 +99,16 @@ def lib():
     L.gv_batch_destroy.argtypes = [vp]
     L.gv_batch_energy_grad.argtypes = [i32, IP, CP, i32, vp, sz, vp, vp, vp]
     L.gv_stream_probe.argtypes = [i32, i32, i32, i32, i32, i32, vp, vp, vp, sz, vp]
+    L.gv_sample_work_bytes.argtypes = [i32]
+    L.gv_sample_work_bytes.restype = sz
+    L.gv_sample.argtypes = [i32, i32, vp, vp, i64, vp, sz, vp, vp]
+    L.gv_argmax.argtypes = [i32, i32, vp, vp, sz, vp, vp, vp]
+    L.gv_pauli_sum_group.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_uint64),
+                                     ctypes.POINTER(ctypes.c_uint64),
+                                     ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(i64)]
+    L.gv_energy_shots_work_bytes.argtypes = [vp, i32, i64]
+    L.gv_energy_shots_work_bytes.restype = sz
+    L.gv_energy_shots.argtypes = [vp, i32, i32, vp, vp, i64, vp, sz, vp, vp]
     L.gv_profile_enable.argtypes = [vp, i32]
     L.gv_profile_reset.argtypes = [vp]
     L.gv_profile_read.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
@@ -109,7 +119,8 @@ def lib():
                  "gv_pauli_sum_info", "gv_pauli_sum_device_bytes", "gv_pauli_sum_prepare",
                  "gv_pauli_sum_prepare_for", "gv_energy", "gv_energy_grad", "gv_batch_query",
                  "gv_batch_create", "gv_batch_run", "gv_batch_destroy", "gv_batch_energy_grad",
-                 "gv_stream_probe", "gv_pauli_sum_plan"):
+                 "gv_stream_probe", "gv_pauli_sum_plan", "gv_sample", "gv_argmax",
+                 "gv_pauli_sum_group", "gv_energy_shots"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -224,7 +235,7 @@ class State:
     PROF_KINDS = {"forward_pass": 0, "backward_pass": 1, "energy": 2, "init": 3,
                   "plain_gate": 4, "other": 5, "offdiag": 6, "first_layer": 7,
                   "forward_pass2": 8, "backward_ld": 9, "backward_gf": 10, "backward_gf_ld": 11,
-                  "turnaround": 12}
+                  "turnaround": 12, "backward2": 13}
 
     def profile(self, enable: bool = True):
         _check(lib().gv_profile_enable(self.handle, int(enable)), "gv_profile_enable")
@@ -535,3 +546,64 @@ class ParamShift:
         self.batch.run()
         e = self.batch.energies[:, 0]
         return 0.5 * (e[0::2] - e[1::2]), e
+
+
+# ---------------------------------------------------------------- measurement
+
+def _amps_arg(amps: torch.Tensor):
+    """(n, precision code) of a complex64 / complex128 amplitude tensor."""
+    assert amps.is_contiguous() and amps.dtype in (torch.complex64, torch.complex128)
+    n = amps.numel().bit_length() - 1
+    assert amps.numel() == 1 << n
+    return n, (C64 if amps.dtype == torch.complex64 else C128)
+
+
+def sample(amps: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
+    """Born-rule indices (uint64 as int64) for the uniform draws u (float64,
+    device): inverse-CDF sampling of |amps|^2 (Sec. V-A)."""
+    n, prec = _amps_arg(amps)
+    assert u.dtype == torch.float64 and u.is_contiguous() and u.device == amps.device
+    out = torch.empty(u.numel(), dtype=torch.int64, device=amps.device)
+    wb = lib().gv_sample_work_bytes(n)
+    owner, work = _aligned_bytes(wb, amps.device)
+    _check(lib().gv_sample(n, prec, _ptr(amps), _ptr(u), u.numel(), _ptr(work), wb, _ptr(out),
+                           _stream_ptr(amps.device)), "gv_sample")
+    return out
+
+
+def argmax(amps: torch.Tensor) -> Tuple[torch.Tensor, torch.Tensor]:
+    """(index, probability) of the most probable basis state (Sec. IV-F)."""
+    n, prec = _amps_arg(amps)
+    idx = torch.empty(1, dtype=torch.int64, device=amps.device)
+    p = torch.empty(1, dtype=torch.float64, device=amps.device)
+    wb = lib().gv_sample_work_bytes(n)
+    owner, work = _aligned_bytes(wb, amps.device)
+    _check(lib().gv_argmax(n, prec, _ptr(amps), _ptr(work), wb, _ptr(idx), _ptr(p),
+                           _stream_ptr(amps.device)), "gv_argmax")
+    return idx, p
+
+
+def pauli_groups(h: "PauliSum"):
+    """[(X qubits, Y qubits, Z qubits, terms), ...] of the off-diagonal terms."""
+    out = []
+    _, _, ng = h.info()
+    for g in range(ng):
+        xm, ym, zm = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        nt = ctypes.c_int64()
+        _check(lib().gv_pauli_sum_group(h.handle, g, ctypes.byref(xm), ctypes.byref(ym),
+                                        ctypes.byref(zm), ctypes.byref(nt)), "gv_pauli_sum_group")
+        out.append((xm.value, ym.value, zm.value, nt.value))
+    return out
+
+
+def energy_shots(h: "PauliSum", amps: torch.Tensor, u: torch.Tensor, shots: int) -> torch.Tensor:
+    """The finite-shot energy estimate (Sec. V-A) of the prepared Pauli sum on
+    amps; u: (1 + groups) * shots uniform draws (float64, device)."""
+    n, prec = _amps_arg(amps)
+    assert u.dtype == torch.float64 and u.is_contiguous()
+    e = torch.empty(2, dtype=torch.float64, device=amps.device)
+    wb = lib().gv_energy_shots_work_bytes(h.handle, prec, shots)
+    owner, work = _aligned_bytes(wb, amps.device)
+    _check(lib().gv_energy_shots(h.handle, n, prec, _ptr(amps), _ptr(u), shots, _ptr(work), wb,
+                                 _ptr(e), _stream_ptr(amps.device)), "gv_energy_shots")
+    return e

@@ -67,6 +67,7 @@ def test_basis_rotation_maps_group_terms_to_z_strings():
         v = np.column_stack([M.basis_rotate(col, n, xm, ym) for col in np.eye(16, dtype=complex)])
         assert np.allclose(v.conj().T @ v, np.eye(16))
         assert np.allclose(M.basis_rotate(psi, n, xm, ym), v @ psi)
+        assert np.allclose(M.basis_rotate(psi, n, xm, ym, single=True), v @ psi, atol=1e-6)
         zm = (~(xm | ym)) & 0b1111
         for sub in range(16):                 # every term the basis allows
             x = sub & (xm | ym)
