@@ -1237,14 +1237,13 @@ gv_status gv_energy_grad(gv_state st, gv_pauli_sum h, const double *theta, const
             fl.store_phi = k >= 1 && !prev_fresh;
             fl.store_lam = 1;
             fl.grad_first = !fl.store_phi && !fl.diag_phi;
-            // STORE keeps the two-layer pass's input: one sweep from there
-            // undoes both layers (3 A s instead of 7)
-            if (op.lb >= 0 && store && k >= 1 && !fl.diag_lam) {
-                ProfScope ps(st, GV_PROF_BACKWARD2, 3.0 * vb);
+            // a two-layer pass is undone in one sweep from its output (3 A s,
+            // 4 when phi must be carried back, instead of 7 or 8)
+            if (op.lb >= 0 && k >= 1 && !fl.diag_lam) {
+                ProfScope ps(st, GV_PROF_BACKWARD2, (fl.store_phi ? 4.0 : 3.0) * vb);
                 if (gv_status r = check_hip(
-                        fused_backward2_pass(st->prec, store_out(c, k - 1, psi, ck, vb), lam, *a,
-                                             c.plan, op.g, op.la, op.in_mode, c.ch, c.ld[op.la],
-                                             c.ld0[op.la], c.tabs, part, c.w.grid, s),
+                        fused_backward2_pass(st->prec, phi_src, psi, lam, *a, c.plan, op.g, op.la,
+                                             fl.store_phi, c.ld[op.la], c.tabs, part, c.w.grid, s),
                         "two-layer backward pass"))
                     return r;
                 continue;

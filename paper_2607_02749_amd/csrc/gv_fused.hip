@@ -74,7 +74,6 @@ struct FusedArgs {
     u64 qmask;               // qubits whose gradient rows are written (others get 0)
     int layer2;              // two-layer passes: the second rotation layer
     LDiagTab ld;             // two-layer passes: diagonal of `layer` in the last assignment
-    LDiagTab ld2;            // fused two-layer reverse: the same diagonal in the load assignment
 };
 
 template <int K, int LOGR>
@@ -952,19 +951,19 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_gf_ld_pass(const void *
 }
 
 // Reverse of a two-layer pass (rotation layers la = a.layer and lb =
-// a.layer2 on the same tile qubits) in one sweep, from the state the pass
-// started from (phi_in, kept by the STORE mode): per tile, phi_in is carried
-// forward in registers to phi_a = RY_la phi_in (kept in a second LDS buffer)
-// and phi_out = RY_lb D_la phi_a; the partials of lb's RZ and RY gates come
-// from (phi_out, lam) at the pass's end point, lam is rotated back through
-// RY_lb and D_la, then the partials of la's RZ and RY gates come from
-// (phi_a, lam) and lam is rotated back through RY_la.  It reads phi_in and
-// lam and writes lam (3 A s) where the two single-layer reverse passes move
-// 7 A s.
-template <typename R, int K, int LOGR, bool CONTIG, uint32_t AM = 0>
-__device__ __forceinline__ void bwd2_body(const cx<R> *phi_in, cx<R> *lam, const FusedArgs &a,
-                                          u64 t0, u64 tstep, int col, cx<R> *lds, cx<R> *ldsa,
-                                          double *sh)
+// a.layer2 on the same tile qubits) in one sweep from the pass's end point
+// (phi_src, the state the pass wrote, with lam at the same point).  Per tile
+// both vectors go back together: the RZ partials of lb there, then through
+// RY_lb (assignments 0 .. NA-1, each RY partial taken before its gate is
+// undone), the RZ partials of la (the diagonal D_la commutes with Z_q, so
+// they can be taken before it is undone), D_la, and RY_la in the order
+// NA-1 .. 0.  lam is stored; phi only when the next reverse pass needs it
+// (a.store_phi, the modes that keep no copy of the pass's input).  It moves
+// 3 A s (4 with phi) where the two single-layer reverse passes move 7 (8).
+template <typename R, int K, int LOGR, bool CONTIG, bool SP, uint32_t AM = 0>
+__device__ __forceinline__ void bwd2_body(const cx<R> *phi_src, cx<R> *phi, cx<R> *lam,
+                                          const FusedArgs &a, u64 t0, u64 tstep, int col,
+                                          cx<R> *lds, double *sh)
 {
     using T = Tile<K, LOGR>;
     const int t = threadIdx.x;
@@ -973,8 +972,6 @@ __device__ __forceinline__ void bwd2_body(const cx<R> *phi_in, cx<R> *lam, const
     RegMap<LOGR, CONTIG> mld;
     mld.init(a.pos + LD);
     LDiag<R, K, LOGR> dg;
-    P0Diag<R, K, LOGR> pd;   // the previous layer's diagonal when the pass applied it on load
-    if (a.in_mode != IN_LOAD) pd.init(a.dt, t);
     double accYa[K], accYb[K], accZa[LOGR], accZb[LOGR], zta = 0.0, ztb = 0.0;
 #pragma unroll
     for (int j = 0; j < K; ++j) accYa[j] = accYb[j] = 0.0;
@@ -984,67 +981,79 @@ __device__ __forceinline__ void bwd2_body(const cx<R> *phi_in, cx<R> *lam, const
     const RyC<R, K, AM> rca(a, a.layer), rcb(a, a.layer2);
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
+        // the diagonal's per-tile factors first: its loop over the straddling
+        // pairs placed between the two layers' chains costs ~200 registers
+        dg.tile(a.ld, tile, base | toff_st, t);
         cx<R> f[T::NR], l[T::NR];
-        load_tile<R, K, LOGR, CONTIG>(f, phi_in, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
         {
+            const cx<R> *fp = phi_src + (base | toff_ld);
             const cx<R> *lp = lam + (base | toff_ld);
 #pragma unroll
-            for (int r = 0; r < T::NR; ++r) l[r] = ld_amp(lp + mld.off(r));
+            for (int r = 0; r < T::NR; ++r) {
+                f[r] = ld_amp(fp + mld.off(r));
+                l[r] = ld_amp(lp + mld.off(r));
+            }
         }
-        // phi_a = RY_la phi_in, kept in the second buffer (last layout)
-        fwd_assign<R, K, LOGR, 0, AM>(f, a, rca);
-        if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1, AM>::run(f, lds, t, a, rca);
-#pragma unroll
-        for (int r = 0; r < T::NR; ++r) ldsa[T::lds_index(t, r, ST)] = f[r];
-        // phi_out = RY_lb D_la phi_a
-        dg.tile(a.ld, tile, base | toff_st, t);
-#pragma unroll
-        for (int r = 0; r < T::NR; ++r) f[r] = cmul(f[r], dg.at(a.ld, r));
-        fwd_assign<R, K, LOGR, T::NA - 1, AM>(f, a, rcb);
-        if constexpr (T::NA > 1) FwdChainRev<R, K, LOGR, T::NA - 2, AM>::run(f, lds, t, a, rcb);
-        // layer lb at the pass's end point, then lam back through RY_lb
+        // layer lb
         z_partials<R, K, LOGR, 0, AM>(f, l, accZb, ztb, a);
-        ygrad_assign<R, K, LOGR, 0, AM>(f, l, accYb, a);
-        if constexpr (T::NA > 1) GradChain<R, K, LOGR, 1, AM>::run(f, l, accYb, lds, t, a);
-        inv_assign<R, K, LOGR, T::NA - 1, AM>(l, a, rcb);
-        if constexpr (T::NA > 1) InvChainRev<R, K, LOGR, T::NA - 2, AM>::run(l, lds, t, a, rcb);
-        // lam back through D_la; phi_a from the second buffer (load layout)
-        __syncthreads();
-        dg.tile(a.ld2, tile, base | toff_ld, t);
+        bwd_assign<R, K, LOGR, 0, AM>(f, l, accYb, a, rcb);
+        if constexpr (T::NA > 1) BwdChain<R, K, LOGR, 1, AM>::run(f, l, accYb, lds, t, a, rcb);
+        // layer la: RZ partials, D_la undone on both, then the RY gates
+        z_partials<R, K, LOGR, T::NA - 1, AM>(f, l, accZa, zta, a);
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
-            l[r] = cmul_conj(l[r], dg.at(a.ld2, r));
-            f[r] = ldsa[T::lds_index(t, r, LD)];
+            const cx<R> d = dg.at(a.ld, r);
+            f[r] = cmul_conj(f[r], d);
+            l[r] = cmul_conj(l[r], d);
         }
-        // layer la, then lam back through RY_la
-        z_partials<R, K, LOGR, 0, AM>(f, l, accZa, zta, a);
-        ygrad_assign<R, K, LOGR, 0, AM>(f, l, accYa, a);
-        if constexpr (T::NA > 1) GradChain<R, K, LOGR, 1, AM>::run(f, l, accYa, lds, t, a);
-        inv_assign<R, K, LOGR, T::NA - 1, AM>(l, a, rca);
-        if constexpr (T::NA > 1) InvChainRev<R, K, LOGR, T::NA - 2, AM>::run(l, lds, t, a, rca);
-        cx<R> *ls = lam + fresh(base | toff_ld);
+        bwd_assign<R, K, LOGR, T::NA - 1, AM>(f, l, accYa, a, rca);
+        if constexpr (T::NA > 1)
+            BwdChainRev<R, K, LOGR, T::NA - 2, AM>::run(f, l, accYa, lds, t, a, rca);
+        const u64 o = fresh(base | toff_ld);
 #pragma unroll
-        for (int r = 0; r < T::NR; ++r) st_amp(ls + mld.off(r), l[r]);
+        for (int r = 0; r < T::NR; ++r) {
+            if constexpr (SP) st_amp(phi + o + mld.off(r), f[r]);
+            st_amp(lam + o + mld.off(r), l[r]);
+        }
     }
     write_partials<R, K, LOGR, 0, true>(accYb, accZb, ztb, sh, a, a.layer2, col);
-    write_partials<R, K, LOGR, 0, true>(accYa, accZa, zta, sh, a, a.layer, col);
+    write_partials<R, K, LOGR, T::NA - 1, true>(accYa, accZa, zta, sh, a, a.layer, col);
+}
+
+// SP: phi is carried back too (a.store_phi)
+template <typename R, int K, int LOGR, bool CONTIG, bool SP>
+__device__ __forceinline__ void bwd2_kernel(const void *phi_src_, void *phi_, void *lam_,
+                                            const FusedArgs &a, cx<R> *lds, double *sh)
+{
+    const int b = blockIdx.x, g = gridDim.x;
+    constexpr uint32_t F = act_full<K>(), L = act_later<R, K>();
+    const cx<R> *ps = (const cx<R> *)phi_src_;
+    cx<R> *p = (cx<R> *)phi_, *l = (cx<R> *)lam_;
+    if (a.active == F)
+        bwd2_body<R, K, LOGR, CONTIG, SP, F>(ps, p, l, a, b, g, b, lds, sh);
+    else if (a.active == L)
+        bwd2_body<R, K, LOGR, CONTIG, SP, L>(ps, p, l, a, b, g, b, lds, sh);
+    else
+        bwd2_body<R, K, LOGR, CONTIG, SP, 0>(ps, p, l, a, b, g, b, lds, sh);
 }
 
 template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd2_pass(const void *phi_in_, void *lam_,
-                                                               FusedArgs a)
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd2_pass(const void *phi_src_, void *phi_,
+                                                               void *lam_, FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
-    __shared__ cx<R> ldsa[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
-    const int b = blockIdx.x, g = gridDim.x;
-    constexpr uint32_t L = act_later<R, K>() | kActRuntime;
-    if (a.active == (L & ~kActRuntime))
-        bwd2_body<R, K, LOGR, CONTIG, L>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, b, g, b, lds,
-                                         ldsa, sh);
-    else
-        bwd2_body<R, K, LOGR, CONTIG, 0>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, b, g, b, lds,
-                                         ldsa, sh);
+    bwd2_kernel<R, K, LOGR, CONTIG, false>(phi_src_, phi_, lam_, a, lds, sh);
+}
+
+template <typename R, int K, int LOGR, bool CONTIG>
+__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd2_phi_pass(const void *phi_src_,
+                                                                   void *phi_, void *lam_,
+                                                                   FusedArgs a)
+{
+    __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
+    __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
+    bwd2_kernel<R, K, LOGR, CONTIG, true>(phi_src_, phi_, lam_, a, lds, sh);
 }
 
 // Last forward pass of the last layer + energy + first reverse pass, for a
@@ -2202,23 +2211,19 @@ hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *la
     return hipGetLastError();
 }
 
-hipError_t fused_backward2_pass(int prec, const void *phi_in, void *lam, const gv_ansatz &an,
-                                const TilePlan &plan, int pass, int layer, int in_mode,
-                                const Chunks &ch, const LDiagTab &ld_last,
-                                const LDiagTab &ld_load, const FusedTables &t, double *part,
-                                int grid, hipStream_t s)
+hipError_t fused_backward2_pass(int prec, const void *phi_src, void *phi, void *lam,
+                                const gv_ansatz &an, const TilePlan &plan, int pass, int layer,
+                                int store_phi, const LDiagTab &ld_last, const FusedTables &t,
+                                double *part, int grid, hipStream_t s)
 {
-    if (in_mode == IN_GENERATE || (in_mode == IN_LOAD_DIAG && (pass != 0 || layer < 1)))
-        return hipErrorInvalidValue;
     FusedArgs a = base_args(an, plan, pass, layer, t);
-    a.in_mode = in_mode;
-    if (in_mode == IN_LOAD_DIAG) a.dt = layer_tab(an, ch, t, layer - 1);
     a.layer2 = layer + 1;
     a.ld = ld_last;
-    a.ld2 = ld_load;
+    a.store_phi = store_phi;
     a.part = part;
     a.grid = grid;
-    GV_LAUNCH_K(k_bwd2_pass, prec, grid, plan.K, phi_in, lam, a);
+    if (store_phi) GV_LAUNCH_K(k_bwd2_phi_pass, prec, grid, plan.K, phi_src, phi, lam, a);
+    else GV_LAUNCH_K(k_bwd2_pass, prec, grid, plan.K, phi_src, phi, lam, a);
     return hipGetLastError();
 }
 

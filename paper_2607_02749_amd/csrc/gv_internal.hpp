@@ -356,17 +356,14 @@ hipError_t fused_forward2_pass(int prec, void *psi, const gv_ansatz &an, const T
                                const FusedTables &t, const LDiagTab &ld, hipStream_t s,
                                const void *src = nullptr);
 // Reverse of a two-layer pass (layers `layer` and layer + 1 on plan pass
-// `pass`) in one sweep from the state stored before it (phi_in): lam is read
-// and rewritten, the partials of both layers written.  in_mode: how the
-// forward pass loaded phi_in (FWD_LOAD, or FWD_LOAD_DIAG in pass 0: times
-// the previous layer's diagonal); lam is left at the point after that load.
-// ld_last / ld_load: `layer`'s diagonal in the pass's last and load
-// assignments.
-hipError_t fused_backward2_pass(int prec, const void *phi_in, void *lam, const gv_ansatz &an,
-                                const TilePlan &plan, int pass, int layer, int in_mode,
-                                const Chunks &ch, const LDiagTab &ld_last,
-                                const LDiagTab &ld_load, const FusedTables &t, double *part,
-                                int grid, hipStream_t s);
+// `pass`) in one sweep from the state the pass wrote (phi_src) and lam at
+// the same point: lam is rewritten in place, the partials of both layers
+// written, and with store_phi the state before the pass goes to phi (which
+// may be phi_src).
+hipError_t fused_backward2_pass(int prec, const void *phi_src, void *phi, void *lam,
+                                const gv_ansatz &an, const TilePlan &plan, int pass, int layer,
+                                int store_phi, const LDiagTab &ld_last, const FusedTables &t,
+                                double *part, int grid, hipStream_t s);
 hipError_t fused_turnaround(int prec, const void *psi, void *lam, const double *hdiag,
                             const gv_ansatz &a, const TilePlan &plan, int pass, int layer,
                             int in_mode, const Chunks &ch, const FusedTables &t, double *part,
