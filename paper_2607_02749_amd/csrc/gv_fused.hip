@@ -639,6 +639,38 @@ constexpr uint32_t act_later()
     return act_full<K>() & ~((1u << (sizeof(R) == 4 ? 4 : 3)) - 1u);
 }
 
+// Each pass kernel is compiled once per mask selector MS, so that every
+// variant gets its own register allocation (a kernel holding the three
+// bodies would run all of them at the occupancy of the largest): MS_FULL and
+// MS_LATER compile the two masks above into the body, MS_ANY reads the
+// pass's mask at run time.  RT: the body still reads the mask at run time,
+// keeping the chains' per-gate branches (fewer live registers in the
+// reverse bodies that rotate both vectors); the whole-assignment skips still
+// come from the compiled mask.
+enum { MS_ANY = 0, MS_FULL = 1, MS_LATER = 2 };
+
+// The pass kernels, and the waves per SIMD each variant is compiled for
+// (its register budget: 4 waves = 128 VGPRs, 3 = 168, 2 = 256).  1 leaves
+// the compiler's own choice; a higher target is set where the variant sits
+// just above a step and the few registers over it spill at no measurable
+// cost (outside the tile loop).
+enum PassKind {
+    PK_FWD_PASS, PK_FWD_LOAD_PASS, PK_FWD2_PASS, PK_FWD2_LOAD_PASS, PK_TURN_PASS,
+    PK_TURN_LOAD_PASS, PK_BWD_PASS, PK_BWD_LD_PASS, PK_BWD_GF_PASS, PK_BWD_GF_LD_PASS,
+    PK_BWD2_PASS, PK_BWD2_PHI_PASS
+};
+template <typename R>
+constexpr int pass_waves(int kind, int ms)
+{
+    return (sizeof(R) == 4 && ms == MS_LATER && kind == PK_BWD2_PASS) ? 3 : 1;
+}
+template <typename R, int K, int MS, bool RT = false>
+constexpr uint32_t pass_mask()
+{
+    return (MS == MS_FULL ? act_full<K>() : (MS == MS_LATER ? act_later<R, K>() : 0u)) |
+           (RT && MS != MS_ANY ? kActRuntime : 0u);
+}
+
 template <typename R, int K, int LOGR, bool CONTIG, bool PL = false, uint32_t AM = 0>
 __device__ __forceinline__ void fwd_body(cx<R> *psi, const cx<R> *src, const FusedArgs &a,
                                          u64 t0, u64 tstep, cx<R> *lds)
@@ -665,35 +697,23 @@ __device__ __forceinline__ void fwd_body(cx<R> *psi, const cx<R> *src, const Fus
     }
 }
 
-template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_pass(void *psi_, const void *src_,
+template <typename R, int K, int LOGR, bool CONTIG, int MS>
+__global__ __launch_bounds__(1 << (K - LOGR), pass_waves<R>(PK_FWD_PASS, MS)) void k_fwd_pass(void *psi_, const void *src_,
                                                               FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     const int b = blockIdx.x, g = gridDim.x;
-    constexpr uint32_t F = act_full<K>(), L = act_later<R, K>();
-    if (a.active == F)
-        fwd_body<R, K, LOGR, CONTIG, false, F>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
-    else if (a.active == L)
-        fwd_body<R, K, LOGR, CONTIG, false, L>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
-    else
-        fwd_body<R, K, LOGR, CONTIG, false, 0>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
+    fwd_body<R, K, LOGR, CONTIG, false, pass_mask<R, K, MS>()>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
 }
 
 // the same for a plain load (no diagonal on load, no generated layer)
-template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd_load_pass(void *psi_, const void *src_,
+template <typename R, int K, int LOGR, bool CONTIG, int MS>
+__global__ __launch_bounds__(1 << (K - LOGR), pass_waves<R>(PK_FWD_LOAD_PASS, MS)) void k_fwd_load_pass(void *psi_, const void *src_,
                                                                    FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     const int b = blockIdx.x, g = gridDim.x;
-    constexpr uint32_t F = act_full<K>(), L = act_later<R, K>();
-    if (a.active == F)
-        fwd_body<R, K, LOGR, CONTIG, true, F>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
-    else if (a.active == L)
-        fwd_body<R, K, LOGR, CONTIG, true, L>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
-    else
-        fwd_body<R, K, LOGR, CONTIG, true, 0>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
+    fwd_body<R, K, LOGR, CONTIG, true, pass_mask<R, K, MS>()>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
 }
 
 // Block sums of the gradient partials of the pass's active tile qubits for
@@ -823,37 +843,25 @@ __device__ __forceinline__ void bwd_body(const cx<R> *phi_in, cx<R> *phi, cx<R> 
     write_partials<R, K, LOGR, 0, true>(accY, accZr, ztot, sh, a, a.layer, col);
 }
 
-template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_pass(const void *phi_in_, void *phi_,
+template <typename R, int K, int LOGR, bool CONTIG, int MS>
+__global__ __launch_bounds__(1 << (K - LOGR), pass_waves<R>(PK_BWD_PASS, MS)) void k_bwd_pass(const void *phi_in_, void *phi_,
                                                               void *lam_, FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
     const int b = blockIdx.x, g = gridDim.x;
-    constexpr uint32_t L = act_later<R, K>() | kActRuntime;
-    if (a.active == (L & ~kActRuntime))
-        bwd_body<R, K, LOGR, CONTIG, false, L>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_,
-                                               a, b, g, b, lds, sh);
-    else
-        bwd_body<R, K, LOGR, CONTIG, false, 0>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_,
-                                               a, b, g, b, lds, sh);
+    bwd_body<R, K, LOGR, CONTIG, false, pass_mask<R, K, MS, true>()>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_, a, b, g, b, lds, sh);
 }
 
 // the reverse pass that first undoes the layer diagonal given in a.ld
-template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_ld_pass(const void *phi_in_, void *phi_,
+template <typename R, int K, int LOGR, bool CONTIG, int MS>
+__global__ __launch_bounds__(1 << (K - LOGR), pass_waves<R>(PK_BWD_LD_PASS, MS)) void k_bwd_ld_pass(const void *phi_in_, void *phi_,
                                                                  void *lam_, FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
     const int b = blockIdx.x, g = gridDim.x;
-    constexpr uint32_t L = act_later<R, K>() | kActRuntime;
-    if (a.active == (L & ~kActRuntime))
-        bwd_body<R, K, LOGR, CONTIG, true, L>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_,
-                                              a, b, g, b, lds, sh);
-    else
-        bwd_body<R, K, LOGR, CONTIG, true, 0>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_,
-                                              a, b, g, b, lds, sh);
+    bwd_body<R, K, LOGR, CONTIG, true, pass_mask<R, K, MS, true>()>((const cx<R> *)phi_in_, (cx<R> *)phi_, (cx<R> *)lam_, a, b, g, b, lds, sh);
 }
 
 // Reverse pass that does not write phi back: every RY and RZ partial of the
@@ -918,36 +926,24 @@ __device__ __forceinline__ void bwd_gf_body(const cx<R> *phi_in, cx<R> *lam, con
     write_partials<R, K, LOGR, 0, true>(accY, accZr, ztot, sh, a, a.layer, col);
 }
 
-template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_gf_pass(const void *phi_in_, void *lam_,
+template <typename R, int K, int LOGR, bool CONTIG, int MS>
+__global__ __launch_bounds__(1 << (K - LOGR), pass_waves<R>(PK_BWD_GF_PASS, MS)) void k_bwd_gf_pass(const void *phi_in_, void *lam_,
                                                                  FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
     const int b = blockIdx.x, g = gridDim.x;
-    constexpr uint32_t L = act_later<R, K>() | kActRuntime;
-    if (a.active == (L & ~kActRuntime))
-        bwd_gf_body<R, K, LOGR, CONTIG, false, L>((const cx<R> *)phi_in_, (cx<R> *)lam_,
-                                                  a, b, g, b, lds, sh);
-    else
-        bwd_gf_body<R, K, LOGR, CONTIG, false, 0>((const cx<R> *)phi_in_, (cx<R> *)lam_,
-                                                  a, b, g, b, lds, sh);
+    bwd_gf_body<R, K, LOGR, CONTIG, false, pass_mask<R, K, MS, true>()>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, b, g, b, lds, sh);
 }
 
-template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd_gf_ld_pass(const void *phi_in_,
+template <typename R, int K, int LOGR, bool CONTIG, int MS>
+__global__ __launch_bounds__(1 << (K - LOGR), pass_waves<R>(PK_BWD_GF_LD_PASS, MS)) void k_bwd_gf_ld_pass(const void *phi_in_,
                                                                     void *lam_, FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
     const int b = blockIdx.x, g = gridDim.x;
-    constexpr uint32_t L = act_later<R, K>() | kActRuntime;
-    if (a.active == (L & ~kActRuntime))
-        bwd_gf_body<R, K, LOGR, CONTIG, true, L>((const cx<R> *)phi_in_, (cx<R> *)lam_,
-                                                 a, b, g, b, lds, sh);
-    else
-        bwd_gf_body<R, K, LOGR, CONTIG, true, 0>((const cx<R> *)phi_in_, (cx<R> *)lam_,
-                                                 a, b, g, b, lds, sh);
+    bwd_gf_body<R, K, LOGR, CONTIG, true, pass_mask<R, K, MS, true>()>((const cx<R> *)phi_in_, (cx<R> *)lam_, a, b, g, b, lds, sh);
 }
 
 // Reverse of a two-layer pass (rotation layers la = a.layer and lb =
@@ -1020,40 +1016,27 @@ __device__ __forceinline__ void bwd2_body(const cx<R> *phi_src, cx<R> *phi, cx<R
     write_partials<R, K, LOGR, T::NA - 1, true>(accYa, accZa, zta, sh, a, a.layer, col);
 }
 
-// SP: phi is carried back too (a.store_phi)
-template <typename R, int K, int LOGR, bool CONTIG, bool SP>
-__device__ __forceinline__ void bwd2_kernel(const void *phi_src_, void *phi_, void *lam_,
-                                            const FusedArgs &a, cx<R> *lds, double *sh)
+template <typename R, int K, int LOGR, bool CONTIG, int MS>
+__global__ __launch_bounds__(1 << (K - LOGR), pass_waves<R>(PK_BWD2_PASS, MS)) void k_bwd2_pass(
+    const void *phi_src_, void *phi_, void *lam_, FusedArgs a)
 {
+    __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
+    __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
     const int b = blockIdx.x, g = gridDim.x;
-    constexpr uint32_t F = act_full<K>(), L = act_later<R, K>();
-    const cx<R> *ps = (const cx<R> *)phi_src_;
-    cx<R> *p = (cx<R> *)phi_, *l = (cx<R> *)lam_;
-    if (a.active == F)
-        bwd2_body<R, K, LOGR, CONTIG, SP, F>(ps, p, l, a, b, g, b, lds, sh);
-    else if (a.active == L)
-        bwd2_body<R, K, LOGR, CONTIG, SP, L>(ps, p, l, a, b, g, b, lds, sh);
-    else
-        bwd2_body<R, K, LOGR, CONTIG, SP, 0>(ps, p, l, a, b, g, b, lds, sh);
+    bwd2_body<R, K, LOGR, CONTIG, false, pass_mask<R, K, MS>()>(
+        (const cx<R> *)phi_src_, (cx<R> *)phi_, (cx<R> *)lam_, a, b, g, b, lds, sh);
 }
 
-template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd2_pass(const void *phi_src_, void *phi_,
-                                                               void *lam_, FusedArgs a)
+// the same, carrying phi back too (a.store_phi)
+template <typename R, int K, int LOGR, bool CONTIG, int MS>
+__global__ __launch_bounds__(1 << (K - LOGR), pass_waves<R>(PK_BWD2_PHI_PASS, MS)) void k_bwd2_phi_pass(
+    const void *phi_src_, void *phi_, void *lam_, FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
-    bwd2_kernel<R, K, LOGR, CONTIG, false>(phi_src_, phi_, lam_, a, lds, sh);
-}
-
-template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_bwd2_phi_pass(const void *phi_src_,
-                                                                   void *phi_, void *lam_,
-                                                                   FusedArgs a)
-{
-    __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
-    __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
-    bwd2_kernel<R, K, LOGR, CONTIG, true>(phi_src_, phi_, lam_, a, lds, sh);
+    const int b = blockIdx.x, g = gridDim.x;
+    bwd2_body<R, K, LOGR, CONTIG, true, pass_mask<R, K, MS>()>(
+        (const cx<R> *)phi_src_, (cx<R> *)phi_, (cx<R> *)lam_, a, b, g, b, lds, sh);
 }
 
 // Last forward pass of the last layer + energy + first reverse pass, for a
@@ -1118,43 +1101,25 @@ __device__ __forceinline__ void turn_body(const cx<R> *psi, cx<R> *lam, const Fu
     }
 }
 
-template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_pass(const void *psi_, void *lam_,
+template <typename R, int K, int LOGR, bool CONTIG, int MS>
+__global__ __launch_bounds__(1 << (K - LOGR), pass_waves<R>(PK_TURN_PASS, MS)) void k_turn_pass(const void *psi_, void *lam_,
                                                                FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
     const int b = blockIdx.x, g = gridDim.x;
-    constexpr uint32_t F = act_full<K>(), L = act_later<R, K>();
-    if (a.active == F)
-        turn_body<R, K, LOGR, CONTIG, false, F>((const cx<R> *)psi_, (cx<R> *)lam_,
-                                                a, b, g, b, lds, sh);
-    else if (a.active == L)
-        turn_body<R, K, LOGR, CONTIG, false, L>((const cx<R> *)psi_, (cx<R> *)lam_,
-                                                a, b, g, b, lds, sh);
-    else
-        turn_body<R, K, LOGR, CONTIG, false, 0>((const cx<R> *)psi_, (cx<R> *)lam_,
-                                                a, b, g, b, lds, sh);
+    turn_body<R, K, LOGR, CONTIG, false, pass_mask<R, K, MS>()>((const cx<R> *)psi_, (cx<R> *)lam_, a, b, g, b, lds, sh);
 }
 
 // the same for a plain load (the layer's last pass is not its only one)
-template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_turn_load_pass(const void *psi_, void *lam_,
+template <typename R, int K, int LOGR, bool CONTIG, int MS>
+__global__ __launch_bounds__(1 << (K - LOGR), pass_waves<R>(PK_TURN_LOAD_PASS, MS)) void k_turn_load_pass(const void *psi_, void *lam_,
                                                                     FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
     const int b = blockIdx.x, g = gridDim.x;
-    constexpr uint32_t F = act_full<K>(), L = act_later<R, K>();
-    if (a.active == F)
-        turn_body<R, K, LOGR, CONTIG, true, F>((const cx<R> *)psi_, (cx<R> *)lam_,
-                                               a, b, g, b, lds, sh);
-    else if (a.active == L)
-        turn_body<R, K, LOGR, CONTIG, true, L>((const cx<R> *)psi_, (cx<R> *)lam_,
-                                               a, b, g, b, lds, sh);
-    else
-        turn_body<R, K, LOGR, CONTIG, true, 0>((const cx<R> *)psi_, (cx<R> *)lam_,
-                                               a, b, g, b, lds, sh);
+    turn_body<R, K, LOGR, CONTIG, true, pass_mask<R, K, MS>()>((const cx<R> *)psi_, (cx<R> *)lam_, a, b, g, b, lds, sh);
 }
 
 // ------------------------------------------------------ two-layer passes
@@ -1196,34 +1161,22 @@ __device__ __forceinline__ void fwd2_body(cx<R> *psi, const cx<R> *src, const Fu
     }
 }
 
-template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd2_pass(void *psi_, const void *src_,
+template <typename R, int K, int LOGR, bool CONTIG, int MS>
+__global__ __launch_bounds__(1 << (K - LOGR), pass_waves<R>(PK_FWD2_PASS, MS)) void k_fwd2_pass(void *psi_, const void *src_,
                                                                FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     const int b = blockIdx.x, g = gridDim.x;
-    constexpr uint32_t F = act_full<K>(), L = act_later<R, K>();
-    if (a.active == F)
-        fwd2_body<R, K, LOGR, CONTIG, false, F>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
-    else if (a.active == L)
-        fwd2_body<R, K, LOGR, CONTIG, false, L>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
-    else
-        fwd2_body<R, K, LOGR, CONTIG, false, 0>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
+    fwd2_body<R, K, LOGR, CONTIG, false, pass_mask<R, K, MS>()>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
 }
 
-template <typename R, int K, int LOGR, bool CONTIG>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_fwd2_load_pass(void *psi_, const void *src_,
+template <typename R, int K, int LOGR, bool CONTIG, int MS>
+__global__ __launch_bounds__(1 << (K - LOGR), pass_waves<R>(PK_FWD2_LOAD_PASS, MS)) void k_fwd2_load_pass(void *psi_, const void *src_,
                                                                     FusedArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     const int b = blockIdx.x, g = gridDim.x;
-    constexpr uint32_t F = act_full<K>(), L = act_later<R, K>();
-    if (a.active == F)
-        fwd2_body<R, K, LOGR, CONTIG, true, F>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
-    else if (a.active == L)
-        fwd2_body<R, K, LOGR, CONTIG, true, L>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
-    else
-        fwd2_body<R, K, LOGR, CONTIG, true, 0>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
+    fwd2_body<R, K, LOGR, CONTIG, true, pass_mask<R, K, MS>()>((cx<R> *)psi_, (const cx<R> *)src_, a, b, g, lds);
 }
 
 // ------------------------------------------------ first-layer gradients
@@ -1798,34 +1751,51 @@ inline int elem_grid(u64 dim)
     return (int)(b < 8192 ? b : 8192);
 }
 
-#define GV_LAUNCH_K(KERNEL, PREC, GRID, K, ...)                                                   \
+#define GV_LAUNCH_KS(KERNEL, MS, PREC, GRID, K, ...)                                                   \
     do {                                                                                          \
         switch (K) {                                                                              \
         case 12:                                                                                  \
             if (PREC == GV_C64)                                                                   \
-                hipLaunchKernelGGL((KERNEL<float, 12, 4, true>), dim3(GRID), dim3(256), 0, s,     \
+                hipLaunchKernelGGL((KERNEL<float, 12, 4, true, MS>), dim3(GRID), dim3(256), 0, s,     \
                                    __VA_ARGS__);                                                  \
             else                                                                                  \
-                hipLaunchKernelGGL((KERNEL<double, 12, 4, true>), dim3(GRID), dim3(256), 0, s,    \
+                hipLaunchKernelGGL((KERNEL<double, 12, 4, true, MS>), dim3(GRID), dim3(256), 0, s,    \
                                    __VA_ARGS__);                                                  \
             break;                                                                                \
         case 10:                                                                                  \
             if (PREC == GV_C64)                                                                   \
-                hipLaunchKernelGGL((KERNEL<float, 10, 4, true>), dim3(GRID), dim3(64), 0, s,  \
+                hipLaunchKernelGGL((KERNEL<float, 10, 4, true, MS>), dim3(GRID), dim3(64), 0, s,  \
                                    __VA_ARGS__);                                                  \
             else                                                                                  \
-                hipLaunchKernelGGL((KERNEL<double, 10, 4, true>), dim3(GRID), dim3(64), 0, s, \
+                hipLaunchKernelGGL((KERNEL<double, 10, 4, true, MS>), dim3(GRID), dim3(64), 0, s, \
                                    __VA_ARGS__);                                                  \
             break;                                                                                \
         case 8:                                                                                   \
             if (PREC == GV_C64)                                                                   \
-                hipLaunchKernelGGL((KERNEL<float, 8, 3, false>), dim3(GRID), dim3(32), 0, s,  \
+                hipLaunchKernelGGL((KERNEL<float, 8, 3, false, MS>), dim3(GRID), dim3(32), 0, s,  \
                                    __VA_ARGS__);                                                  \
             else                                                                                  \
-                hipLaunchKernelGGL((KERNEL<double, 8, 3, false>), dim3(GRID), dim3(32), 0, s, \
+                hipLaunchKernelGGL((KERNEL<double, 8, 3, false, MS>), dim3(GRID), dim3(32), 0, s, \
                                    __VA_ARGS__);                                                  \
             break;                                                                                \
         default: return hipErrorInvalidValue;                                                     \
+        }                                                                                         \
+    } while (0)
+
+// the selector of a pass's active mask (the kernels' pass_mask, on the host)
+static int mask_sel(int prec, int K, uint32_t active)
+{
+    const uint32_t full = (1u << K) - 1u;
+    const uint32_t later = full & ~((1u << (prec == GV_C64 ? 4 : 3)) - 1u);
+    return active == full ? MS_FULL : (active == later ? MS_LATER : MS_ANY);
+}
+
+#define GV_LAUNCH_KM(KERNEL, PREC, GRID, K, ACTIVE, ...)                                          \
+    do {                                                                                          \
+        switch (mask_sel(PREC, K, ACTIVE)) {                                                      \
+        case MS_FULL: GV_LAUNCH_KS(KERNEL, MS_FULL, PREC, GRID, K, __VA_ARGS__); break;           \
+        case MS_LATER: GV_LAUNCH_KS(KERNEL, MS_LATER, PREC, GRID, K, __VA_ARGS__); break;         \
+        default: GV_LAUNCH_KS(KERNEL, MS_ANY, PREC, GRID, K, __VA_ARGS__); break;                 \
         }                                                                                         \
     } while (0)
 
@@ -2175,8 +2145,8 @@ hipError_t fused_forward_pass(int prec, void *psi, const gv_ansatz &an, const Ti
     if (in_mode == IN_LOAD_DIAG) a.dt = layer_tab(an, ch, t, layer - 1);
     if (in_mode == IN_GENERATE) a.dt = make_diagtab(an, ch, t.gtab, 0 < an.layers);
     const int grid = fused_grid(prec, plan, an.n);
-    if (in_mode == IN_LOAD) GV_LAUNCH_K(k_fwd_load_pass, prec, grid, plan.K, psi, src, a);
-    else GV_LAUNCH_K(k_fwd_pass, prec, grid, plan.K, psi, src, a);
+    if (in_mode == IN_LOAD) GV_LAUNCH_KM(k_fwd_load_pass, prec, grid, plan.K, a.active, psi, src, a);
+    else GV_LAUNCH_KM(k_fwd_pass, prec, grid, plan.K, a.active, psi, src, a);
     return hipGetLastError();
 }
 
@@ -2201,12 +2171,12 @@ hipError_t fused_backward_pass(int prec, const void *phi_in, void *phi, void *la
     a.grid = grid;
     if (ld_load) a.ld = *ld_load;
     if (fl.grad_first) {
-        if (ld_load) GV_LAUNCH_K(k_bwd_gf_ld_pass, prec, grid, plan.K, phi_in, lam, a);
-        else GV_LAUNCH_K(k_bwd_gf_pass, prec, grid, plan.K, phi_in, lam, a);
+        if (ld_load) GV_LAUNCH_KM(k_bwd_gf_ld_pass, prec, grid, plan.K, a.active, phi_in, lam, a);
+        else GV_LAUNCH_KM(k_bwd_gf_pass, prec, grid, plan.K, a.active, phi_in, lam, a);
     } else if (ld_load) {
-        GV_LAUNCH_K(k_bwd_ld_pass, prec, grid, plan.K, phi_in, phi, lam, a);
+        GV_LAUNCH_KM(k_bwd_ld_pass, prec, grid, plan.K, a.active, phi_in, phi, lam, a);
     } else {
-        GV_LAUNCH_K(k_bwd_pass, prec, grid, plan.K, phi_in, phi, lam, a);
+        GV_LAUNCH_KM(k_bwd_pass, prec, grid, plan.K, a.active, phi_in, phi, lam, a);
     }
     return hipGetLastError();
 }
@@ -2222,8 +2192,8 @@ hipError_t fused_backward2_pass(int prec, const void *phi_src, void *phi, void *
     a.store_phi = store_phi;
     a.part = part;
     a.grid = grid;
-    if (store_phi) GV_LAUNCH_K(k_bwd2_phi_pass, prec, grid, plan.K, phi_src, phi, lam, a);
-    else GV_LAUNCH_K(k_bwd2_pass, prec, grid, plan.K, phi_src, phi, lam, a);
+    if (store_phi) GV_LAUNCH_KM(k_bwd2_phi_pass, prec, grid, plan.K, a.active, phi_src, phi, lam, a);
+    else GV_LAUNCH_KM(k_bwd2_pass, prec, grid, plan.K, a.active, phi_src, phi, lam, a);
     return hipGetLastError();
 }
 
@@ -2371,8 +2341,8 @@ hipError_t fused_forward2_pass(int prec, void *psi, const gv_ansatz &an, const T
     if (in_mode == IN_LOAD_DIAG) a.dt = layer_tab(an, ch, t, layer - 1);
     if (in_mode == IN_GENERATE) a.dt = make_diagtab(an, ch, t.gtab, 0 < an.layers);
     const int grid = fused_grid(prec, plan, an.n);
-    if (in_mode == IN_LOAD) GV_LAUNCH_K(k_fwd2_load_pass, prec, grid, plan.K, psi, src, a);
-    else GV_LAUNCH_K(k_fwd2_pass, prec, grid, plan.K, psi, src, a);
+    if (in_mode == IN_LOAD) GV_LAUNCH_KM(k_fwd2_load_pass, prec, grid, plan.K, a.active, psi, src, a);
+    else GV_LAUNCH_KM(k_fwd2_pass, prec, grid, plan.K, a.active, psi, src, a);
     return hipGetLastError();
 }
 
@@ -2390,8 +2360,8 @@ hipError_t fused_turnaround(int prec, const void *psi, void *lam, const double *
     a.part = part;
     a.epart = epart;
     a.grid = grid;
-    if (in_mode == IN_LOAD) GV_LAUNCH_K(k_turn_load_pass, prec, grid, plan.K, psi, lam, a);
-    else GV_LAUNCH_K(k_turn_pass, prec, grid, plan.K, psi, lam, a);
+    if (in_mode == IN_LOAD) GV_LAUNCH_KM(k_turn_load_pass, prec, grid, plan.K, a.active, psi, lam, a);
+    else GV_LAUNCH_KM(k_turn_pass, prec, grid, plan.K, a.active, psi, lam, a);
     return hipGetLastError();
 }
 
