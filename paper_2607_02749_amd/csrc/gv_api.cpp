@@ -929,17 +929,38 @@ static void build_cover(gv_pauli_s *h, int K, int C, int logr)
                 return std::make_pair(imag, h->oz[k] & regmask);
             };
             std::stable_sort(ks.begin(), ks.end(), [&](int64_t a, int64_t b) { return key(a) < key(b); });
+            cl.ti = cl.t0 + (int32_t)ks.size();
+            uint32_t flat_off = 0;   // sides with a register sign
             for (size_t i = 0; i < ks.size(); ++i) {
                 const int64_t k = ks[i];
+                const uint64_t z = h->oz[k];
+                const int ph = __builtin_popcountll(x & z) & 3;
+                if ((ph & 1) && cl.ti == cl.t0 + (int32_t)ks.size())
+                    cl.ti = (int32_t)h->class_terms.size();
                 OffTerm tm;
-                tm.z = h->oz[k];
-                tm.c = h->oc[k];
-                tm.ph = __builtin_popcountll(h->ox[k] & h->oz[k]) & 3;
-                tm.pad = (i + 1 == ks.size() || key(ks[i + 1]) != key(k)) ? kOffGroupEnd : 0;
+                tm.z = z;
+                // i^ph = +-1 or +-i; the -1 of ph & 2 and of the parity of
+                // x & z (the flipped bits' share of (i ^ x) & z) go into cf
+                const bool neg = ((ph >> 1) & 1) ^ (__builtin_popcountll(x & z) & 1);
+                tm.cf = neg ? -h->oc[k] : h->oc[k];
+                tm.tz = 0;
+                for (int j = 0; j < K - logr; ++j)
+                    if ((z >> op.pos[j]) & 1) tm.tz |= 1u << j;
+                tm.sig = 0;
+                for (int r = 0; r < (1 << logr); ++r) {
+                    int par = 0;
+                    for (int b = 0; b < logr; ++b)
+                        if ((r >> b) & 1) par ^= (int)((z >> op.pos[K - logr + b]) & 1);
+                    tm.sig |= (uint32_t)par << r;
+                }
+                if (i + 1 == ks.size() || key(ks[i + 1]) != key(k)) tm.sig |= kOffGroupEnd;
+                tm.cf32 = (float)tm.cf;
+                tm.pad = 0;
+                if (tm.sig & 0xffffu) flat_off |= (ph & 1) ? kOffImFlat : kOffReFlat;
                 h->class_terms.push_back(tm);
             }
             cl.t1 = (int32_t)h->class_terms.size();
-            cl.pad = 0;
+            cl.xu |= (kOffReFlat | kOffImFlat) & ~flat_off;
             h->classes.push_back(cl);
         }
         op.c1 = (int)h->classes.size();

@@ -1360,67 +1360,73 @@ struct OffArgs {
     int estride;
 };
 
-// A term of a cover pass as the inner loop uses it: z, its coefficient
-// with the fixed signs folded in (c, times -1 for ph & 2 and for the parity
-// of x & z), and per register r the sign of the register bits' share of
-// (i ^ x) & z (bit r of `regsign`) plus the real / imaginary choice (ph odd)
-// and whether it ends a group of terms with the same register signs and
-// phase parity (the host orders a class's terms that way).
-struct OffStaged {
-    u64 z;
-    double cf;
-    uint32_t regsign_imag;   // bits 0..15: register signs; bit 30: group end;
-                             // bit 31: i^ph is imaginary
-    uint32_t pad;
-};
-constexpr int kOffStage = kOffPassTerms;  // terms staged in LDS per pass (the rest read in place)
+// The pass's classes and terms are read through the scalar unit's cache:
+// every lane reads the same entry (constant address space, read only).
+typedef __attribute__((address_space(4))) const OffTerm ScalarTerm;
+typedef __attribute__((address_space(4))) const OffClass ScalarClass;
 
-template <int LOGR>
-__device__ __forceinline__ OffStaged stage_term(const OffTerm &tm, u64 x,
-                                                const RegMap<LOGR, false> &m)
+__device__ __forceinline__ float term_cf(ScalarTerm &q, float) { return q.cf32; }
+__device__ __forceinline__ double term_cf(ScalarTerm &q, double) { return q.cf; }
+
+// Signed sum over terms [k0, k1) of a class for this thread: the tile
+// base's share of each term's sign on the scalar unit, the thread's through
+// tz.
+template <typename R>
+__device__ __forceinline__ R off_term(ScalarTerm &q, u64 base, uint32_t tid)
 {
-    constexpr int NR = 1 << LOGR;
-    uint32_t pat = 0;
-    for (int r = 0; r < NR; ++r)
-        if (__popcll(m.off(r) & tm.z) & 1) pat |= 1u << r;
-    double cf = tm.c;
-    if ((tm.ph & 2) ^ ((__popcll(x & tm.z) & 1) << 1)) cf = -cf;
-    return OffStaged{tm.z, cf,
-                     pat | ((uint32_t)(tm.pad & kOffGroupEnd) << 30) |
-                         ((uint32_t)(tm.ph & 1) << 31),
-                     0u};
+    R cf = term_cf(q, R(0));
+    if (__popcll(base & q.z) & 1) cf = -cf;
+    return (__popc(tid & q.tz) & 1) ? -cf : cf;
+}
+template <typename R>
+__device__ __forceinline__ R off_sum(ScalarTerm *q, int k0, int k1, u64 base, uint32_t tid)
+{
+    R w = 0;
+    for (int k = k0; k < k1; ++k) w += off_term<R>(q[k], base, tid);
+    return w;
+}
+// The same per group (its terms share their register signs; every class
+// side ends with a group end), each group's sum spread over X once.
+template <typename R, int NR>
+__device__ __forceinline__ void off_groups(R (&X)[NR], ScalarTerm *q, int k0, int k1, u64 base,
+                                           uint32_t tid)
+{
+    for (int k = k0; k < k1;) {
+        R w = 0;
+        uint32_t sig;
+        do {
+            w += off_term<R>(q[k], base, tid);
+            sig = q[k].sig;
+            ++k;
+        } while (!(sig & kOffGroupEnd));
+#pragma unroll
+        for (int r = 0; r < NR; ++r) X[r] += ((sig >> r) & 1) ? -w : w;
+    }
 }
 
 // One cover pass: the psi tile sits in LDS, so for every class (flip mask x
 // inside the tile) each amplitude reads its partner psi_{i^x} there and adds
 // F(i^x) psi_{i^x} to lam_i, where F(i^x) = sum_k c_k i^{ph_k}
-// (-1)^{popcount((i^x) & z_k)}.  The parity splits over the index bits:
-// x & z (fixed per term), the tile base and the thread's bits (once per
-// tile and thread), and the register bits (a fixed sign pattern over the
-// registers), so each term costs one select and one add per amplitude.
-// The pass's share of <psi|H|psi> goes to FP64 partials.
+// (-1)^{popcount((i^x) & z_k)}: the real part from the class's real terms,
+// the imaginary part from the others (a side without terms skips its
+// products, a side without register signs uses one factor for all of the
+// thread's registers).  The pass's share of <psi|H|psi> goes to FP64
+// partials.
 template <typename R, int K, int LOGR>
 __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const OffArgs &a, u64 t0,
-                                         u64 tstep, int col, cx<R> *lds, double *sh,
-                                         OffStaged *stg)
+                                         u64 tstep, int col, cx<R> *lds, double *sh)
 {
     using T = Tile<K, LOGR>;
     const int t = threadIdx.x;
     constexpr int LD = T::lo(0);
+    constexpr int STRIDE = T::lds_stride(LD);
+    static_assert(T::lds_linear(LD), "load layout");
     const u64 toff = thread_off<K, LOGR>(t, LD, a);
     RegMap<LOGR, false> m;
     m.init(a.pos + LD);
-    // stage the pass's terms (classes c0 .. c1-1 own terms k0 .. k1-1)
-    const int k0 = a.cls[a.c0].t0, k1 = a.cls[a.c1 - 1].t1;
-    const int nst = min(k1 - k0, kOffStage);
-    for (int c = a.c0; c < a.c1; ++c) {
-        const OffClass C = a.cls[c];
-        for (int k = C.t0 + t; k < C.t1; k += blockDim.x) {
-            if (k - k0 >= nst) break;
-            stg[k - k0] = stage_term<LOGR>(a.terms[k], C.x, m);
-        }
-    }
-    __syncthreads();
+    ScalarTerm *q = (ScalarTerm *)a.terms;
+    ScalarClass *cls = (ScalarClass *)a.cls;
+    constexpr uint32_t TMASK = (1u << LD) - 1u;   // tile bits held by the thread id
     double er = 0.0, ei = 0.0;
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
@@ -1431,39 +1437,63 @@ __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const Off
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
             v[r] = ld_amp(pt + m.off(r));
-            lds[T::pad(T::u_of(t, r, LD))] = v[r];
+            lds[T::lds_index(t, r, LD)] = v[r];
             acc[r].re = acc[r].im = R(0);
         }
         __syncthreads();
         for (int c = a.c0; c < a.c1; ++c) {
-            const OffClass C = a.cls[c];
-            R A[T::NR], B[T::NR];
+            const uint32_t xu = cls[c].xu;
+            const int c_t0 = cls[c].t0, c_ti = cls[c].ti, c_t1 = cls[c].t1;
+            // partners: thread t ^ xl, register r ^ xh
+            const uint32_t xl = xu & TMASK, xh = (xu & 0xffffu) >> LD;
+            const int tp = t ^ (int)xl;
+            const int pbase = T::pad(tp);
+            cx<R> pv[T::NR];
+            if (xh == 0) {
 #pragma unroll
-            for (int r = 0; r < T::NR; ++r) A[r] = B[r] = R(0);
-
-            // a group's terms share their register signs: sum their signed
-            // coefficients for this thread, then spread the sum over the
-            // registers once (the group-end flag is the same in every lane)
-            R w = 0;
-            for (int k = C.t0; k < C.t1; ++k) {
-                const OffStaged q = k - k0 < nst ? stg[k - k0]
-                                                 : stage_term<LOGR>(a.terms[k], C.x, m);
-                w += (__popcll(bt & q.z) & 1) ? -(R)q.cf : (R)q.cf;
-                if (!((q.regsign_imag >> 30) & 1)) continue;
-                if (q.regsign_imag >> 31) {
+                for (int r = 0; r < T::NR; ++r) pv[r] = lds[pbase + r * STRIDE];
+            } else {
 #pragma unroll
-                    for (int r = 0; r < T::NR; ++r) B[r] += ((q.regsign_imag >> r) & 1) ? -w : w;
+                for (int r = 0; r < T::NR; ++r) pv[r] = lds[pbase + (r ^ (int)xh) * STRIDE];
+            }
+            R A[T::NR];
+            if (c_ti > c_t0) {
+                if (xu & kOffReFlat) {
+                    const R w = off_sum<R>(q, c_t0, c_ti, base, (uint32_t)t);
+#pragma unroll
+                    for (int r = 0; r < T::NR; ++r) {
+                        acc[r].re += w * pv[r].re;
+                        acc[r].im += w * pv[r].im;
+                    }
                 } else {
 #pragma unroll
-                    for (int r = 0; r < T::NR; ++r) A[r] += ((q.regsign_imag >> r) & 1) ? -w : w;
-                }
-                w = 0;
-            }
+                    for (int r = 0; r < T::NR; ++r) A[r] = R(0);
+                    off_groups<R, T::NR>(A, q, c_t0, c_ti, base, (uint32_t)t);
 #pragma unroll
-            for (int r = 0; r < T::NR; ++r) {
-                const cx<R> pv = lds[T::pad(T::u_of(t, r, LD) ^ (int)C.xu)];
-                acc[r].re += A[r] * pv.re - B[r] * pv.im;
-                acc[r].im += A[r] * pv.im + B[r] * pv.re;
+                    for (int r = 0; r < T::NR; ++r) {
+                        acc[r].re += A[r] * pv[r].re;
+                        acc[r].im += A[r] * pv[r].im;
+                    }
+                }
+            }
+            if (c_t1 > c_ti) {
+                if (xu & kOffImFlat) {
+                    const R w = off_sum<R>(q, c_ti, c_t1, base, (uint32_t)t);
+#pragma unroll
+                    for (int r = 0; r < T::NR; ++r) {
+                        acc[r].re -= w * pv[r].im;
+                        acc[r].im += w * pv[r].re;
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < T::NR; ++r) A[r] = R(0);
+                    off_groups<R, T::NR>(A, q, c_ti, c_t1, base, (uint32_t)t);
+#pragma unroll
+                    for (int r = 0; r < T::NR; ++r) {
+                        acc[r].re -= A[r] * pv[r].im;
+                        acc[r].im += A[r] * pv[r].re;
+                    }
+                }
             }
         }
         cx<R> *lt = lam ? lam + fresh(bt) : nullptr;
@@ -1494,9 +1524,8 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_offdiag_pass(const void *ps
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
-    __shared__ OffStaged stg[kOffStage];
     off_body<R, K, LOGR>((const cx<R> *)psi_, (cx<R> *)lam_, a, blockIdx.x, gridDim.x, blockIdx.x,
-                         lds, sh, stg);
+                         lds, sh);
 }
 
 // ------------------------------------------------------------ table kernels
@@ -1898,7 +1927,7 @@ __device__ __forceinline__ DiagTab batch_layer_tab(const BatchInst &I, int layer
 }
 
 template <typename R>
-__device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh, OffStaged *stg)
+__device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh)
 {
     constexpr int K = 12, LOGR = 4;
     const int t = threadIdx.x, nt = blockDim.x;
@@ -1965,7 +1994,7 @@ __device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh, OffSt
         o.terms = I.terms;
         o.epart = I.energy;
         o.estride = 1;
-        off_body<R, K, LOGR>(psi, eonly ? nullptr : lam, o, 0, 1, 0, lds, sh, stg);
+        off_body<R, K, LOGR>(psi, eonly ? nullptr : lam, o, 0, 1, 0, lds, sh);
         __syncthreads();
     }
     if (eonly) {
@@ -2000,7 +2029,6 @@ __global__ __launch_bounds__(256) void k_batch(const BatchInst *insts, const int
 {
     __shared__ cx<R> lds[Tile<12, 4>::LDS];
     __shared__ double sh[8];
-    __shared__ OffStaged stg[kOffStage];
     __shared__ int next;
     for (;;) {
         if (threadIdx.x == 0) next = (int)atomicAdd(counter, 1u);
@@ -2008,7 +2036,7 @@ __global__ __launch_bounds__(256) void k_batch(const BatchInst *insts, const int
         const int idx = next;
         __syncthreads();
         if (idx >= count) break;   // every block leaves once the queue is empty
-        batch_instance<R>(insts[order[idx]], lds, sh, stg);
+        batch_instance<R>(insts[order[idx]], lds, sh);
     }
 }
 

@@ -31,20 +31,35 @@ struct QwcGroup {
 
 // Off-diagonal terms that flip the same index bits x form a class: on the
 // amplitude pair (i, i ^ x) their sum acts as one complex factor
-// F(i ^ x) = sum_k c_k i^{ph_k} (-1)^{popcount((i ^ x) & z_k)}.
+// F(i ^ x) = sum_k c_k i^{ph_k} (-1)^{popcount((i ^ x) & z_k)}.  A class's
+// terms with a real i^{ph} come first ([t0, ti)), the imaginary ones after
+// ([ti, t1)).
 struct OffClass {
     u64 x;          // flip mask
     uint32_t xu;    // the same mask in the tile-local bits of its cover pass
+                    // (bits 0..15), plus kOffReFlat / kOffImFlat
     int32_t t0, t1; // its terms [t0, t1) in the term table
-    int32_t pad;
+    int32_t ti;     // first term with an imaginary i^{ph}
 };
+// the class's real (imaginary) terms carry no register signs: their sum is
+// the same for all of a thread's registers
+constexpr uint32_t kOffReFlat = 1u << 16;
+constexpr uint32_t kOffImFlat = 1u << 17;
+// A term as the cover pass's kernel applies it (everything that depends
+// only on the pass's tile layout is folded in on the host): the sign of
+// term k at amplitude i ^ x is cf times (-1) to the parities of z & the
+// tile base, tz & the thread id (the thread bits of the load layout) and
+// the register bits (sig bit r for register r).
 struct OffTerm {
     u64 z;
-    double c;
-    int32_t ph;     // popcount(x & z) mod 4: the i^ph factor of P(x, z)
-    int32_t pad;    // kOffGroupEnd: last term of its (phase parity, register-bit z) group
+    double cf;      // c_k times -1 for ph & 2 and for the parity of x & z
+    float cf32;     // the same in single precision
+    uint32_t tz;    // z on the load layout's thread bits, as thread-id bits
+    uint32_t sig;   // bits 0..15: register signs; kOffGroupEnd: last term of
+                    // its group (same register signs and phase parity)
+    uint32_t pad;
 };
-constexpr int32_t kOffGroupEnd = 1;
+constexpr uint32_t kOffGroupEnd = 1u << 30;
 constexpr int kOffPassTerms = 512;   // terms one cover pass stages in LDS
 // A cover pass: a tile whose bits hold every flip bit of its classes.
 struct OffPass {
