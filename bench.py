@@ -419,9 +419,9 @@ def bench_batch(args, torch, gv, synth):
         th = torch.tensor(inst.theta, dtype=torch.float64, device=dev)
         items.append((an, th, gv.PauliSum(inst.n, inst.x, inst.z, inst.c), inst.cluster_mask))
     tune = autotune.tune_batch(items, "c64")
-    log("tuned", {k: tune[k] for k in ("blocks_per_cu", "order", "split_n", "ms", "cached")})
+    log("tuned", {k: tune[k] for k in ("blocks_per_cu", "order", "split_n", "lds_n", "ms", "cached")})
     b = gv.Batch(items, "c64", blocks_per_cu=tune["blocks_per_cu"], order=tune["order"],
-                 split_n=tune["split_n"], graph=True)
+                 split_n=tune["split_n"], lds_n=tune["lds_n"], graph=True)
     for _ in range(args.warmup):
         b.run()
     wall, ev = time_steps(b.run, args.steps, torch)
@@ -460,7 +460,7 @@ def bench_batch(args, torch, gv, synth):
         "config": {"workload": "batch256_n12-20_L3-5", "instances": len(insts),
                    "n_range": [min(x.n for x in insts), max(x.n for x in insts)],
                    "graph": True,
-                   "tuning": {k: tune[k] for k in ("blocks_per_cu", "order", "split_n")},
+                   "tuning": {k: tune[k] for k in ("blocks_per_cu", "order", "split_n", "lds_n")},
                    "tuning_sweep_ms": tune.get("timings"),
                    "event_ms_per_step": ms},
         "roofline": {"bound": "hbm", "kernel": "k_batch<float>", "achieved": achieved,

@@ -245,6 +245,12 @@ typedef struct {
     int32_t order;             /* 0: largest instance first (default), 1: input order */
     int32_t split_n;           /* n from which instances run as whole-GPU passes;
                                   0: default (17), > 30: never */
+    int32_t lds_n;             /* instances with n <= lds_n keep psi and lam in the
+                                  workgroup's LDS for the whole evaluation (own
+                                  persistent kernel, one block per compute unit):
+                                  complex64 only, at most 12 (the two 32 KB vectors
+                                  and the 34 KB tile exchange buffer fill most of
+                                  the 160 KB); 0: default (12), -1: never */
 } gv_batch_tuning;
 
 typedef struct gv_batch_s *gv_batch;

@@ -1,10 +1,15 @@
 """Autotuner for the batched path.
 
-The batch has three launch choices (``gv_batch_tuning`` in the C ABI): how
+The batch has four launch choices (``gv_batch_tuning`` in the C ABI): how
 many workgroups the persistent kernel keeps resident per compute unit, the
 order in which its atomic queue hands out instances (largest first, or input
-order), and the instance size from which instances leave the persistent
-kernel and run as whole-GPU tile passes on side streams.  ``tune_batch``
+order), and two size-class splits: the instance size up to which instances
+keep their state and adjoint in one workgroup's LDS (their own persistent
+kernel, one workgroup per compute unit), and the size from which instances
+leave the persistent kernel and run as whole-GPU tile passes on side
+streams.  (The tile shape itself, 12 tile qubits with 16 amplitudes per
+lane, is fixed per prepared Hamiltonian: its off-diagonal cover and term
+encoding are built for it.)  ``tune_batch``
 times every candidate on the real batch with HIP events on the launching
 stream and keeps the fastest; the result is cached in
 a JSON file keyed by GPU architecture, precision and the batch's size class,
@@ -23,6 +28,7 @@ from typing import Callable, Dict, Iterable, List, Optional, Sequence, Tuple
 ORDERS = {"largest_first": 0, "input": 1}
 DEFAULT_BLOCKS = (1, 2, 4, 8)
 DEFAULT_SPLITS = (15, 16, 17, 18, 31)   # 31: never split
+DEFAULT_LDS = (-1, 12)                    # -1: no LDS-resident class
 
 
 def cache_path() -> str:
@@ -67,19 +73,21 @@ def store_cache(key: str, entry: dict, path: Optional[str] = None) -> None:
     os.replace(tmp, path)
 
 
-def sweep(candidates: Iterable[Tuple[int, int, int]],
-          time_ms: Callable[[int, int, int], float]) -> dict:
-    """Time every (blocks_per_cu, order, split_n) candidate with ``time_ms``
-    and return the fastest together with all timings."""
+def sweep(candidates: Iterable[Tuple[int, int, int, int]],
+          time_ms: Callable[[int, int, int, int], float]) -> dict:
+    """Time every (blocks_per_cu, order, split_n, lds_n) candidate with
+    ``time_ms`` and return the fastest together with all timings."""
     timings: List[dict] = []
-    for bpc, order, split in candidates:
-        ms = float(time_ms(bpc, order, split))
-        timings.append({"blocks_per_cu": bpc, "order": order, "split_n": split, "ms": ms})
+    for bpc, order, split, lds in candidates:
+        ms = float(time_ms(bpc, order, split, lds))
+        timings.append({"blocks_per_cu": bpc, "order": order, "split_n": split, "lds_n": lds,
+                        "ms": ms})
     if not timings:
         raise ValueError("no candidates")
     best = min(timings, key=lambda t: t["ms"])
     return {"blocks_per_cu": best["blocks_per_cu"], "order": best["order"],
-            "split_n": best["split_n"], "ms": best["ms"], "timings": timings}
+            "split_n": best["split_n"], "lds_n": best["lds_n"], "ms": best["ms"],
+            "timings": timings}
 
 
 def _arch(device) -> str:
@@ -91,7 +99,7 @@ def _arch(device) -> str:
 def tune_batch(items, precision: str = "c64", blocks: Sequence[int] = DEFAULT_BLOCKS,
                orders: Sequence[int] = (0, 1), reps: int = 3, graph: bool = True,
                use_cache: bool = True, path: Optional[str] = None, device="cuda",
-               splits: Sequence[int] = DEFAULT_SPLITS) -> dict:
+               splits: Sequence[int] = DEFAULT_SPLITS, lds: Sequence[int] = DEFAULT_LDS) -> dict:
     """Best launch choice for this batch (from the cache when it holds the
     batch's size class, else by timing every candidate)."""
     import torch
@@ -106,12 +114,12 @@ def tune_batch(items, precision: str = "c64", blocks: Sequence[int] = DEFAULT_BL
     if use_cache:
         hit = load_cache(path).get(key)
         if (hit and hit.get("blocks_per_cu") in blocks and hit.get("order") in orders
-                and hit.get("split_n") in splits):
+                and hit.get("split_n") in splits and hit.get("lds_n") in lds):
             return dict(hit, key=key, cached=True)
 
-    def time_ms(bpc: int, order: int, split: int) -> float:
+    def time_ms(bpc: int, order: int, split: int, lds_n: int) -> float:
         b = gv.Batch(items, precision, blocks_per_cu=bpc, order=order, graph=graph, device=dev,
-                     split_n=split)
+                     split_n=split, lds_n=lds_n)
         b.run()                                  # warm-up (first launch loads the code object)
         torch.cuda.synchronize(dev)
         best = float("inf")
@@ -126,12 +134,13 @@ def tune_batch(items, precision: str = "c64", blocks: Sequence[int] = DEFAULT_BL
         del b
         return best
 
-    res = sweep([(bpc, o, sp) for sp in splits for bpc in blocks for o in orders], time_ms)
+    res = sweep([(bpc, o, sp, ld) for ld in lds for sp in splits for bpc in blocks for o in orders],
+                time_ms)
     res["key"] = key
     res["cached"] = False
     if use_cache:
-        store_cache(key, {k: res[k] for k in ("blocks_per_cu", "order", "split_n", "ms", "timings")},
-                    path)
+        store_cache(key, {k: res[k] for k in ("blocks_per_cu", "order", "split_n", "lds_n", "ms",
+                                              "timings")}, path)
     return res
 
 
@@ -140,4 +149,4 @@ def tuned_batch(items, precision: str = "c64", graph: bool = True, device="cuda"
     from . import gv
     t = tune_batch(items, precision, graph=graph, device=device, **kw)
     return gv.Batch(items, precision, blocks_per_cu=t["blocks_per_cu"], order=t["order"],
-                    graph=graph, device=device, split_n=t["split_n"])
+                    graph=graph, device=device, split_n=t["split_n"], lds_n=t["lds_n"])

@@ -15,7 +15,8 @@ constexpr int kSideStreams = 8;
 
 struct gv_batch_s {
     int count = 0;
-    int nsmall = 0;                 // instances in the persistent kernel's queue
+    int nsmall = 0;                 // instances in the persistent kernels' queues
+    int nlds = 0;                   // ... of which the first nlds keep their vectors in LDS
     gv_precision prec = GV_C64;
     void *work = nullptr;
     size_t work_bytes = 0;
@@ -23,7 +24,7 @@ struct gv_batch_s {
     gv::BatchInst *dev_insts = nullptr;
     int *dev_order = nullptr;
     unsigned *counter = nullptr;
-    int grid = 0;
+    int grid = 0, grid_lds = 0;
     bool graph = false;
     hipStream_t capture_stream = nullptr;
     hipGraph_t g = nullptr;
@@ -41,7 +42,7 @@ struct gv_batch_s {
     // every instance's Hamiltonian and its prepare generation at creation
     std::vector<std::pair<const gv_pauli_s *, uint64_t>> hgen;
     hipStream_t side[kSideStreams] = {};
-    hipEvent_t fork = nullptr;
+    hipEvent_t fork = nullptr, fork2 = nullptr;
     hipEvent_t join[kSideStreams] = {};
 };
 
@@ -62,6 +63,15 @@ int split_of(const gv_batch_tuning *tu)
 {
     const int s = tu ? tu->split_n : 0;
     return s <= 0 ? 17 : s;
+}
+
+// instances with n <= lds_n keep psi and lam in LDS (complex64, n = 12:
+// 2 x 32 KB beside the tile exchange buffer); 0 = default, < 0 = never
+int lds_n_of(const gv_batch_tuning *tu, gv_precision prec)
+{
+    const int v = tu ? tu->lds_n : 0;
+    if (prec != GV_C64 || v < 0) return 0;
+    return v == 0 ? kBatchK : std::min(v, kBatchK);
 }
 
 gv_status check_instances(int count, const gv_instance *inst, gv_precision prec)
@@ -142,26 +152,38 @@ BatchLayout batch_layout(int count, const gv_instance *inst, gv_precision prec, 
 }
 
 // One evaluation of every instance, enqueued on s: the persistent kernel
-// for the small instances on s, the whole-GPU instances round-robin on the
-// side streams between a fork and a join event (so a HIP-graph capture of s
-// records both branches).
+// for the small instances on s; the LDS-resident instances' kernel and the
+// whole-GPU instances (round-robin) on the side streams, between fork events
+// and a join (so a HIP-graph capture of s records every branch).
 gv_status launch_all(gv_batch b, hipStream_t s)
 {
     hipError_t e = hipSuccess;
-    const bool fork = !b->large.empty() && b->side_streams;
+    const bool fork = b->side_streams && (!b->large.empty() || b->nlds > 0);
     if (fork) {
         e = hipEventRecord(b->fork, s);
-        for (int k = 0; k < kSideStreams && e == hipSuccess; ++k)
+        for (int k = 0; k < kSideStreams - 1 && e == hipSuccess; ++k)
             e = hipStreamWaitEvent(b->side[k], b->fork, 0);
         if (e != hipSuccess) return check_hip(e, "batch fork");
     }
     e = batch_tables(b->prec, b->dev_insts, b->count, s);
-    if (e == hipSuccess && b->nsmall > 0)
-        e = batch_run(b->prec, b->dev_insts, b->dev_order, b->nsmall, b->counter, b->grid, s);
+    if (e == hipSuccess) e = batch_zero(b->counter, s);
+    // the LDS-resident kernel needs the tables and its counter: a second fork
+    hipStream_t sl = s;
+    if (e == hipSuccess && fork) {
+        sl = b->side[kSideStreams - 1];
+        e = hipEventRecord(b->fork2, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(sl, b->fork2, 0);
+    }
+    if (e == hipSuccess && b->nlds > 0)
+        e = batch_run(b->prec, b->dev_insts, b->dev_order, b->nlds, b->counter + 1, b->grid_lds,
+                      true, sl);
+    if (e == hipSuccess && b->nsmall > b->nlds)
+        e = batch_run(b->prec, b->dev_insts, b->dev_order + b->nlds, b->nsmall - b->nlds,
+                      b->counter, b->grid, false, s);
     if (e != hipSuccess) return check_hip(e, "batch launch");
     for (size_t j = 0; j < b->large.size(); ++j) {
         gv_state_s &st = b->states[j];
-        st.stream = fork ? b->side[j % kSideStreams] : s;
+        st.stream = fork ? b->side[j % kSideStreams] : s;   // after the LDS kernel on the last
         const gv_instance &I = b->large[j];
         if (b->large_q[j] == 0) {   // empty block: the energy alone
             if (gv_status r = gv_apply_ansatz(&st, I.params_dev, &I.ansatz)) return r;
@@ -224,10 +246,10 @@ static gv_status batch_create_impl(int32_t count, const gv_instance *inst,
         }
     }
     if (!work || ((uintptr_t)work % kAlign)) return set_error(GV_EINVAL, "work must be 256-byte aligned");
-    gv_batch_tuning tu = {2, 0, 0};
+    gv_batch_tuning tu = {2, 0, 0, 0};
     if (tuning) tu = *tuning;
     if (tu.blocks_per_cu < 1 || tu.blocks_per_cu > 8 || tu.order < 0 || tu.order > 1 ||
-        tu.split_n < 0)
+        tu.split_n < 0 || tu.lds_n < -1 || tu.lds_n > 30)
         return set_error(GV_EINVAL, "tuning out of range");
     const int split = split_of(&tu);
     const BatchLayout L = batch_layout(count, inst, prec, split);
@@ -291,12 +313,23 @@ static gv_status batch_create_impl(int32_t count, const gv_instance *inst,
         }
         cost[i] = (double)(1ull << a.n) * (double)(b.rot * b.np * 3 + b.noff);
     }
-    std::vector<int> order, large;
-    for (int i = 0; i < count; ++i) (inst[i].ansatz.n >= split ? large : order).push_back(i);
-    if (tu.order == 0) {
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-        std::stable_sort(large.begin(), large.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    // three classes: LDS-resident, the persistent kernel's, whole-GPU
+    const int lds_n = lds_n_of(&tu, prec);
+    std::vector<int> order, order_lds, large;
+    for (int i = 0; i < count; ++i) {
+        const int n = inst[i].ansatz.n;
+        if (n >= split) large.push_back(i);
+        else if (n <= lds_n) order_lds.push_back(i);
+        else order.push_back(i);
     }
+    if (tu.order == 0) {
+        auto by_cost = [&](int x, int y) { return cost[x] > cost[y]; };
+        std::stable_sort(order.begin(), order.end(), by_cost);
+        std::stable_sort(order_lds.begin(), order_lds.end(), by_cost);
+        std::stable_sort(large.begin(), large.end(), by_cost);
+    }
+    const int nlds = (int)order_lds.size();
+    order.insert(order.begin(), order_lds.begin(), order_lds.end());
 
     gv_batch b = new (std::nothrow) gv_batch_s;
     if (!b) return set_error(GV_EINVAL, "out of host memory");
@@ -316,7 +349,9 @@ static gv_status batch_create_impl(int32_t count, const gv_instance *inst,
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
-    b->grid = std::max(1, std::min(b->nsmall, tu.blocks_per_cu * cus));
+    b->nlds = nlds;
+    b->grid = std::max(1, std::min(b->nsmall - nlds, tu.blocks_per_cu * cus));
+    b->grid_lds = std::max(1, std::min(nlds, cus));   // one 99 KB block per CU
 
     hipError_t e = hipSuccess;
     for (int i : large) {
@@ -343,12 +378,13 @@ static gv_status batch_create_impl(int32_t count, const gv_instance *inst,
         b->states.push_back(st);
         b->masks.push_back(dm);
     }
-    if (!large.empty() && side_streams) {
+    if ((!large.empty() || nlds > 0) && side_streams) {
         for (int k = 0; k < kSideStreams && e == hipSuccess; ++k) {
             e = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming);
         }
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork2, hipEventDisableTiming);
     }
     if (e == hipSuccess && count > 0) {
         // stream-ordered behind whatever the caller still runs on the work
@@ -417,6 +453,7 @@ gv_status gv_batch_destroy(gv_batch b)
         if (b->join[k]) (void)hipEventDestroy(b->join[k]);
     }
     if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->fork2) (void)hipEventDestroy(b->fork2);
     delete b;
     return GV_OK;
 }

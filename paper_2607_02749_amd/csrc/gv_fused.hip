@@ -1895,9 +1895,10 @@ __global__ void k_batch_tables(const BatchInst *insts)
     }
 }
 
+// the batch's two queue counters (a fill kernel: capturable in a HIP graph)
 __global__ void k_zero_u32(unsigned *p)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
+    if (threadIdx.x < 2 && blockIdx.x == 0) p[threadIdx.x] = 0u;
 }
 
 __device__ __forceinline__ void batch_fill_pass(FusedArgs &a, const BatchInst &I, int p, int layer)
@@ -1927,11 +1928,13 @@ __device__ __forceinline__ DiagTab batch_layer_tab(const BatchInst &I, int layer
 }
 
 template <typename R>
-__device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh)
+__device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh, cx<R> *psi_lds = nullptr,
+                               cx<R> *lam_lds = nullptr)
 {
     constexpr int K = 12, LOGR = 4;
     const int t = threadIdx.x, nt = blockDim.x;
-    cx<R> *psi = (cx<R> *)I.psi, *lam = (cx<R> *)I.lam;
+    // psi_lds / lam_lds: the instance's vectors live in the block's LDS
+    cx<R> *psi = psi_lds ? psi_lds : (cx<R> *)I.psi, *lam = lam_lds ? lam_lds : (cx<R> *)I.lam;
     const u64 dim = 1ull << I.n;
     const int R_ = I.rot, np = I.np;
     FusedArgs a;
@@ -2037,6 +2040,27 @@ __global__ __launch_bounds__(256) void k_batch(const BatchInst *insts, const int
         __syncthreads();
         if (idx >= count) break;   // every block leaves once the queue is empty
         batch_instance<R>(insts[order[idx]], lds, sh);
+    }
+}
+
+// The same for instances small enough to keep psi and lam in the block's
+// LDS for the whole evaluation (kBatchLdsAmps amplitudes each, next to the
+// tile exchange buffer: 2 x 32 KB + 34 KB of the 160 KB in complex64).
+template <typename R>
+__global__ __launch_bounds__(256) void k_batch_lds(const BatchInst *insts, const int *order,
+                                                   int count, unsigned *counter)
+{
+    __shared__ cx<R> lds[Tile<12, 4>::LDS];
+    __shared__ cx<R> vpsi[kBatchLdsAmps], vlam[kBatchLdsAmps];
+    __shared__ double sh[8];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int idx = next;
+        __syncthreads();
+        if (idx >= count) break;   // every block leaves once the queue is empty
+        batch_instance<R>(insts[order[idx]], lds, sh, vpsi, vlam);
     }
 }
 
@@ -2490,18 +2514,27 @@ hipError_t batch_tables(int prec, const BatchInst *dev_insts, int count, hipStre
     return hipGetLastError();
 }
 
-hipError_t batch_run(int prec, const BatchInst *dev_insts, const int *order, int count,
-                     unsigned *counter, int grid, hipStream_t s)
+hipError_t batch_zero(unsigned *counter, hipStream_t s)
 {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counter);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || count <= 0) return e;
-    if (prec == GV_C64)
+    return hipGetLastError();
+}
+
+hipError_t batch_run(int prec, const BatchInst *dev_insts, const int *order, int count,
+                     unsigned *counter, int grid, bool lds_resident, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    if (lds_resident) {
+        if (prec != GV_C64) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_batch_lds<float>, dim3(grid), dim3(256), 0, s, dev_insts, order,
+                           count, counter);
+    } else if (prec == GV_C64) {
         hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(256), 0, s, dev_insts, order, count,
                            counter);
-    else
+    } else {
         hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(256), 0, s, dev_insts, order, count,
                            counter);
+    }
     return hipGetLastError();
 }
 

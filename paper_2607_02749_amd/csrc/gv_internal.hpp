@@ -428,8 +428,14 @@ struct BatchInst {
 // tables of every instance (one launch), then the queue counter reset and the
 // persistent kernel; grid = persistent blocks
 hipError_t batch_tables(int prec, const BatchInst *dev_insts, int count, hipStream_t s);
+// The batch's two queue counters (persistent kernel, LDS-resident kernel)
+// reset to zero, then one persistent kernel over order[0 .. count): the
+// LDS-resident one (complex64 instances of at most kBatchLdsAmps
+// amplitudes, their vectors in the block's LDS) or the plain one.
+constexpr int kBatchLdsAmps = 4096;
+hipError_t batch_zero(unsigned *counter, hipStream_t s);
 hipError_t batch_run(int prec, const BatchInst *dev_insts, const int *order, int count,
-                     unsigned *counter, int grid, hipStream_t s);
+                     unsigned *counter, int grid, bool lds_resident, hipStream_t s);
 // host helpers shared with gv_batch.cpp
 DiagTab make_diagtab(const gv_ansatz &an, const Chunks &ch, const void *tab, bool cz_layer);
 TabArgs make_tab_args(const gv_ansatz &an, const Chunks &ch, size_t stride);

@@ -53,7 +53,7 @@ class _Cluster(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("split_n", ctypes.c_int32)]
+                ("split_n", ctypes.c_int32), ("lds_n", ctypes.c_int32)]
 
 
 _lib = None
@@ -433,11 +433,12 @@ class Batch:
     packed buffer, instance i at offset sum_{j<i} P_j.  Rewriting the theta
     tensors in place and calling run() again evaluates the new angles.
     Instances with n >= split_n run as whole-GPU tile passes beside the
-    persistent kernel (None: the library default).  While the batch lives,
-    its PauliSums refuse to be prepared again."""
+    persistent kernel, those with n <= lds_n keep their vectors in LDS (-1:
+    never; None: the library defaults).  While the batch lives, its
+    PauliSums refuse to be prepared again."""
 
     def __init__(self, items, precision="c64", blocks_per_cu=None, order=None, graph=True,
-                 device="cuda", split_n=None):
+                 device="cuda", split_n=None, lds_n=None):
         dev = _device(device)
         self.device = dev
         self.precision = _PREC[precision]
@@ -456,9 +457,9 @@ class Batch:
         self._hams = [h for _, _, h, _ in self.items]
         self._h_buffers = [h._owner for h in self._hams]
         tu = None
-        if blocks_per_cu is not None or order is not None or split_n is not None:
+        if any(v is not None for v in (blocks_per_cu, order, split_n, lds_n)):
             tu = _Tuning(2 if blocks_per_cu is None else blocks_per_cu, 0 if order is None else order,
-                         0 if split_n is None else split_n)
+                         0 if split_n is None else split_n, 0 if lds_n is None else lds_n)
         self.tuning = tu
         wb = ctypes.c_size_t()
         _check(lib().gv_batch_query(count, arr, self.precision,

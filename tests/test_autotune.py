@@ -30,7 +30,7 @@ def test_cache_ignores_corrupt_file(tmp_path):
 
 
 def test_sweep_picks_fastest():
-    fake = {(1, 0, 17): 3.0, (1, 1, 17): 2.5, (2, 0, 31): 1.25, (2, 1, 15): 4.0}
-    r = autotune.sweep(sorted(fake), lambda b, o, sp: fake[(b, o, sp)])
-    assert (r["blocks_per_cu"], r["order"], r["split_n"], r["ms"]) == (2, 0, 31, 1.25)
+    fake = {(1, 0, 17, 12): 3.0, (1, 1, 17, -1): 2.5, (2, 0, 31, 12): 1.25, (2, 1, 15, -1): 4.0}
+    r = autotune.sweep(sorted(fake), lambda b, o, sp, ld: fake[(b, o, sp, ld)])
+    assert (r["blocks_per_cu"], r["order"], r["split_n"], r["lds_n"], r["ms"]) == (2, 0, 31, 12, 1.25)
     assert len(r["timings"]) == 4

@@ -36,12 +36,13 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("precision", ["c64", "c128"])
-@pytest.mark.parametrize("split_n", [None, 13])
-def test_batch_matches_oracle(precision, split_n):
-    # split_n = 13: every instance with n >= 13 runs as whole-GPU tile passes
+@pytest.mark.parametrize("split_n,lds_n", [(None, None), (13, None), (None, -1)])
+def test_batch_matches_oracle(precision, split_n, lds_n):
+    # split_n = 13: every instance with n >= 13 runs as whole-GPU tile passes;
+    # lds_n = None keeps the n = 12 instances' vectors in LDS (complex64), -1 not
     insts = synth.workload_batch(count=10, seed=3, n_lo=12, n_hi=15)
     items = make_items(insts)
-    b = gv.Batch(items, precision, graph=False, split_n=split_n)
+    b = gv.Batch(items, precision, graph=False, split_n=split_n, lds_n=lds_n)
     b.run()
     torch.cuda.synchronize()
     te, tg = TOL[precision]
@@ -99,18 +100,34 @@ def test_graph_replays_follow_new_angles(split_n):
         assert torch.equal(g_batch.grad_buf, eager.grad_buf)
 
 
+def test_lds_resident_instances_match_global_ones():
+    # the same arithmetic on vectors in LDS or in global memory: equal bits
+    insts = synth.workload_batch(count=24, seed=13, n_lo=12, n_hi=13)
+    assert sum(i.n == 12 for i in insts) >= 4
+    on = gv.Batch(make_items(insts), "c64", graph=True, lds_n=12)
+    off = gv.Batch(make_items(insts), "c64", graph=True, lds_n=-1)
+    for rep in range(2):
+        on.run()
+        off.run()
+        torch.cuda.synchronize()
+        assert torch.equal(on.energies, off.energies)
+        assert torch.equal(on.grad_buf, off.grad_buf)
+
+
 def test_autotuned_batch_matches_default(tmp_path):
     from paper_2607_02749_amd import autotune
     insts = synth.workload_batch(count=24, seed=11, n_lo=12, n_hi=16)
     items = make_items(insts)
     path = str(tmp_path / "tune.json")
-    r = autotune.tune_batch(items, "c64", blocks=(1, 2), orders=(0, 1), splits=(31,), reps=2,
-                            path=path)
-    assert not r["cached"] and len(r["timings"]) == 4
-    r2 = autotune.tune_batch(items, "c64", blocks=(1, 2), orders=(0, 1), splits=(31,), path=path)
-    assert r2["cached"] and (r2["blocks_per_cu"], r2["order"]) == (r["blocks_per_cu"], r["order"])
+    r = autotune.tune_batch(items, "c64", blocks=(1, 2), orders=(0, 1), splits=(31,),
+                            lds=(-1, 12), reps=2, path=path)
+    assert not r["cached"] and len(r["timings"]) == 8
+    r2 = autotune.tune_batch(items, "c64", blocks=(1, 2), orders=(0, 1), splits=(31,),
+                             lds=(-1, 12), path=path)
+    assert r2["cached"] and (r2["blocks_per_cu"], r2["order"], r2["lds_n"]) == \
+        (r["blocks_per_cu"], r["order"], r["lds_n"])
     tuned = gv.Batch(items, "c64", blocks_per_cu=r["blocks_per_cu"], order=r["order"],
-                     split_n=r["split_n"])
+                     split_n=r["split_n"], lds_n=r["lds_n"])
     ref = gv.Batch(make_items(insts), "c64", split_n=31)
     tuned.run()
     ref.run()
