@@ -590,6 +590,16 @@ struct InvChain {
     }
 };
 
+// A tile's registers in the load assignment, plain loads (o: tile base |
+// thread offset)
+template <typename R, int LOGR, bool CONTIG>
+__device__ __forceinline__ void prefetch_tile(cx<R> (&v)[1 << LOGR], const cx<R> *src, u64 o,
+                                              const RegMap<LOGR, CONTIG> &m)
+{
+#pragma unroll
+    for (int r = 0; r < (1 << LOGR); ++r) v[r] = ld_amp(src + o + m.off(r));
+}
+
 // Load a pass's tile in the load assignment.  In pass 0 the loaded values
 // may be multiplied by the layer diagonal (IN_LOAD_DIAG) or replaced by the
 // generated first-layer state (IN_GENERATE).
@@ -685,10 +695,22 @@ __device__ __forceinline__ void fwd_body(cx<R> *psi, const cx<R> *src, const Fus
     P0Diag<R, K, LOGR> pd;
     if (a.in_mode != IN_LOAD) pd.init(a.dt, t);
     const RyC<R, K, AM> rc(a, a.layer);
+    // plain loads: the next tile's loads go out before this tile's chain
+    // (the exchange barriers do not wait for them), one tile of registers
+    cx<R> nx[T::NR];
+    if constexpr (PL)
+        if (t0 < a.ntiles) prefetch_tile<R, LOGR, CONTIG>(nx, src, tile_base(t0, a) | toff_ld, mld);
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> v[T::NR];
-        load_tile<R, K, LOGR, CONTIG, PL>(v, src, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
+        if constexpr (PL) {
+#pragma unroll
+            for (int r = 0; r < T::NR; ++r) v[r] = nx[r];
+            if (tile + tstep < a.ntiles)
+                prefetch_tile<R, LOGR, CONTIG>(nx, src, tile_base(tile + tstep, a) | toff_ld, mld);
+        } else {
+            load_tile<R, K, LOGR, CONTIG, PL>(v, src, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
+        }
         fwd_assign<R, K, LOGR, 0, AM>(v, a, rc);
         if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1, AM>::run(v, lds, t, a, rc);
         cx<R> *pp = psi + fresh(base | toff_st);
@@ -1144,10 +1166,20 @@ __device__ __forceinline__ void fwd2_body(cx<R> *psi, const cx<R> *src, const Fu
     LDiag<R, K, LOGR> dg;
     const RyC<R, K, AM> rc(a, a.layer);
     const RyC<R, K, AM> rc2(a, a.layer2);
+    cx<R> nx[T::NR];   // the next tile, loaded ahead (plain loads)
+    if constexpr (PL)
+        if (t0 < a.ntiles) prefetch_tile<R, LOGR, CONTIG>(nx, src, tile_base(t0, a) | toff_ld, mld);
     for (u64 tile = t0; tile < a.ntiles; tile += tstep) {
         const u64 base = tile_base(tile, a);
         cx<R> v[T::NR];
-        load_tile<R, K, LOGR, CONTIG, PL>(v, src, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
+        if constexpr (PL) {
+#pragma unroll
+            for (int r = 0; r < T::NR; ++r) v[r] = nx[r];
+            if (tile + tstep < a.ntiles)
+                prefetch_tile<R, LOGR, CONTIG>(nx, src, tile_base(tile + tstep, a) | toff_ld, mld);
+        } else {
+            load_tile<R, K, LOGR, CONTIG, PL>(v, src, base, toff_ld, mld, a.in_mode, pd, a.dt, t);
+        }
         fwd_assign<R, K, LOGR, 0, AM>(v, a, rc);
         if constexpr (T::NA > 1) FwdChain<R, K, LOGR, 1, AM>::run(v, lds, t, a, rc);
         dg.tile(a.ld, tile, base | toff_st, t);
