@@ -1960,8 +1960,10 @@ __device__ __forceinline__ DiagTab batch_layer_tab(const BatchInst &I, int layer
 }
 
 template <typename R>
-__device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh, cx<R> *psi_lds = nullptr,
-                               cx<R> *lam_lds = nullptr)
+// fa / oa: the pass arguments in LDS (written by thread 0 before each body;
+// as a local array they would live in per-lane scratch memory)
+__device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh, FusedArgs &a,
+                               OffArgs &oa, cx<R> *psi_lds = nullptr, cx<R> *lam_lds = nullptr)
 {
     constexpr int K = 12, LOGR = 4;
     const int t = threadIdx.x, nt = blockDim.x;
@@ -1969,7 +1971,6 @@ __device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh, cx<R>
     cx<R> *psi = psi_lds ? psi_lds : (cx<R> *)I.psi, *lam = lam_lds ? lam_lds : (cx<R> *)I.lam;
     const u64 dim = 1ull << I.n;
     const int R_ = I.rot, np = I.np;
-    FusedArgs a;
     // forward: R_0|0..0> (generated inside layer 1's first pass), then the layers
     if (R_ == 1) {
         for (u64 i = t; i < dim; i += nt) psi[i] = diag_entry<R>(i, I.g0);
@@ -1977,11 +1978,14 @@ __device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh, cx<R>
     }
     for (int l = 1; l < R_; ++l) {
         for (int p = 0; p < np; ++p) {
-            batch_fill_pass(a, I, p, l);
-            if (p == 0) {
-                a.in_mode = l == 1 ? IN_GENERATE : IN_LOAD_DIAG;
-                a.dt = l == 1 ? I.gt : batch_layer_tab(I, l - 1);
+            if (t == 0) {
+                batch_fill_pass(a, I, p, l);
+                if (p == 0) {
+                    a.in_mode = l == 1 ? IN_GENERATE : IN_LOAD_DIAG;
+                    a.dt = l == 1 ? I.gt : batch_layer_tab(I, l - 1);
+                }
             }
+            __syncthreads();
             fwd_body<R, K, LOGR, true>(psi, psi, a, 0, 1, lds);
             __syncthreads();
         }
@@ -2016,20 +2020,22 @@ __device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh, cx<R>
         __syncthreads();
     }
     for (int k = 0; k < I.noff; ++k) {
-        OffArgs o;
-        const BatchOffPass &op = I.offp[k];
-        o.n = I.n;
-        for (int j = 0; j < kMaxTileBits; ++j) o.pos[j] = op.tile.pos[j];
-        o.nruns = op.tile.nruns;
-        for (int q = 0; q <= kMaxTileBits; ++q) o.run[q] = op.tile.run[q];
-        o.ntiles = I.ntiles;
-        o.cls = I.cls;
-        o.c0 = op.c0;
-        o.c1 = op.c1;
-        o.terms = I.terms;
-        o.epart = I.energy;
-        o.estride = 1;
-        off_body<R, K, LOGR>(psi, eonly ? nullptr : lam, o, 0, 1, 0, lds, sh);
+        if (t == 0) {
+            const BatchOffPass &op = I.offp[k];
+            oa.n = I.n;
+            for (int j = 0; j < kMaxTileBits; ++j) oa.pos[j] = op.tile.pos[j];
+            oa.nruns = op.tile.nruns;
+            for (int q = 0; q <= kMaxTileBits; ++q) oa.run[q] = op.tile.run[q];
+            oa.ntiles = I.ntiles;
+            oa.cls = I.cls;
+            oa.c0 = op.c0;
+            oa.c1 = op.c1;
+            oa.terms = I.terms;
+            oa.epart = I.energy;
+            oa.estride = 1;
+        }
+        __syncthreads();
+        off_body<R, K, LOGR>(psi, eonly ? nullptr : lam, oa, 0, 1, 0, lds, sh);
         __syncthreads();
     }
     if (eonly) {
@@ -2041,16 +2047,19 @@ __device__ void batch_instance(const BatchInst &I, cx<R> *lds, double *sh, cx<R>
     for (int l = R_ - 1; l >= 0; --l) {
         for (int p = 0; p < np; ++p) {
             const bool last = p == np - 1;
-            batch_fill_pass(a, I, p, l);
-            if (p == 0) {
-                a.phi_gen = l == 0;
-                if (a.phi_gen) a.gt = I.g0;
-                a.diag_phi = post && l > 0;
-                a.diag_lam = post;
-                if (a.diag_phi || a.diag_lam) a.dt = batch_layer_tab(I, l);
+            if (t == 0) {
+                batch_fill_pass(a, I, p, l);
+                if (p == 0) {
+                    a.phi_gen = l == 0;
+                    if (a.phi_gen) a.gt = I.g0;
+                    a.diag_phi = post && l > 0;
+                    a.diag_lam = post;
+                    if (a.diag_phi || a.diag_lam) a.dt = batch_layer_tab(I, l);
+                }
+                a.store_phi = !last || l - 1 >= 1;
+                a.store_lam = !(l == 0 && last);
             }
-            a.store_phi = !last || l - 1 >= 1;
-            a.store_lam = !(l == 0 && last);
+            __syncthreads();
             bwd_body<R, K, LOGR, true, false>(psi, psi, lam, a, 0, 1, 0, lds, sh);
             __syncthreads();
         }
@@ -2064,6 +2073,8 @@ __global__ __launch_bounds__(256) void k_batch(const BatchInst *insts, const int
 {
     __shared__ cx<R> lds[Tile<12, 4>::LDS];
     __shared__ double sh[8];
+    __shared__ FusedArgs fa;
+    __shared__ OffArgs oa;
     __shared__ int next;
     for (;;) {
         if (threadIdx.x == 0) next = (int)atomicAdd(counter, 1u);
@@ -2071,7 +2082,7 @@ __global__ __launch_bounds__(256) void k_batch(const BatchInst *insts, const int
         const int idx = next;
         __syncthreads();
         if (idx >= count) break;   // every block leaves once the queue is empty
-        batch_instance<R>(insts[order[idx]], lds, sh);
+        batch_instance<R>(insts[order[idx]], lds, sh, fa, oa);
     }
 }
 
@@ -2085,6 +2096,8 @@ __global__ __launch_bounds__(256) void k_batch_lds(const BatchInst *insts, const
     __shared__ cx<R> lds[Tile<12, 4>::LDS];
     __shared__ cx<R> vpsi[kBatchLdsAmps], vlam[kBatchLdsAmps];
     __shared__ double sh[8];
+    __shared__ FusedArgs fa;
+    __shared__ OffArgs oa;
     __shared__ int next;
     for (;;) {
         if (threadIdx.x == 0) next = (int)atomicAdd(counter, 1u);
@@ -2092,7 +2105,7 @@ __global__ __launch_bounds__(256) void k_batch_lds(const BatchInst *insts, const
         const int idx = next;
         __syncthreads();
         if (idx >= count) break;   // every block leaves once the queue is empty
-        batch_instance<R>(insts[order[idx]], lds, sh, vpsi, vlam);
+        batch_instance<R>(insts[order[idx]], lds, sh, fa, oa, vpsi, vlam);
     }
 }
 
