@@ -115,6 +115,13 @@ const char *gv_version(void);
 /* Thread-local text of the last non-OK status ("" if none). */
 const char *gv_last_error(void);
 
+/* Test hook for the error paths: after `after` more successful HIP status
+ * checks (process-wide), the next one reports GV_EHIP ("injected HIP
+ * error") as if the runtime had failed, then the hook turns itself off;
+ * after < 0 turns it off.  The work already enqueued runs normally; the
+ * failing call returns at that point like on a real HIP error. */
+gv_status gv_debug_inject_hip_error(int64_t after);
+
 /* Number of ansatz parameters, 2 n (layers + final_rotation), or -1 if the
  * ansatz is invalid. */
 int64_t gv_num_params(const gv_ansatz *ansatz);

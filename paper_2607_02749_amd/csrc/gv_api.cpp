@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <new>
 #include <string>
@@ -30,9 +31,17 @@ gv_status set_error(gv_status s, const char *fmt, ...)
     return s;
 }
 
+// Error-path test hook: when >= 0, the number of HIP status checks that
+// still pass before one reports an injected failure (then it turns off).
+static std::atomic<int64_t> g_inject_after{-1};
+
 gv_status check_hip(hipError_t e, const char *what)
 {
-    if (e == hipSuccess) return GV_OK;
+    if (e == hipSuccess) {
+        if (g_inject_after.load(std::memory_order_relaxed) < 0) return GV_OK;
+        if (g_inject_after.fetch_sub(1) != 0) return GV_OK;
+        return set_error(GV_EHIP, "%s: injected HIP error (test hook)", what);
+    }
     return set_error(GV_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
@@ -596,6 +605,12 @@ extern "C" {
 const char *gv_version(void) { return "gv 0.1 (gfx950)"; }
 
 const char *gv_last_error(void) { return g_last_error.c_str(); }
+
+gv_status gv_debug_inject_hip_error(int64_t after)
+{
+    g_inject_after.store(after < 0 ? -1 : after);
+    return GV_OK;
+}
 
 int64_t gv_num_params(const gv_ansatz *a)
 {

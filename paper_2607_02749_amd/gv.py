@@ -71,6 +71,7 @@ def lib():
     AP = ctypes.POINTER(_Ansatz)
     L.gv_version.restype = ctypes.c_char_p
     L.gv_last_error.restype = ctypes.c_char_p
+    L.gv_debug_inject_hip_error.argtypes = [i64]
     L.gv_num_params.argtypes = [AP]
     L.gv_num_params.restype = i64
     L.gv_query_sizes.argtypes = [AP, i32, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(sz),
@@ -124,6 +125,12 @@ def lib():
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
+
+
+def inject_hip_error(after: int) -> None:
+    """Error-path test hook: the (after+1)-th HIP status check from now
+    reports an injected failure (after < 0: off)."""
+    _check(lib().gv_debug_inject_hip_error(int(after)), "gv_debug_inject_hip_error")
 
 
 def _check(status: int, what: str):
