@@ -1436,6 +1436,62 @@ __device__ __forceinline__ void off_groups(R (&X)[NR], ScalarTerm *q, int k0, in
     }
 }
 
+// One class on a thread's 16 registers: partner reads from the LDS tile (pb:
+// the partner thread's register 0; XH: the flip also touches register
+// bits, xh), the real and imaginary sums, their products into acc.
+template <typename R, int NR, int STRIDE, bool XH>
+__device__ __forceinline__ void off_class(cx<R> (&acc)[NR], const cx<R> *pb, uint32_t xh,
+                                          uint32_t xu, int t0, int ti, int t1, ScalarTerm *q,
+                                          u64 base, uint32_t tid)
+{
+    typedef R r2 __attribute__((ext_vector_type(2)));
+    cx<R> pv[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const r2 v = *(const r2 *)(pb + (XH ? (int)((uint32_t)r ^ xh) : r) * STRIDE);
+        pv[r] = cx<R>{v.x, v.y};
+    }
+    R A[NR];
+    if (ti > t0) {
+        if (xu & kOffReFlat) {
+            const R w = off_sum<R>(q, t0, ti, base, tid);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                acc[r].re += w * pv[r].re;
+                acc[r].im += w * pv[r].im;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) A[r] = R(0);
+            off_groups<R, NR>(A, q, t0, ti, base, tid);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                acc[r].re += A[r] * pv[r].re;
+                acc[r].im += A[r] * pv[r].im;
+            }
+        }
+    }
+    if (t1 > ti) {
+        if (xu & kOffImFlat) {
+            const R w = off_sum<R>(q, ti, t1, base, tid);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                acc[r].re -= w * pv[r].im;
+                acc[r].im += w * pv[r].re;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) A[r] = R(0);
+            off_groups<R, NR>(A, q, ti, t1, base, tid);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                acc[r].re -= A[r] * pv[r].im;
+                acc[r].im += A[r] * pv[r].re;
+            }
+        }
+    }
+}
+
 // One cover pass: the psi tile sits in LDS, so for every class (flip mask x
 // inside the tile) each amplitude reads its partner psi_{i^x} there and adds
 // F(i^x) psi_{i^x} to lam_i, where F(i^x) = sum_k c_k i^{ph_k}
@@ -1475,58 +1531,15 @@ __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const Off
         __syncthreads();
         for (int c = a.c0; c < a.c1; ++c) {
             const uint32_t xu = cls[c].xu;
-            const int c_t0 = cls[c].t0, c_ti = cls[c].ti, c_t1 = cls[c].t1;
-            // partners: thread t ^ xl, register r ^ xh
+            // partners: thread t ^ xl, register r ^ xh (immediate offsets when xh = 0)
             const uint32_t xl = xu & TMASK, xh = (xu & 0xffffu) >> LD;
-            const int tp = t ^ (int)xl;
-            const int pbase = T::pad(tp);
-            cx<R> pv[T::NR];
-            if (xh == 0) {
-#pragma unroll
-                for (int r = 0; r < T::NR; ++r) pv[r] = lds[pbase + r * STRIDE];
-            } else {
-#pragma unroll
-                for (int r = 0; r < T::NR; ++r) pv[r] = lds[pbase + (r ^ (int)xh) * STRIDE];
-            }
-            R A[T::NR];
-            if (c_ti > c_t0) {
-                if (xu & kOffReFlat) {
-                    const R w = off_sum<R>(q, c_t0, c_ti, base, (uint32_t)t);
-#pragma unroll
-                    for (int r = 0; r < T::NR; ++r) {
-                        acc[r].re += w * pv[r].re;
-                        acc[r].im += w * pv[r].im;
-                    }
-                } else {
-#pragma unroll
-                    for (int r = 0; r < T::NR; ++r) A[r] = R(0);
-                    off_groups<R, T::NR>(A, q, c_t0, c_ti, base, (uint32_t)t);
-#pragma unroll
-                    for (int r = 0; r < T::NR; ++r) {
-                        acc[r].re += A[r] * pv[r].re;
-                        acc[r].im += A[r] * pv[r].im;
-                    }
-                }
-            }
-            if (c_t1 > c_ti) {
-                if (xu & kOffImFlat) {
-                    const R w = off_sum<R>(q, c_ti, c_t1, base, (uint32_t)t);
-#pragma unroll
-                    for (int r = 0; r < T::NR; ++r) {
-                        acc[r].re -= w * pv[r].im;
-                        acc[r].im += w * pv[r].re;
-                    }
-                } else {
-#pragma unroll
-                    for (int r = 0; r < T::NR; ++r) A[r] = R(0);
-                    off_groups<R, T::NR>(A, q, c_ti, c_t1, base, (uint32_t)t);
-#pragma unroll
-                    for (int r = 0; r < T::NR; ++r) {
-                        acc[r].re -= A[r] * pv[r].im;
-                        acc[r].im += A[r] * pv[r].re;
-                    }
-                }
-            }
+            const cx<R> *pb = lds + T::pad(t ^ (int)xl);
+            if (xh == 0)
+                off_class<R, T::NR, STRIDE, false>(acc, pb, 0, xu, cls[c].t0, cls[c].ti, cls[c].t1,
+                                                   q, base, (uint32_t)t);
+            else
+                off_class<R, T::NR, STRIDE, true>(acc, pb, xh, xu, cls[c].t0, cls[c].ti, cls[c].t1,
+                                                  q, base, (uint32_t)t);
         }
         cx<R> *lt = lam ? lam + fresh(bt) : nullptr;
 #pragma unroll
