@@ -672,7 +672,7 @@ enum PassKind {
 template <typename R>
 constexpr int pass_waves(int kind, int ms)
 {
-    return (sizeof(R) == 4 && ms == MS_LATER && kind == PK_BWD2_PASS) ? 3 : 1;
+    return (sizeof(R) == 4 && ms != MS_ANY && kind == PK_BWD2_PASS) ? 3 : 1;
 }
 template <typename R, int K, int MS, bool RT = false>
 constexpr uint32_t pass_mask()
