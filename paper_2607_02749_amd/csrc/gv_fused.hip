@@ -661,9 +661,10 @@ enum { MS_ANY = 0, MS_FULL = 1, MS_LATER = 2 };
 
 // The pass kernels, and the waves per SIMD each variant is compiled for
 // (its register budget: 4 waves = 128 VGPRs, 3 = 168, 2 = 256).  1 leaves
-// the compiler's own choice; a higher target is set where the variant sits
-// just above a step and the few registers over it spill at no measurable
-// cost (outside the tile loop).
+// the compiler's own choice.  The complex64 two-layer reverse passes are held
+// to 3 waves: their bodies want ~175-220 registers, and the third wave hides
+// more of the exchanges' barrier waits than the ~30 registers spilled (a few
+// scratch accesses per tile) cost.
 enum PassKind {
     PK_FWD_PASS, PK_FWD_LOAD_PASS, PK_FWD2_PASS, PK_FWD2_LOAD_PASS, PK_TURN_PASS,
     PK_TURN_LOAD_PASS, PK_BWD_PASS, PK_BWD_LD_PASS, PK_BWD_GF_PASS, PK_BWD_GF_LD_PASS,
@@ -672,7 +673,8 @@ enum PassKind {
 template <typename R>
 constexpr int pass_waves(int kind, int ms)
 {
-    return (sizeof(R) == 4 && ms != MS_ANY && kind == PK_BWD2_PASS) ? 3 : 1;
+    const bool bwd2 = kind == PK_BWD2_PASS || kind == PK_BWD2_PHI_PASS;
+    return (sizeof(R) == 4 && ms != MS_ANY && bwd2) ? 3 : 1;
 }
 template <typename R, int K, int MS, bool RT = false>
 constexpr uint32_t pass_mask()
