@@ -291,15 +291,20 @@ __device__ __forceinline__ cx<R> cmul_conj(cx<R> a, cx<R> d)  // a * conj(d)
     return o;
 }
 
-// RY on the pair (x, y): (c x - s y, s x + c y)
+// The rotation by phi on the pair (x, y), (c x - s y, s x + c y), as three
+// shears: x -= t y, y += s x, x -= t y with t = tan(phi / 2), s = sin phi
+// (1 - s t = cos phi and t (1 + cos phi) = sin phi).  Three multiply-adds
+// per component pair instead of four; the angle's table keeps |phi| <=
+// pi / 2, so |t| <= 1.  The inverse is (-t, -s).
 template <typename R>
-__device__ __forceinline__ void rot_pair(cx<R> &x, cx<R> &y, R c, R sn)
+__device__ __forceinline__ void rot_pair(cx<R> &x, cx<R> &y, R t, R sn)
 {
-    const cx<R> a = x, b = y;
-    x.re = c * a.re - sn * b.re;
-    x.im = c * a.im - sn * b.im;
-    y.re = sn * a.re + c * b.re;
-    y.im = sn * a.im + c * b.im;
+    x.re -= t * y.re;
+    x.im -= t * y.im;
+    y.re += sn * x.re;
+    y.im += sn * x.im;
+    x.re -= t * y.re;
+    x.im -= t * y.im;
 }
 
 // Whether tile bit j holds an active gate: from the compile-time mask AM
@@ -315,23 +320,23 @@ __device__ __forceinline__ bool on(const FusedArgs &a, int j)
     else return (a.active >> j) & 1;
 }
 
-// (cos, sin) of the half angles of one rotation layer's RY gates on the K
-// tile qubits, read once per block: inside the tile loop each gate would
+// Shear coefficients (t, s) of one rotation layer's RY gates on the K tile
+// qubits, read once per block: inside the tile loop each gate would
 // otherwise wait for its own load.  Only the pass's active qubits are read
-// (the gates the assignments apply); the others hold the identity.
+// (the gates the assignments apply); the others hold the identity (0, 0).
 template <typename R, int K, uint32_t AM = 0>
 struct RyC {
-    R c[K], s[K];
+    R t[K], s[K];
     __device__ __forceinline__ RyC(const FusedArgs &a, int layer)
     {
         const cx<R> *ry = (const cx<R> *)a.ry + (int64_t)layer * a.nparam_layer;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            c[j] = R(1);
+            t[j] = R(0);
             s[j] = R(0);
             if (on<AM>(a, j)) {
                 const cx<R> e = ry[a.pos[j]];
-                c[j] = e.re;
+                t[j] = e.re;
                 s[j] = e.im;
             }
         }
@@ -350,10 +355,10 @@ __device__ __forceinline__ void fwd_assign(cx<R> (&v)[1 << LOGR], const FusedArg
     for (int k = 0; k < LOGR; ++k) {
         const int j = LO + k;
         if (!((NEW >> j) & 1) || !on<AM>(a, j)) continue;
-        const R c = rc.c[j], sn = rc.s[j];
+        const R tn = rc.t[j], sn = rc.s[j];
 #pragma unroll
         for (int r = 0; r < T::NR; ++r)
-            if (!(r & (1 << k))) rot_pair(v[r], v[r | (1 << k)], c, sn);
+            if (!(r & (1 << k))) rot_pair(v[r], v[r | (1 << k)], tn, sn);
     }
 }
 
@@ -372,15 +377,15 @@ __device__ __forceinline__ void bwd_assign(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 <
     for (int k = 0; k < LOGR; ++k) {
         const int j = LO + k;
         if (!((NEW >> j) & 1) || !on<AM>(a, j)) continue;
-        const R c = rc.c[j], sn = -rc.s[j];
+        const R tn = -rc.t[j], sn = -rc.s[j];
         R g = 0;
 #pragma unroll
         for (int r = 0; r < T::NR; ++r) {
             if (r & (1 << k)) continue;
             const int r1 = r | (1 << k);
             g += (l[r1].re * f[r].re + l[r1].im * f[r].im) - (l[r].re * f[r1].re + l[r].im * f[r1].im);
-            rot_pair(f[r], f[r1], c, sn);
-            rot_pair(l[r], l[r1], c, sn);
+            rot_pair(f[r], f[r1], tn, sn);
+            rot_pair(l[r], l[r1], tn, sn);
         }
         accY[j] += (double)g;
     }
@@ -422,10 +427,10 @@ __device__ __forceinline__ void inv_assign(cx<R> (&v)[1 << LOGR], const FusedArg
     for (int k = 0; k < LOGR; ++k) {
         const int j = LO + k;
         if (!((NEW >> j) & 1) || !on<AM>(a, j)) continue;
-        const R c = rc.c[j], sn = -rc.s[j];
+        const R tn = -rc.t[j], sn = -rc.s[j];
 #pragma unroll
         for (int r = 0; r < T::NR; ++r)
-            if (!(r & (1 << k))) rot_pair(v[r], v[r | (1 << k)], c, sn);
+            if (!(r & (1 << k))) rot_pair(v[r], v[r | (1 << k)], tn, sn);
     }
 }
 
@@ -1576,15 +1581,42 @@ __global__ __launch_bounds__(1 << (K - LOGR)) void k_offdiag_pass(const void *ps
 }
 
 // ------------------------------------------------------------ table kernels
-// ry[p] = (cos(theta_p / 2), sin(theta_p / 2)), computed in FP64 and
-// rounded once to the amplitude precision (so the passes read them as
-// scalar operands)
+// RY(theta) rotates each pair by phi = theta / 2.  Where cos phi < 0 the
+// passes rotate by phi - pi instead, the same gate times -1, so that the
+// shear coefficients stay bounded: ry[p] = (tan(phi' / 2), sin phi') of that
+// angle, computed in FP64 (tan(phi' / 2) = sin phi' / (1 + cos phi'), no
+// cancellation for cos phi' >= 0) and rounded once to the amplitude
+// precision (so the passes read them as scalar operands).
+__device__ __forceinline__ bool ry_flipped(double theta, double &sn, double &cs)
+{
+    sincos(0.5 * theta, &sn, &cs);
+    if (cs >= 0.0) return false;
+    sn = -sn;
+    cs = -cs;
+    return true;
+}
 template <typename R>
 __device__ __forceinline__ void ry_entry(double theta, cx<R> *e)
 {
     double sn, cs;
-    sincos(0.5 * theta, &sn, &cs);
-    *e = cx<R>{(R)cs, (R)sn};
+    ry_flipped(theta, sn, cs);
+    *e = cx<R>{(R)(sn / (1.0 + cs)), (R)sn};
+}
+// The -1 of every RY gate the passes rotate by phi - pi (those of rotation
+// layers 1 .. rot-1; the first layer is generated from its tables, never
+// rotated): their product S goes into the first chunk of the first layer's
+// tables, so the generated state is S R_0|0..0>, every later state carries
+// the product of the flips still to come (the state after the last layer is
+// exact), and in the reverse sweep phi and lam carry the same sign.
+__device__ __forceinline__ double ry_flip_sign(const double *theta, int n, int rot)
+{
+    int par = 0;
+    for (int l = 1; l < rot; ++l)
+        for (int q = 0; q < n; ++q) {
+            double sn, cs;
+            par ^= (int)ry_flipped(theta[(int64_t)l * 2 * n + q], sn, cs);
+        }
+    return par ? -1.0 : 1.0;
 }
 
 template <typename R>
@@ -1651,7 +1683,8 @@ __global__ void k_diag_tables(const double *theta, TabArgs ta, char *dtab)
 
 // first-layer tables: g0 = prod_{q in chunk} (bit ? sin : cos)(theta_q / 2)
 // (the product state R_0|0...0>), g = g0 times the chunk's diagonal phase of
-// layer 0 (the state D_0 R_0|0...0>)
+// layer 0 (the state D_0 R_0|0...0>); the first chunk also carries the sign
+// S of the flipped RY gates
 template <typename R>
 __global__ void k_init_tables(const double *theta, TabArgs ta, cx<R> *gtab, cx<R> *g0tab)
 {
@@ -1662,7 +1695,7 @@ __global__ void k_init_tables(const double *theta, TabArgs ta, cx<R> *gtab, cx<R
         double ang;
         int par;
         chunk_phase(theta, ta, 0, c, v, ang, par);
-        double mag = 1.0;
+        double mag = c == 0 ? ry_flip_sign(theta, ta.n, ta.rot_layers) : 1.0;
         for (int q = ta.b[c]; q < ta.b[c + 1]; ++q) {
             double s, co;
             sincos(0.5 * theta[q], &s, &co);
@@ -1923,7 +1956,7 @@ __global__ void k_batch_tables(const BatchInst *insts)
             out.im = (R)sn;
             ((cx<R> *)(I.dtab + (size_t)l * I.dtab_stride))[w] = out;
         } else {
-            double mag = 1.0;
+            double mag = c == 0 ? ry_flip_sign(I.theta, ta.n, ta.rot_layers) : 1.0;
             for (int q = ta.b[c]; q < ta.b[c + 1]; ++q) {
                 double s2, c2;
                 sincos(0.5 * I.theta[q], &s2, &c2);
