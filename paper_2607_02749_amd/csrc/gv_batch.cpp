@@ -437,7 +437,10 @@ gv_status gv_batch_run(gv_batch b)
     for (size_t i = 0; i < b->hgen.size(); ++i)
         if (b->hgen[i].first->prep_gen != b->hgen[i].second || !b->hgen[i].first->prepared)
             return set_error(GV_ESTATE, "instance %zu: its Hamiltonian was prepared again after "
-                                        "the batch was created", i);
+                                        "the batch was created (generation %llu, now %llu, "
+                                        "prepared %d)", i, (unsigned long long)b->hgen[i].second,
+                             (unsigned long long)b->hgen[i].first->prep_gen,
+                             (int)b->hgen[i].first->prepared);
     if (b->graph) return check_hip(hipGraphLaunch(b->exec, b->stream), "graph launch");
     return launch_all(b, b->stream);
 }
