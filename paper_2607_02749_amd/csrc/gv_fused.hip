@@ -1607,15 +1607,21 @@ __device__ __forceinline__ void ry_entry(double theta, cx<R> *e)
 // rotated): their product S goes into the first chunk of the first layer's
 // tables, so the generated state is S R_0|0..0>, every later state carries
 // the product of the flips still to come (the state after the last layer is
-// exact), and in the reverse sweep phi and lam carry the same sign.
+// exact), and in the reverse sweep phi and lam carry the same sign.  Called
+// by every thread of the block (each tests a share of the gates, the
+// parities meet in LDS); each gets S.
 __device__ __forceinline__ double ry_flip_sign(const double *theta, int n, int rot)
 {
-    int par = 0;
-    for (int l = 1; l < rot; ++l)
-        for (int q = 0; q < n; ++q) {
-            double sn, cs;
-            par ^= (int)ry_flipped(theta[(int64_t)l * 2 * n + q], sn, cs);
-        }
+    __shared__ int par;
+    if (threadIdx.x == 0) par = 0;
+    __syncthreads();
+    int p = 0;
+    for (int i = threadIdx.x; i < (rot - 1) * n; i += blockDim.x) {
+        double sn, cs;
+        p ^= (int)ry_flipped(theta[(int64_t)(1 + i / n) * 2 * n + i % n], sn, cs);
+    }
+    if (p) atomicXor(&par, 1);
+    __syncthreads();
     return par ? -1.0 : 1.0;
 }
 
@@ -1688,6 +1694,7 @@ __global__ void k_diag_tables(const double *theta, TabArgs ta, char *dtab)
 template <typename R>
 __global__ void k_init_tables(const double *theta, TabArgs ta, cx<R> *gtab, cx<R> *g0tab)
 {
+    const double S = ry_flip_sign(theta, ta.n, ta.rot_layers);
     const int per = ta.off[4];
     for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < per; w += gridDim.x * blockDim.x) {
         const int c = chunk_of(ta, w);
@@ -1695,7 +1702,7 @@ __global__ void k_init_tables(const double *theta, TabArgs ta, cx<R> *gtab, cx<R
         double ang;
         int par;
         chunk_phase(theta, ta, 0, c, v, ang, par);
-        double mag = c == 0 ? ry_flip_sign(theta, ta.n, ta.rot_layers) : 1.0;
+        double mag = c == 0 ? S : 1.0;
         for (int q = ta.b[c]; q < ta.b[c + 1]; ++q) {
             double s, co;
             sincos(0.5 * theta[q], &s, &co);
@@ -1925,6 +1932,7 @@ __global__ void k_batch_tables(const BatchInst *insts)
 {
     const BatchInst &I = insts[blockIdx.y];
     const TabArgs &ta = I.ta;
+    const double S = ry_flip_sign(I.theta, ta.n, ta.rot_layers);
     const int per = ta.off[4];
     const int64_t np = 2ll * I.n * I.rot;
     const int64_t nd = (int64_t)per * I.rot;
@@ -1956,7 +1964,7 @@ __global__ void k_batch_tables(const BatchInst *insts)
             out.im = (R)sn;
             ((cx<R> *)(I.dtab + (size_t)l * I.dtab_stride))[w] = out;
         } else {
-            double mag = c == 0 ? ry_flip_sign(I.theta, ta.n, ta.rot_layers) : 1.0;
+            double mag = c == 0 ? S : 1.0;
             for (int q = ta.b[c]; q < ta.b[c + 1]; ++q) {
                 double s2, c2;
                 sincos(0.5 * I.theta[q], &s2, &c2);
