@@ -64,7 +64,7 @@ struct FusedArgs {
     int nruns;               // tile id -> outside bits, as runs of contiguous bits:
     uint32_t run[kMaxTileBits + 1];  // source bit | width << 8 | destination bit << 16
     u64 ntiles;
-    const void *ry;          // [P] (cos, sin) of half angles, amplitude precision
+    const void *ry;          // [P] shear coefficients (tan(phi/2), sin phi) of the RY gates
     DiagTab dt;              // layer diagonal (or the first layer's generator in forward)
     DiagTab gt;              // reverse: generator of R_0|0...0>
     const double *hdiag;     // turnaround: diagonal of the Hamiltonian

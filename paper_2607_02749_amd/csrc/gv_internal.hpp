@@ -219,7 +219,7 @@ struct WorkLayout {
     size_t lam = 0;          // adjoint vector
     size_t ckpt = 0;         // stored states: L-2 boundaries (CHECKPOINT) or pass outputs (STORE)
     size_t scratch = 0;      // one vector (CNOT gather)
-    size_t ry_tab = 0;       // per parameter: (cos, sin) of the half angle, amplitude precision
+    size_t ry_tab = 0;       // per parameter: RY shear coefficients, amplitude precision
     size_t dtab = 0;         // per rotation layer: diagonal tables in pass 0's load layout
     size_t gtab = 0;         // first-layer tables D_0 R_0|0..0>
     size_t g0tab = 0;        // first-layer tables R_0|0..0>
@@ -318,7 +318,7 @@ hipError_t offdiag_pass(int prec, const void *psi, void *lam, int n, int K, cons
 
 // fused engine
 struct FusedTables {
-    const void *ry;      // [P]: (cos, sin) of half angles in the amplitude precision
+    const void *ry;      // [P]: RY shear coefficients in the amplitude precision
     void *dtab;          // per rotation layer diagonal tables (RZ phases, CZ signs)
     size_t dtab_stride;
     void *gtab;          // D_0 R_0|0...0> tables
@@ -416,7 +416,7 @@ struct BatchInst {
     const OffTerm *terms;
     const BatchOffPass *offp;
     void *psi, *lam;
-    void *ry;            // [P] (cos, sin) of half angles, amplitude precision
+    void *ry;            // [P] RY shear coefficients, amplitude precision
     char *dtab;
     size_t dtab_stride;
     void *gtab, *g0tab;
