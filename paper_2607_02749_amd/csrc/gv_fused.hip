@@ -1271,7 +1271,7 @@ __device__ __forceinline__ void block_sum2_all(double &x, double &y, double *sh)
 // thread and tile factors multiply in afterwards.  One read of lam replaces
 // the layer's reverse passes.
 template <typename R, int K, int LOGR>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_layer0_grad(const void *lam_, Layer0Args a)
+__global__ __launch_bounds__(1 << (K - LOGR), sizeof(R) == 4 ? 3 : 1) void k_layer0_grad(const void *lam_, Layer0Args a)
 {
     constexpr int NR = 1 << LOGR, LD = K - LOGR;
     __shared__ double sh[2 * ((1 << (K - LOGR)) / 64 + 1)];
