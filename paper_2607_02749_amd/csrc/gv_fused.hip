@@ -1571,7 +1571,9 @@ __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const Off
 }
 
 template <typename R, int K, int LOGR>
-__global__ __launch_bounds__(1 << (K - LOGR)) void k_offdiag_pass(const void *psi_, void *lam_,
+// complex64: held to 4 waves per SIMD (the LDS tile allows 4 blocks per CU);
+// the extra wave hides more of the per-term scalar loads than its spills cost
+__global__ __launch_bounds__(1 << (K - LOGR), sizeof(R) == 4 ? 4 : 1) void k_offdiag_pass(const void *psi_, void *lam_,
                                                                   OffArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
