@@ -1571,8 +1571,8 @@ __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const Off
 }
 
 template <typename R, int K, int LOGR>
-// complex64: held to 4 waves per SIMD (the LDS tile allows 4 blocks per CU);
-// the extra wave hides more of the per-term scalar loads than its spills cost
+// complex64: held to 4 waves per SIMD (128 VGPRs; the LDS tile allows 4
+// blocks per CU): the fourth wave hides more of the per-term scalar loads
 __global__ __launch_bounds__(1 << (K - LOGR), sizeof(R) == 4 ? 4 : 1) void k_offdiag_pass(const void *psi_, void *lam_,
                                                                   OffArgs a)
 {
