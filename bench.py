@@ -45,7 +45,7 @@ KERNELS = {
     "backward_pass": "k_bwd_pass<float,12,4>", "backward_ld": "k_bwd_ld_pass<float,12,4>",
     "backward_gf": "k_bwd_gf_pass<float,12,4>", "backward_gf_ld": "k_bwd_gf_ld_pass<float,12,4>",
     "turnaround": "k_turn_load_pass<float,12,4>", "first_layer": "k_layer0_grad<float,12,4>",
-    "energy": "k_energy_diag<float>", "offdiag": "k_offdiag_pass<float,12,4>",
+    "energy": "k_energy_diag<float>", "offdiag": "k_offdiag_pass<float,12,4,W>",
     "backward2": "k_bwd2_pass<float,12,4>",
 }
 

@@ -1570,11 +1570,13 @@ __device__ __forceinline__ void off_body(const cx<R> *psi, cx<R> *lam, const Off
     __syncthreads();
 }
 
-template <typename R, int K, int LOGR>
-// complex64: held to 4 waves per SIMD (128 VGPRs; the LDS tile allows 4
-// blocks per CU): the fourth wave hides more of the per-term scalar loads
-__global__ __launch_bounds__(1 << (K - LOGR), sizeof(R) == 4 ? 4 : 1) void k_offdiag_pass(const void *psi_, void *lam_,
-                                                                  OffArgs a)
+// W: waves per SIMD the kernel is compiled for (1: the compiler's choice).
+// Large complex64 states run the W = 4 variant (128 VGPRs; the LDS tile
+// allows 4 blocks per CU): the fourth wave hides more of the per-term scalar
+// loads; small grids, where no CU gets a fourth block, keep the other.
+template <typename R, int K, int LOGR, int W = 1>
+__global__ __launch_bounds__(1 << (K - LOGR), W) void k_offdiag_pass(const void *psi_, void *lam_,
+                                                                     OffArgs a)
 {
     __shared__ cx<R> lds[Tile<K, LOGR>::LDS];
     __shared__ double sh[(1 << (K - LOGR)) / 64 + 1];
@@ -2584,10 +2586,13 @@ hipError_t offdiag_pass(int prec, const void *psi, void *lam, int n, int K, cons
     if (grid > estride) return hipErrorInvalidValue;
     switch (K) {
     case 12:
-        if (prec == GV_C64)
+        if (prec == GV_C64 && a.ntiles >= (1ull << 16)) {
+            hipLaunchKernelGGL((k_offdiag_pass<float, 12, 4, 4>), dim3(grid), dim3(256), 0, s, psi, lam, a);
+        } else if (prec == GV_C64) {
             hipLaunchKernelGGL((k_offdiag_pass<float, 12, 4>), dim3(grid), dim3(256), 0, s, psi, lam, a);
-        else
+        } else {
             hipLaunchKernelGGL((k_offdiag_pass<double, 12, 4>), dim3(grid), dim3(256), 0, s, psi, lam, a);
+        }
         break;
     case 10:
         if (prec == GV_C64)
